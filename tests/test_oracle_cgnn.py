@@ -1,0 +1,201 @@
+"""Pins of the oracle's CGNN: direct-sum convolution, equivariances, LN, MP, FD gradients (no GPU)."""
+import numpy as np
+import pytest
+from scipy.signal import correlate2d
+
+from oracle import cgnn, nr, receiver, slot_sim
+
+
+def _direct_conv(x, w, b):
+    """Pure-Python loops: out[s,t,o] = b[o] + sum_{i,j,c} w[i,j,c,o] x[s+i-1,t+j-1,c] (zero outside)."""
+    S, T, C = x.shape
+    O = w.shape[3]
+    out = np.zeros((S, T, O))
+    for s in range(S):
+        for t in range(T):
+            for o in range(O):
+                acc = b[o]
+                for i in range(3):
+                    for j in range(3):
+                        ss, tt = s + i - 1, t + j - 1
+                        if 0 <= ss < S and 0 <= tt < T:
+                            for c in range(C):
+                                acc += w[i, j, c, o] * x[ss, tt, c]
+                out[s, t, o] = acc
+    return out
+
+
+def test_conv_matches_direct_sum():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((5, 4, 3))
+    w = rng.standard_normal((3, 3, 3, 2))
+    b = rng.standard_normal(2)
+    assert np.allclose(cgnn.conv3x3(x, w, b), _direct_conv(x, w, b), atol=1e-12)
+
+
+def test_conv_matches_scipy_correlate():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((9, 14, 4))
+    w = rng.standard_normal((3, 3, 4, 3))
+    out = cgnn.conv3x3(x, w, np.zeros(3))
+    for o in range(3):
+        ref = sum(correlate2d(x[:, :, c], w[:, :, c, o], mode="same") for c in range(4))
+        assert np.allclose(out[:, :, o], ref, atol=1e-12)
+
+
+def test_conv_impulse_orientation():
+    # a one-hot input at (s0, t0) produces w[i, j] at output (s0 - i + 1, t0 - j + 1)
+    w = np.arange(9, dtype=float).reshape(3, 3, 1, 1)
+    x = np.zeros((5, 5, 1))
+    x[2, 2, 0] = 1
+    out = cgnn.conv3x3(x, w, np.zeros(1))[:, :, 0]
+    for i in range(3):
+        for j in range(3):
+            assert out[2 - i + 1, 2 - j + 1] == w[i, j, 0, 0]
+    # zero padding: an impulse in the corner only reaches the 2x2 neighbourhood
+    x = np.zeros((5, 5, 1))
+    x[0, 0, 0] = 1
+    out = cgnn.conv3x3(x, np.ones((3, 3, 1, 1)), np.zeros(1))[:, :, 0]
+    assert out.sum() == 4
+
+
+def test_layer_norm_cases():
+    g = np.array([2.0, 3.0, 4.0])
+    b = np.array([0.5, -1.0, 0.0])
+    y, _ = cgnn.layer_norm(np.full((2, 3), 7.0), g, b)
+    assert np.allclose(y, b)                                  # constant row -> beta
+    z = np.array([[1.0, 2.0, 6.0]])
+    y, _ = cgnn.layer_norm(z, np.ones(3), np.zeros(3))
+    assert np.isclose(y.mean(), 0) and np.isclose((y ** 2).mean(), 14 / 3 / (14 / 3 + 1e-5))
+
+
+def test_aggregate_others():
+    m = np.arange(12, dtype=float).reshape(1, 3, 4)
+    agg = cgnn.aggregate_others(m)
+    assert np.allclose(agg, m.sum(axis=1, keepdims=True) - m)
+    assert np.all(cgnn.aggregate_others(m[:, :1]) == 0)      # one UE: nothing received
+
+
+def test_positional_encoding():
+    pe = cgnn.positional_encoding(8, 4)
+    assert np.isclose(pe[0, :, 0, 0].mean(), 0) and np.isclose(pe[0, :, 0, 0].std(), 1)
+    assert pe[0, 2, 0, 0] == pe[0, 11, 0, 0] == pe[0, :, 0, 0].min()
+    assert pe[0, 0, 0, 1] == -1 and pe[1, 0, 0, 1] == 1          # CDM group 0 on even subcarriers
+    assert pe[0, 0, 2, 1] == 1 and pe[1, 0, 2, 1] == -1          # CDM group 1 on odd subcarriers
+
+
+def _random_net(cfg, seed=0):
+    rng = np.random.default_rng(seed)
+    W = {}
+    for name, shape in cgnn.layout(cfg):
+        if name.endswith(".g"):
+            W[name] = 1 + 0.1 * rng.standard_normal(shape)
+        elif len(shape) == 1:
+            W[name] = 0.1 * rng.standard_normal(shape)
+        else:
+            fan = np.prod(shape[:-1])
+            W[name] = rng.standard_normal(shape) * np.sqrt(2 / fan)
+    return W
+
+
+def _slot(n_prb=2, B=2, U=3, m=4, seed=0):
+    cfg = slot_sim.SimConfig(n_taps=3, tap_decay_ns=100, snr_db_lo=5, snr_db_hi=15)
+    desc = slot_sim.SlotDesc(n_prb, B, U, [m] * U)
+    r = slot_sim.simulate_slot(seed, 0, 0, cfg, desc, m)
+    return desc, r, receiver.ls_estimate(r["y"], desc)
+
+
+def test_layout_counts():
+    cfg = cgnn.NetConfig(8, 128, 6, 2, 4)
+    names = [n for n, _ in cgnn.layout(cfg)]
+    assert names[0] == "conv_in.w" and names[-1] == "readout.b2"
+    assert cfg.mp_blocks() == [0, 3]
+    assert cgnn.NetConfig(16, 128, 8, 3, 6).mp_blocks() == [0, 2, 5]
+    assert dict(cgnn.layout(cfg))["blk0.conv_a.w"] == (3, 3, 258, 128)
+    assert dict(cgnn.layout(cfg))["blk1.conv_a.w"] == (3, 3, 128, 128)
+
+
+def test_ue_permutation_equivariance():
+    cfg = cgnn.NetConfig(2, 8, 2, 1, 4)
+    W = _random_net(cfg)
+    desc, r, h = _slot()
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    perm = [2, 0, 1]
+    l1 = cgnn.forward_x(W, cfg, X, [4] * 3)
+    l2 = cgnn.forward_x(W, cfg, X[:, :, perm], [4] * 3)
+    assert np.allclose(l1[perm], l2, atol=1e-10)
+
+
+def test_subcarrier_shift_equivariance_interior():
+    cfg = cgnn.NetConfig(2, 8, 2, 1, 4)
+    W = _random_net(cfg)
+    desc, r, h = _slot(n_prb=4)
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    l1 = cgnn.forward_x(W, cfg, X, [4] * 3)
+    l2 = cgnn.forward_x(W, cfg, X[2:], [4] * 3)      # drop two subcarriers: PE pattern keeps its phase
+    depth = 1 + 2 * cfg.C + 1                         # receptive-field radius in subcarriers
+    assert np.allclose(l1[:, :, 2 + depth:-depth], l2[:, :, depth:-depth], atol=1e-10)
+
+
+def test_single_ue_gets_no_messages_and_masking():
+    cfg = cgnn.NetConfig(2, 8, 2, 1, 4)
+    W = _random_net(cfg)
+    desc, r, h = _slot(U=1)
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    W2 = dict(W)
+    W2["mp0.w2"] = W["mp0.w2"] * 5.0
+    W2["mp0.b2"] = W["mp0.b2"] + 1.0
+    assert np.allclose(cgnn.forward_x(W, cfg, X, [4]), cgnn.forward_x(W2, cfg, X, [4]))
+    full = cgnn.forward_x(W, cfg, X, [4])
+    part = cgnn.forward_x(W, cfg, X, [2])
+    assert np.allclose(part[..., :2], full[..., :2]) and np.all(part[..., 2:] == 0)
+
+
+def _loss(W, cfg, X, bits, m_list, S):
+    llr = cgnn.forward_x(W, cfg, X, m_list)
+    lab, msk = cgnn.bit_labels_grid(bits, S, cfg.m_max)
+    valid = msk * (np.arange(cfg.m_max) < np.array(m_list)[:, None, None, None])
+    return cgnn.bce_terms(llr, lab, valid).sum() / valid.sum()
+
+
+def test_backward_matches_finite_differences():
+    # central differences in fp64 on a small instance (2 PRB, width 6, 2 blocks, 1 MP round, B=2, U=3)
+    cfg = cgnn.NetConfig(2, 6, 2, 1, 4)
+    W = _random_net(cfg, 3)
+    desc, r, h = _slot(seed=4)
+    m_list = [4, 2, 4]
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    llr, cache = cgnn.forward_x(W, cfg, X, m_list, keep=True)
+    lab, msk = cgnn.bit_labels_grid(r["bits"], desc.n_sc, cfg.m_max)
+    valid = msk * (np.arange(cfg.m_max) < np.array(m_list)[:, None, None, None])
+    G = cgnn.backward(W, cfg, cache, cgnn.bce_grad(llr, lab, valid, valid.sum()))
+    rng = np.random.default_rng(5)
+    eps = 1e-6
+    for name, shape in cgnn.layout(cfg):
+        for _ in range(3):
+            idx = tuple(rng.integers(0, n) for n in shape)
+            Wp, Wm = dict(W), dict(W)
+            Wp[name] = W[name].copy(); Wp[name][idx] += eps
+            Wm[name] = W[name].copy(); Wm[name][idx] -= eps
+            fd = (_loss(Wp, cfg, X, r["bits"], m_list, desc.n_sc)
+                  - _loss(Wm, cfg, X, r["bits"], m_list, desc.n_sc)) / (2 * eps)
+            assert abs(fd - G[name][idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, idx, fd, G[name][idx])
+    # a random direction through all weights at once
+    v = {k: rng.standard_normal(w.shape) for k, w in W.items()}
+    Wp = {k: W[k] + eps * v[k] for k in W}
+    Wm = {k: W[k] - eps * v[k] for k in W}
+    fd = (_loss(Wp, cfg, X, r["bits"], m_list, desc.n_sc) - _loss(Wm, cfg, X, r["bits"], m_list, desc.n_sc)) / (2 * eps)
+    an = sum(np.sum(G[k] * v[k]) for k in W)
+    assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def test_bce_and_adam():
+    assert np.isclose(cgnn.bce_terms(np.zeros(1), np.zeros(1), np.ones(1))[0], np.log(2))
+    big = np.array([800.0, -800.0])
+    assert np.allclose(cgnn.bce_terms(big, np.array([1.0, 0.0]), np.ones(2)), 0)
+    assert np.allclose(cgnn.bce_terms(big, np.array([0.0, 1.0]), np.ones(2)), 800)
+    # first Adam step moves every weight by lr * sign(g) (up to eps)
+    w = np.zeros(4)
+    g = np.array([3.0, -0.01, 1e-3, -40.0])
+    w1, m, v = cgnn.adam_step(w, g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
+    assert np.allclose(w1, -1e-3 * np.sign(g), rtol=1e-4)
