@@ -1,0 +1,149 @@
+// Device-side helpers shared by the libnrx kernels (gfx950 / CDNA4 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define NRX_T 14                 // OFDM symbols per slot
+#define NRX_DMRS0 2              // DMRS symbols (type A, l0 = 2, one additional position)
+#define NRX_DMRS1 11
+#define NRX_D 128                // state depth supported by the kernels
+#define NRX_MAXU 4
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
+typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8_t;
+
+typedef uint16_t bf16_t;  // storage type of bfloat16 activations and weights
+
+// float -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Scalar element traits for the two activation storage types.
+template <typename T> struct elem;
+template <> struct elem<float> {
+  __device__ static __forceinline__ float to_f(float x) { return x; }
+  __device__ static __forceinline__ float from_f(float x) { return x; }
+};
+template <> struct elem<bf16_t> {
+  __device__ static __forceinline__ float to_f(bf16_t x) { return bf2f(x); }
+  __device__ static __forceinline__ bf16_t from_f(float x) { return f2bf(x); }
+};
+
+// 16 bytes of operand data
+struct __align__(16) v16 { uint32_t w[4]; };
+
+__device__ __forceinline__ v16 ld16(const void *p) { return *reinterpret_cast<const v16 *>(p); }
+__device__ __forceinline__ void st16(void *p, v16 v) { *reinterpret_cast<v16 *>(p) = v; }
+
+// MFMA on one 16x16 output block.  D layout (all variants): lane l holds rows
+// 4*(l/16)+i, i = 0..3, of column l%16.
+//   bf16 16x16x32: lane l holds A[l%16][8*(l/16) .. +7] and B[8*(l/16) .. +7][l%16]
+//   fp32 16x16x4 : lane l holds A[l%16][l/16] and B[l/16][l%16]; four k-steps are
+//                  packed in one 16-byte fragment (k = 4*q + l/16, q = 0..3)
+__device__ __forceinline__ f32x4_t mfma_bf16(v16 a, v16 b, f32x4_t c) {
+  bf16x8_t av, bv;
+  __builtin_memcpy(&av, &a, 16);
+  __builtin_memcpy(&bv, &b, 16);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4_t mfma_f32x4(v16 a, v16 b, f32x4_t c) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w[q]), __uint_as_float(b.w[q]), c, 0, 0, 0);
+  return c;
+}
+
+template <typename T> struct mma;
+template <> struct mma<float> {
+  // one 16-byte fragment covers K = 16 (four fp32 k-steps)
+  static constexpr int KF = 16;
+  __device__ static __forceinline__ f32x4_t run(v16 a, v16 b, f32x4_t c) { return mfma_f32x4(a, b, c); }
+};
+template <> struct mma<bf16_t> {
+  static constexpr int KF = 32;
+  __device__ static __forceinline__ f32x4_t run(v16 a, v16 b, f32x4_t c) { return mfma_bf16(a, b, c); }
+};
+
+// Physical position of logical channel k inside a 64-byte K chunk so that each
+// lane's fragment is one contiguous 16-byte load (identity for bf16).
+template <typename T> __host__ __device__ __forceinline__ int kperm(int k);
+template <> __host__ __device__ __forceinline__ int kperm<bf16_t>(int k) { return k; }
+template <> __host__ __device__ __forceinline__ int kperm<float>(int k) { return (k & 3) * 4 + (k >> 2); }
+
+// Output-channel permutation used by every MFMA GEMM here: n-block nb, column j
+// of the MFMA output holds channel 8*j + nb, so a lane owns 8 consecutive
+// channels of each of its rows.
+__host__ __device__ __forceinline__ int nperm(int nb, int j) { return 8 * j + nb; }
+
+__device__ __forceinline__ float shfl_xor16(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// sum over the 16 lanes that share l/16 (the lanes owning one row's channels)
+__device__ __forceinline__ float row_sum16(float v) {
+  v += shfl_xor16(v, 1);
+  v += shfl_xor16(v, 2);
+  v += shfl_xor16(v, 4);
+  v += shfl_xor16(v, 8);
+  return v;
+}
+
+// 8 consecutive channels <-> 16/32 bytes
+template <typename T> struct pack8;
+template <> struct pack8<bf16_t> {
+  __device__ static __forceinline__ void load(const bf16_t *p, float *o) {
+    v16 v = ld16(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = __uint_as_float(v.w[i] << 16);
+      o[2 * i + 1] = __uint_as_float(v.w[i] & 0xFFFF0000u);
+    }
+  }
+  __device__ static __forceinline__ void store(bf16_t *p, const float *x) {
+    v16 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v.w[i] = (uint32_t)f2bf(x[2 * i]) | ((uint32_t)f2bf(x[2 * i + 1]) << 16);
+    st16(p, v);
+  }
+};
+template <> struct pack8<float> {
+  __device__ static __forceinline__ void load(const float *p, float *o) {
+    v16 a = ld16(p), b = ld16(p + 4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { o[i] = __uint_as_float(a.w[i]); o[4 + i] = __uint_as_float(b.w[i]); }
+  }
+  __device__ static __forceinline__ void store(float *p, const float *x) {
+    v16 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { a.w[i] = __float_as_uint(x[i]); b.w[i] = __float_as_uint(x[4 + i]); }
+    st16(p, a);
+    st16(p + 4, b);
+  }
+};
+
+// Per-slot geometry used by the row-tiled kernels (device copy of the plan).
+struct SlotGeo {
+  int32_t S;          // subcarriers
+  int32_t U;          // UEs
+  int32_t B;          // antennas of the slot
+  int32_t m[4];       // bits per symbol of each UE
+  int32_t slot_number, n_id, n_scid;
+  float n0;
+  int32_t pad;
+  int64_t row_base;   // first activation row of the slot
+  int64_t y_off;      // complex elements
+  int64_t h_off;      // complex elements
+  int64_t llr_off;    // floats
+  int64_t bits_off;   // bytes
+  int64_t dmrs_off;   // complex elements into the DMRS table ([2][S/2] per slot)
+};
+
+struct Tile {
+  int32_t slot;
+  int32_t row0;       // first row within the slot
+  int32_t nrows;
+  int32_t pad;
+};

@@ -1,0 +1,245 @@
+// 3x3 resource-grid convolution as an implicit GEMM on MFMA (gfx950).
+//
+// The CGNN's StateInit and CNN updates (Sec. II-A) are 3x3 convolutions over
+// (subcarrier, OFDM symbol) applied to every UE's state.  Activations are
+// stored channels-last as rows (slot, s, t, u) x 128 channels, so the 3x3
+// neighbourhood of a row is nine fixed row offsets {di*14U + dj*U} and the
+// rows of a tile plus one subcarrier of halo on each side are one contiguous
+// block of memory.
+//
+// Work decomposition
+//   workgroup = 4 waves, one tile of 64*MB consecutive rows of one slot
+//   wave      = 16*MB rows x all 128 output channels (MB x 8 MFMA blocks)
+//   K loop    = input-channel chunks of 64 bytes; per chunk the halo block is
+//               staged global -> registers -> LDS (double buffered, next chunk
+//               loaded while the current one is consumed) and reused by all
+//               nine taps; weights go global -> VGPRs directly (prefetched one
+//               tap ahead), since every wave needs all 128 output columns.
+//   t edges   = taps reaching t = -1 or t = 14 read a zero LDS row;
+//               s edges = halo rows outside the slot are staged as zeros.
+//   epilogue  = bias (+ positional-encoding field) -> store, or LayerNorm over
+//               the 128 channels of a row (intra-wave shuffles) -> ReLU, or a
+//               residual add; each lane owns 8 consecutive channels of a row so
+//               stores are full 16/32-byte vectors.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int PITCH = 80;  // bytes per LDS row: 64 data + 16 pad
+
+__host__ __device__ constexpr int halo_rows_max(int tile_rows) {
+  int best = 0;
+  for (int U = 1; U <= 4; ++U) {
+    int v = ((tile_rows - 1) / (14 * U) + 4) * 14 * U;
+    best = v > best ? v : best;
+  }
+  return best;
+}
+
+template <typename T, int MB, int EPI>
+__global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
+  constexpr int TILE = 64 * MB;
+  constexpr int HMAX = halo_rows_max(TILE);
+  constexpr int ZROW = HMAX;                     // all-zero row
+  constexpr int KC = 64 / (int)sizeof(T);        // channels per chunk
+  constexpr int UNITS = (HMAX * 4 + 255) / 256;  // 16-byte staging units per thread
+  __shared__ __align__(16) unsigned char lds[2][(HMAX + 1) * PITCH];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lr = lane & 15;   // MFMA row (A) / column (B, D) index
+  const int lk = lane >> 4;   // MFMA k-group (A, B) / row-group (D)
+
+  if (tid < 2 * (PITCH / 16)) {
+    v16 z = {{0, 0, 0, 0}};
+    st16(&lds[tid / (PITCH / 16)][ZROW * PITCH + (tid % (PITCH / 16)) * 16], z);
+  }
+
+  const int cin = a.c0 + a.c1;
+  const int nch = cin / KC;
+  int buf = 0;
+
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const int U = g.U, S = g.S;
+    const int rps = 14 * U;                       // rows per subcarrier
+    const int s_first = tl.row0 / rps;
+    const int s_last = (tl.row0 + tl.nrows - 1) / rps;
+    const int halo = (s_last - s_first + 3) * rps;
+    const int64_t g0 = g.row_base + (int64_t)(s_first - 1) * rps;   // global row of halo row 0
+
+    // per-lane A-row geometry for each m-block
+    int hc[MB], tt[MB];
+    bool rv[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      int r = wave * 16 * MB + mb * 16 + lr;
+      rv[mb] = r < tl.nrows;
+      int R = tl.row0 + r;
+      int s = R / rps;
+      int t = (R - s * rps) / U;
+      tt[mb] = t;
+      hc[mb] = R - (s_first - 1) * rps;
+    }
+
+    v16 stg[UNITS];
+    auto stage_load = [&](int c) {
+      const T *src;
+      int cs, coff;
+      if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
+      else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
+#pragma unroll
+      for (int q = 0; q < UNITS; ++q) {
+        int unit = tid + q * 256;
+        int h = unit >> 2, piece = unit & 3;
+        int s = s_first - 1 + h / rps;
+        v16 v = {{0, 0, 0, 0}};
+        if (h < halo && s >= 0 && s < S)
+          v = ld16(src + (g0 + h) * cs + coff + piece * (16 / (int)sizeof(T)));
+        stg[q] = v;
+      }
+    };
+    auto stage_store = [&](int b) {
+#pragma unroll
+      for (int q = 0; q < UNITS; ++q) {
+        int unit = tid + q * 256;
+        int h = unit >> 2, piece = unit & 3;
+        if (h < halo) {
+          unsigned char *row = &lds[b][h * PITCH];
+          if constexpr (sizeof(T) == 2) {
+            st16(row + piece * 16, stg[q]);
+          } else {
+            // fp32: logical channel 4*piece+e goes to position kperm = 4*e + piece
+            float *rf = reinterpret_cast<float *>(row);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) rf[4 * e + piece] = __uint_as_float(stg[q].w[e]);
+          }
+        }
+      }
+    };
+
+    f32x4_t acc[MB][8];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    stage_load(0);
+    buf ^= 1;
+    stage_store(buf);
+    __syncthreads();
+
+    // weight fragment pointer for (chunk, tap, nb): prepped [chunk][tap][nb][16][KC]
+    const T *wl = a.w + lr * KC + lk * (KC / 4);
+    auto load_b = [&](int c, int tap, v16 *bf) {
+      const T *p = wl + (size_t)((c * 9 + tap) * 8) * 16 * KC;
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) bf[nb] = ld16(p + nb * 16 * KC);
+    };
+
+    v16 bcur[8], bnxt[8];
+    load_b(0, 0, bcur);
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) stage_load(c + 1);
+      const unsigned char *lb = &lds[buf][lk * 16];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        if (tap < 8) load_b(c, tap + 1, bnxt);
+        else if (c + 1 < nch) load_b(c + 1, 0, bnxt);
+        const int di = tap / 3 - 1, dj = tap % 3 - 1;
+        const int off = di * rps + dj * U;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          bool ok = rv[mb] && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
+          int row = ok ? hc[mb] + off : ZROW;
+          v16 af = ld16(lb + row * PITCH);
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = mma<T>::run(af, bcur[nb], acc[mb][nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) bcur[nb] = bnxt[nb];
+      }
+      if (c + 1 < nch) {
+        buf ^= 1;
+        stage_store(buf);
+        __syncthreads();
+      }
+    }
+
+    // ---------------------------------------------------------- epilogue --
+    const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
+    float bias[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+        const bool valid = r < tl.nrows;
+        const int R = tl.row0 + (valid ? r : 0);
+        const int s = R / rps;
+        const int rem = R - s * rps;
+        const int t = rem / U, u = rem - (rem / U) * U;
+        const int64_t grow = g.row_base + R;
+        float v[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
+        if (a.pe) {
+          int par = (s - (u >> 1)) & 1;
+          int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
+          const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
+        }
+        if constexpr (EPI == EPI_LN_RELU) {
+          float sm = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) sm += v[nb];
+          const float mean = row_sum16(sm) * (1.0f / NRX_D);
+          float sq = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
+          const float var = row_sum16(sq) * (1.0f / NRX_D);
+          const float rstd = 1.0f / sqrtf(var + 1e-5f);
+          if (valid && a.save_z) {
+            pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
+            if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
+          }
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
+            v[nb] = n > 0.f ? n : 0.f;
+          }
+        } else if constexpr (EPI == EPI_RESID) {
+          float rsd[8];
+          if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
+        }
+        if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_conv(const ConvArgs<T> &a, int epi, int mb, int grid, hipStream_t st) {
+  dim3 blk(256);
+#define NRX_CONV_CASE(MBV, E)                                              \
+  if (mb == MBV && epi == E) {                                             \
+    hipLaunchKernelGGL((conv3x3_kernel<T, MBV, E>), dim3(grid), blk, 0, st, a); \
+    return;                                                                \
+  }
+  NRX_CONV_CASE(7, EPI_STORE) NRX_CONV_CASE(7, EPI_LN_RELU) NRX_CONV_CASE(7, EPI_RESID)
+  NRX_CONV_CASE(4, EPI_STORE) NRX_CONV_CASE(4, EPI_LN_RELU) NRX_CONV_CASE(4, EPI_RESID)
+#undef NRX_CONV_CASE
+}
+
+template void launch_conv<float>(const ConvArgs<float> &, int, int, int, hipStream_t);
+template void launch_conv<bf16_t>(const ConvArgs<bf16_t> &, int, int, int, hipStream_t);

@@ -1,0 +1,232 @@
+// Per-RE MLPs on MFMA: cross-UE message passing and the LLR readout.
+//
+// Message passing (Sec. II-A, CGNNit): every UE's state goes through an MLP,
+// m_u = W2 ReLU(W1 h_u + b1) + b2, and UE u receives the sum of the messages of
+// all *other* UEs at the same RE.  Rows are ordered (slot, s, t, u), so the U
+// rows of one RE are adjacent; a tile holds whole REs, both 128x128 GEMMs run on
+// MFMA (hidden activations pass through LDS to change from the output to the
+// operand layout), and the cross-UE sum is read back from LDS.
+//
+// ReadoutLLRs (Sec. II-A): l = W2 ReLU(W1 h + b1) + b2 with d -> d -> m_max; the
+// first layer runs on MFMA, the second (m_max <= 8 outputs) as per-lane partial
+// dot products over the lane's 8 channels reduced across the 16 lanes of a row.
+// Outputs j >= m_u are written as 0 (masking, Sec. III) in the [u][t][s][j]
+// layout.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int MLP_ROWS = 128;          // rows per tile, 4 waves x 2 m-blocks
+constexpr int MLP_MB = 2;
+
+// A fragment of row `row` (natural channel order, global) for K chunk c.
+template <typename T>
+__device__ __forceinline__ v16 afrag_global(const T *row, int c, int lk) {
+  constexpr int KC = 64 / (int)sizeof(T);
+  if constexpr (sizeof(T) == 2) {
+    return ld16(row + c * KC + lk * 8);
+  } else {
+    // fp32: the lane needs logical channels 4q + lk, q = 0..3
+    v16 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v.w[q] = __float_as_uint(row[c * KC + 4 * q + lk]);
+    return v;
+  }
+}
+
+// acc[mb][nb] += A(rows) x W for a 128-deep K; A comes from `afn(mb, c)`.
+template <typename T, typename AF>
+__device__ __forceinline__ void gemm128(f32x4_t (&acc)[MLP_MB][8], const T *w, int lr, int lk, AF afn) {
+  constexpr int KC = 64 / (int)sizeof(T);
+  constexpr int NCH = NRX_D / KC;
+#pragma unroll
+  for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const T *wl = w + lr * KC + lk * (KC / 4);
+#pragma unroll 2
+  for (int c = 0; c < NCH; ++c) {
+    v16 bf[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) bf[nb] = ld16(wl + (size_t)(c * 8 + nb) * 16 * KC);
+#pragma unroll
+    for (int mb = 0; mb < MLP_MB; ++mb) {
+      v16 af = afn(mb, c);
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = mma<T>::run(af, bf[nb], acc[mb][nb]);
+    }
+  }
+}
+
+// LDS staging of a 128-row x 128-channel tile in operand layout: row pitch of
+// 128 elements + 16 bytes, K chunks contiguous, channels permuted with kperm.
+template <typename T>
+struct OpTile {
+  static constexpr int KC = 64 / (int)sizeof(T);
+  static constexpr int PITCHB = NRX_D * (int)sizeof(T) + 16;
+  __device__ static __forceinline__ void put8(unsigned char *lds, int row, int ch0, const float *v) {
+    T *r = reinterpret_cast<T *>(lds + row * PITCHB);
+    if constexpr (sizeof(T) == 2) {
+      pack8<T>::store(r + ch0, v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int ch = ch0 + e;
+        r[(ch / KC) * KC + kperm<T>(ch % KC)] = v[e];
+      }
+    }
+  }
+  __device__ static __forceinline__ v16 frag(const unsigned char *lds, int row, int c, int lk) {
+    return ld16(lds + row * PITCHB + c * 64 + lk * 16);
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void mp_kernel(MlpArgs<T> a) {
+  // one region reused: hidden activations (operand layout), then fp32 messages
+  constexpr int MSG_PITCH = NRX_D + 4;   // floats
+  constexpr int BYTES = MLP_ROWS * MSG_PITCH * 4;
+  __shared__ __align__(16) unsigned char lds[BYTES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ch0 = 8 * lr;
+
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const int64_t gbase = g.row_base + tl.row0;
+    f32x4_t acc[MLP_MB][8];
+    // GEMM 1 from global rows
+    gemm128<T>(acc, a.w1, lr, lk, [&](int mb, int c) {
+      int r = wave * 16 * MLP_MB + mb * 16 + lr;
+      r = r < tl.nrows ? r : 0;
+      return afrag_global<T>(a.h + (gbase + r) * NRX_D, c, lk);
+    });
+    __syncthreads();   // previous tile's readers of the LDS region are done
+#pragma unroll
+    for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
+        float v[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          float x = acc[mb][nb][i] + a.b1[ch0 + nb];
+          v[nb] = x > 0.f ? x : 0.f;
+        }
+        if (sizeof(T) == 2) {   // the bf16 path feeds bf16-rounded hidden values to GEMM 2
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) v[nb] = bf2f(f2bf(v[nb]));
+        }
+        OpTile<T>::put8(lds, r, ch0, v);
+        if (a.save_m1 && r < tl.nrows) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, v);
+      }
+    __syncthreads();
+    gemm128<T>(acc, a.w2, lr, lk, [&](int mb, int c) {
+      int r = wave * 16 * MLP_MB + mb * 16 + lr;
+      return OpTile<T>::frag(lds, r, c, lk);
+    });
+    __syncthreads();   // all hidden-activation reads done before the region is reused
+    float *msg = reinterpret_cast<float *>(lds);
+#pragma unroll
+    for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) msg[r * MSG_PITCH + ch0 + nb] = acc[mb][nb][i] + a.b2[ch0 + nb];
+      }
+    __syncthreads();
+    // aggregation: agg_u = sum over the other UEs of the same RE
+    const int U = g.U;
+    for (int e = tid; e < tl.nrows * 16; e += 256) {
+      const int r = e >> 4, c8 = (e & 15) * 8;
+      const int u = r % U, re0 = r - u;
+      float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int o = 0; o < U; ++o) {
+        if (o == u) continue;
+        const float *m = msg + (re0 + o) * MSG_PITCH + c8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] += m[k];
+      }
+      pack8<T>::store(a.out + (gbase + r) * NRX_D + c8, v);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int ch0 = 8 * lr;
+  const int M = a.m_max;
+  float w2[8][8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w2[nb][j] = j < M ? a.w2f[(ch0 + nb) * M + j] : 0.f;
+
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const int64_t gbase = g.row_base + tl.row0;
+    f32x4_t acc[MLP_MB][8];
+    gemm128<T>(acc, a.w1, lr, lk, [&](int mb, int c) {
+      int r = wave * 16 * MLP_MB + mb * 16 + lr;
+      r = r < tl.nrows ? r : 0;
+      return afrag_global<T>(a.h + (gbase + r) * NRX_D, c, lk);
+    });
+    const int U = g.U, S = g.S;
+#pragma unroll
+    for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
+        float q[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          float x = acc[mb][nb][i] + a.b1[ch0 + nb];
+          q[nb] = x > 0.f ? x : 0.f;
+        }
+        if (sizeof(T) == 2) {
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) q[nb] = bf2f(f2bf(q[nb]));
+        }
+        const bool valid = r < tl.nrows;
+        if (a.save_m1 && valid) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, q);
+        float o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float p = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) p += q[nb] * w2[nb][j];
+          o[j] = row_sum16(p);
+        }
+        if (valid && lr == 0) {
+          const int R = tl.row0 + r;
+          const int s = R / (14 * U);
+          const int rem = R - s * 14 * U;
+          const int t = rem / U, u = rem - t * U;
+          const int mu = g.m[u];
+          float *dst = a.llr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
+          for (int j = 0; j < M; ++j) dst[j] = j < mu ? o[j] + a.b2[j] : 0.f;
+        }
+      }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(mp_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+template <typename T>
+void launch_readout(const MlpArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(readout_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+template void launch_mp<float>(const MlpArgs<float> &, int, hipStream_t);
+template void launch_mp<bf16_t>(const MlpArgs<bf16_t> &, int, hipStream_t);
+template void launch_readout<float>(const MlpArgs<float> &, int, hipStream_t);
+template void launch_readout<bf16_t>(const MlpArgs<bf16_t> &, int, hipStream_t);

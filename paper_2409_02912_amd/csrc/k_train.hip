@@ -1,0 +1,189 @@
+// Weight preparation, BCE loss and Adam.
+//
+// Weight preparation turns the fp32 master weights (natural layout: convolutions
+// [3][3][C_in][C_out], dense [C_in][C_out]) into MFMA operand layouts in the
+// compute precision, and folds the positional-encoding input channels of a
+// convolution into a bias field.  The PE (distance in symbols to the nearest
+// DMRS symbol, standardised over the slot; +-1 for REs off/on the UE's DMRS comb)
+// depends on (s, t) only through t, the subcarrier parity relative to the UE's
+// CDM group and whether s is the first or last subcarrier, so its 3x3
+// convolution is a [2][3][14][C_out] table.
+//
+// BCE (Sec. II-B): softplus(l) - b l over the data REs of every UE's m_u bits,
+// averaged; the loss is reduced in fp64, deterministically (fixed partial order).
+// Adam: Kingma & Ba, bias-corrected.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+__device__ float pe_t_value(int t) {
+  float mean = 0.f;
+  float d[14];
+  for (int k = 0; k < 14; ++k) {
+    int a = k - NRX_DMRS0, b = k - NRX_DMRS1;
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    d[k] = (float)(a < b ? a : b);
+    mean += d[k];
+  }
+  mean /= 14.f;
+  float var = 0.f;
+  for (int k = 0; k < 14; ++k) var += (d[k] - mean) * (d[k] - mean);
+  return (d[t] - mean) / sqrtf(var / 14.f);
+}
+
+template <typename T>
+__global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int64_t total, T *wprep,
+                            float *fields) {
+  constexpr int KC = 64 / (int)sizeof(T);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int jb = 0;
+  int64_t base = 0;
+  while (jb < n_jobs && e >= base + jobs[jb].count) { base += jobs[jb].count; ++jb; }
+  const PrepJob J = jobs[jb];
+  const int64_t k = e - base;
+  if (J.kind == 2) {
+    // PE field [par][edge][t][o]
+    const int o = k % NRX_D, t = (k / NRX_D) % 14, edge = (k / (NRX_D * 14)) % 3, par = k / (NRX_D * 42);
+    float acc = 0.f;
+    for (int i = 0; i < 3; ++i) {
+      const int di = i - 1;
+      if ((edge == 1 && di < 0) || (edge == 2 && di > 0)) continue;
+      const float pf = ((par + di) & 1) ? 1.f : -1.f;
+      for (int j = 0; j < 3; ++j) {
+        const int tt = t + j - 1;
+        if (tt < 0 || tt >= 14) continue;
+        const int64_t wt = J.src + ((int64_t)(i * 3 + j) * J.cin_total + J.cin_real) * NRX_D + o;
+        acc += w[wt] * pe_t_value(tt) + w[wt + NRX_D] * pf;
+      }
+    }
+    fields[J.dst + k] = acc;
+    return;
+  }
+  const int p = k % KC;
+  const int kl = sizeof(T) == 4 ? ((p & 3) * 4 + (p >> 2)) : p;   // inverse of kperm (an involution)
+  const int j = (k / KC) % 16, nb = (k / (16 * KC)) % 8;
+  const int n = nperm(nb, j);
+  float v = 0.f;
+  if (J.kind == 1) {
+    const int chunk = k / (128 * KC);
+    const int c = chunk * KC + kl;
+    if (c < J.cin_real) v = w[J.src + (int64_t)c * NRX_D + n];
+  } else {
+    const int tap = (k / (128 * KC)) % 9, chunk = k / (1152 * KC);
+    const int c = chunk * KC + kl;
+    if (J.kind == 0) {
+      if (c < J.cin_real) v = w[J.src + ((int64_t)tap * J.cin_total + c) * NRX_D + n];
+    } else {
+      // transposed, flipped: K = original output channel c, N = original input channel cin_first + n
+      v = w[J.src + ((int64_t)(8 - tap) * J.cin_total + J.cin_first + n) * NRX_D + c];
+    }
+  }
+  wprep[J.dst + k] = elem<T>::from_f(v);
+}
+
+__global__ void bce_kernel(const SlotGeo *geo, int m_max, const float *llr, const uint8_t *bits, float *dllr,
+                           double *partials, unsigned long long *perr, double inv_n) {
+  const int slot = blockIdx.y;
+  const SlotGeo g = geo[slot];
+  const int S = g.S, U = g.U;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // (u, t, s)
+  double loss = 0.0;
+  unsigned long long nerr = 0;
+  if (idx < U * 14 * S) {
+    const int u = idx / (14 * S), t = (idx / S) % 14, s = idx % S;
+    const float *l = llr + g.llr_off + (int64_t)idx * m_max;
+    float *dl = dllr ? dllr + g.llr_off + (int64_t)idx * m_max : nullptr;
+    const bool data = t != NRX_DMRS0 && t != NRX_DMRS1;
+    const int td = t < NRX_DMRS0 ? t : (t < NRX_DMRS1 ? t - 1 : t - 2);
+    const uint8_t *b = bits + g.bits_off + ((int64_t)u * S * 12 + (int64_t)td * S + s) * m_max;
+    for (int j = 0; j < m_max; ++j) {
+      float gr = 0.f;
+      if (data && j < g.m[u]) {
+        const double x = l[j];
+        const double y = b[j];
+        loss += fmax(x, 0.0) + log1p(exp(-fabs(x))) - y * x;
+        gr = (float)((1.0 / (1.0 + exp(-x)) - y) * inv_n);
+        nerr += ((x > 0.0) != (b[j] != 0));
+      }
+      if (dl) dl[j] = gr;
+    }
+  }
+  // block reduction (fixed order)
+  __shared__ double sl[256];
+  __shared__ unsigned long long se[256];
+  sl[threadIdx.x] = loss;
+  se[threadIdx.x] = nerr;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) { sl[threadIdx.x] += sl[threadIdx.x + w]; se[threadIdx.x] += se[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t pi = (int64_t)slot * gridDim.x + blockIdx.x;
+    partials[pi] = sl[0];
+    perr[pi] = se[0];
+  }
+}
+
+__global__ void reduce_kernel(const double *partials, const unsigned long long *perr, int64_t n, double *loss,
+                              unsigned long long *nerr, double inv_n) {
+  __shared__ double sl[256];
+  __shared__ unsigned long long se[256];
+  double a = 0.0;
+  unsigned long long c = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) { a += partials[i]; c += perr[i]; }
+  sl[threadIdx.x] = a;
+  se[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) { sl[threadIdx.x] += sl[threadIdx.x + w]; se[threadIdx.x] += se[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (loss) *loss = sl[0] * inv_n;
+    if (nerr) *nerr = se[0];
+  }
+}
+
+__global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_prep(const float *w, const PrepJob *jobs, int n_jobs, int64_t total, T *wprep, float *fields,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(prep_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, w, jobs, n_jobs, total,
+                     wprep, fields);
+}
+template void launch_prep<float>(const float *, const PrepJob *, int, int64_t, float *, float *, hipStream_t);
+template void launch_prep<bf16_t>(const float *, const PrepJob *, int, int64_t, bf16_t *, float *, hipStream_t);
+
+void launch_bce(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_ute, int m_max, const float *llr,
+                const uint8_t *bits, float *dllr, double *partials, int n_part_per_slot, double *loss,
+                unsigned long long *nerr, double inv_n, hipStream_t st) {
+  unsigned long long *perr = reinterpret_cast<unsigned long long *>(partials + (int64_t)n_slots * n_part_per_slot);
+  hipLaunchKernelGGL(bce_kernel, dim3(n_part_per_slot, n_slots), dim3(256), 0, st, geo, m_max, llr, bits, dllr,
+                     partials, perr, inv_n);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, (const double *)partials,
+                     (const unsigned long long *)perr, (int64_t)n_slots * n_part_per_slot, loss, nerr, inv_n);
+  (void)max_ute;
+}
+
+void launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps,
+                     c1, c2);
+}

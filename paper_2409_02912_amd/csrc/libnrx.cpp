@@ -1,0 +1,804 @@
+// libnrx host side: validation, batch plans, workspace layout and the C ABI.
+//
+// A "plan" is everything derived from a batch's slot descriptors: per-slot
+// geometry, the row tiles of every kernel and the workspace layout.  Plans are
+// cached by a hash of the descriptors; their device-side tables are staged in
+// pinned host memory and copied into the caller's workspace with an async copy on
+// the caller's stream at every call, so a call only enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/libnrx.h"
+#include "internal.h"
+
+// ------------------------------------------------------------------ errors --
+
+static thread_local std::string g_err;
+
+static nrx_status fail(nrx_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(NRX_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char *nrx_last_error(void) { return g_err.c_str(); }
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ----------------------------------------------------------------- layouts --
+
+namespace {
+
+constexpr int CONV_MB = 4;                 // conv tile = 64 * CONV_MB rows
+constexpr int CONV_TILE = 64 * CONV_MB;
+constexpr int MLP_TILE = 128;
+
+struct TensorInfo {
+  std::string name;
+  int64_t off;
+  int ndim;
+  int shape[4];
+};
+
+struct ConvLayer {
+  int64_t w = 0, b = 0;         // master offsets
+  int cin_real = 0, cin_total = 0, n_chunks = 0;
+  int64_t prep = 0;             // element offset in the prepped buffer
+  int64_t field = -1;           // element offset in the field buffer (PE folded) or -1
+};
+
+struct BlockLayer {
+  ConvLayer a, b;
+  int64_t g = 0, beta = 0;
+  int mp_round = -1;            // message-passing round before this block, or -1
+};
+
+struct DenseLayer {
+  int64_t w1 = 0, b1 = 0, w2 = 0, b2 = 0;
+  int64_t p1 = 0, p2 = -1;      // prepped offsets
+};
+
+struct Plan {
+  int n = 0;
+  std::vector<SlotGeo> geo;
+  std::vector<Tile> ct, mt, rt;
+  std::vector<int64_t> pair_off, tap_off;
+  int64_t rows = 0, max_rows = 0, max_re = 0, max_pairs = 0, max_ute = 0, max_bits = 0;
+  int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
+  int max_ubl = 0;
+  // device table blob
+  size_t off_geo = 0, off_ct = 0, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
+  std::vector<char> blob;        // host image of the device tables
+  void *pinned = nullptr;        // pinned copy, allocated on first upload
+  ~Plan() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
+};
+
+uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+struct PlanCache {
+  std::mutex mu;
+  std::map<uint64_t, std::unique_ptr<Plan>> plans;
+};
+
+PlanCache g_plans;  // shared by model-free calls and models
+
+// Validates descriptors and builds (or fetches) the plan.  max_ant bounds n_ant.
+nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int sim_taps, Plan **out) {
+  if (!d || n <= 0) return fail(NRX_ERR_INVALID, "no slot descriptors");
+  for (int i = 0; i < n; ++i) {
+    const nrx_slot_desc &s = d[i];
+    if (s.n_prb < 1 || s.n_prb > 275) return fail(NRX_ERR_SHAPE, "slot %d: n_prb %d outside 1..275", i, s.n_prb);
+    if (s.n_ant < 1 || s.n_ant > max_ant)
+      return fail(NRX_ERR_SHAPE, "slot %d: n_ant %d outside 1..%d", i, s.n_ant, max_ant);
+    if (s.n_ue < 1 || s.n_ue > 4) return fail(NRX_ERR_SHAPE, "slot %d: n_ue %d outside 1..4", i, s.n_ue);
+    for (int u = 0; u < s.n_ue; ++u) {
+      int m = s.bits_per_sym[u];
+      if (m != 2 && m != 4 && m != 6 && m != 8) return fail(NRX_ERR_SHAPE, "slot %d UE %d: bits_per_sym %d", i, u, m);
+      if (m > m_max) return fail(NRX_ERR_SHAPE, "slot %d UE %d: bits_per_sym %d > m_max %d", i, u, m, m_max);
+    }
+    if (s.n_scid < 0 || s.n_scid > 1 || s.n_id < 0 || s.n_id > 65535 || s.slot_number < 0 || s.slot_number > 1023)
+      return fail(NRX_ERR_SHAPE, "slot %d: DMRS scrambling parameters out of range", i);
+    if (s.y_offset < 0 || s.h_offset < 0 || s.llr_offset < 0 || s.bits_offset < 0)
+      return fail(NRX_ERR_INVALID, "slot %d: negative offset", i);
+  }
+  uint64_t key = fnv(d, sizeof(nrx_slot_desc) * (size_t)n);
+  key = fnv(&n, sizeof n, key);
+  key = fnv(&sim_taps, sizeof sim_taps, key);
+  std::lock_guard<std::mutex> lk(g_plans.mu);
+  auto it = g_plans.plans.find(key);
+  if (it != g_plans.plans.end()) { *out = it->second.get(); return NRX_OK; }
+  if (g_plans.plans.size() >= 4096) return fail(NRX_ERR_UNSUPPORTED, "too many distinct batch shapes cached");
+  auto P = std::make_unique<Plan>();
+  P->n = n;
+  int64_t row = 0, dm = 0, pr = 0, tp = 0;
+  for (int i = 0; i < n; ++i) {
+    const nrx_slot_desc &s = d[i];
+    SlotGeo g{};
+    g.S = 12 * s.n_prb;
+    g.U = s.n_ue;
+    g.B = s.n_ant;
+    for (int u = 0; u < 4; ++u) g.m[u] = u < s.n_ue ? s.bits_per_sym[u] : 0;
+    g.slot_number = s.slot_number;
+    g.n_id = s.n_id;
+    g.n_scid = s.n_scid;
+    g.n0 = s.n0;
+    g.row_base = row;
+    g.y_off = s.y_offset;
+    g.h_off = s.h_offset;
+    g.llr_off = s.llr_offset;
+    g.bits_off = s.bits_offset;
+    g.dmrs_off = dm;
+    P->geo.push_back(g);
+    const int64_t rows = (int64_t)g.S * 14 * g.U;
+    for (int64_t r = 0; r < rows; r += CONV_TILE)
+      P->ct.push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(CONV_TILE, rows - r), 0});
+    const int mtr = (MLP_TILE / g.U) * g.U;
+    for (int64_t r = 0; r < rows; r += mtr)
+      P->mt.push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(mtr, rows - r), 0});
+    for (int64_t r = 0; r < rows; r += MLP_TILE)
+      P->rt.push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(MLP_TILE, rows - r), 0});
+    P->pair_off.push_back(pr);
+    P->tap_off.push_back(tp);
+    const int64_t npairs = 2LL * g.U * (g.S / 4) * g.B;
+    const int ubl = g.U * g.B * std::max(sim_taps, 1);
+    row += rows;
+    dm += g.S;
+    pr += npairs;
+    tp += (int64_t)ubl * 14;
+    P->max_rows = std::max(P->max_rows, rows);
+    P->max_re = std::max<int64_t>(P->max_re, (int64_t)g.S * 14);
+    P->max_pairs = std::max(P->max_pairs, npairs);
+    P->max_ute = std::max<int64_t>(P->max_ute, (int64_t)g.U * 14 * g.S);
+    P->max_bits = std::max<int64_t>(P->max_bits, (int64_t)g.U * 12 * g.S);
+    P->max_ubl = std::max(P->max_ubl, ubl);
+    int nb = 0;
+    for (int u = 0; u < g.U; ++u) nb += g.m[u];
+    P->n_data_bits += (int64_t)nb * 12 * g.S;
+  }
+  P->pair_off.push_back(pr);
+  P->tap_off.push_back(tp);
+  P->rows = row;
+  P->dmrs_total = dm;
+  P->pairs_total = pr;
+  size_t o = 0;
+  P->off_geo = o; o = align256(o + sizeof(SlotGeo) * P->geo.size());
+  P->off_ct = o; o = align256(o + sizeof(Tile) * P->ct.size());
+  P->off_mt = o; o = align256(o + sizeof(Tile) * P->mt.size());
+  P->off_rt = o; o = align256(o + sizeof(Tile) * P->rt.size());
+  P->off_pair = o; o = align256(o + sizeof(int64_t) * P->pair_off.size());
+  P->off_tap = o; o = align256(o + sizeof(int64_t) * P->tap_off.size());
+  P->meta_bytes = o;
+  P->blob.assign(o, 0);
+  char *b = P->blob.data();
+  memcpy(b + P->off_geo, P->geo.data(), sizeof(SlotGeo) * P->geo.size());
+  memcpy(b + P->off_ct, P->ct.data(), sizeof(Tile) * P->ct.size());
+  memcpy(b + P->off_mt, P->mt.data(), sizeof(Tile) * P->mt.size());
+  memcpy(b + P->off_rt, P->rt.data(), sizeof(Tile) * P->rt.size());
+  memcpy(b + P->off_pair, P->pair_off.data(), sizeof(int64_t) * P->pair_off.size());
+  memcpy(b + P->off_tap, P->tap_off.data(), sizeof(int64_t) * P->tap_off.size());
+  *out = P.get();
+  g_plans.plans[key] = std::move(P);
+  return NRX_OK;
+}
+
+// Enqueues the copy of the plan's device tables into the workspace.
+nrx_status plan_upload(Plan *P, char *dst, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g_plans.mu);
+    if (!P->pinned) {
+      if (hipHostMalloc(&P->pinned, P->meta_bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(NRX_ERR_HIP, "hipHostMalloc of %zu bytes failed", P->meta_bytes);
+      memcpy(P->pinned, P->blob.data(), P->meta_bytes);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(dst, P->pinned, P->meta_bytes, hipMemcpyHostToDevice, st));
+  return NRX_OK;
+}
+
+struct Dev {
+  const SlotGeo *geo;
+  const Tile *ct, *mt, *rt;
+  const int64_t *pair_off, *tap_off;
+};
+
+Dev dev_tables(const Plan *P, char *ws) {
+  return Dev{(const SlotGeo *)(ws + P->off_geo), (const Tile *)(ws + P->off_ct), (const Tile *)(ws + P->off_mt),
+             (const Tile *)(ws + P->off_rt), (const int64_t *)(ws + P->off_pair), (const int64_t *)(ws + P->off_tap)};
+}
+
+int g_num_cu = 0;
+int num_cu() {
+  if (!g_num_cu) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) g_num_cu = p.multiProcessorCount;
+    if (g_num_cu <= 0) g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- model --
+
+struct nrx_model {
+  nrx_model_config cfg;
+  std::vector<TensorInfo> tensors;
+  int64_t n_w = 0;
+  int cx = 0;                           // feature channels of the StateInit input
+  ConvLayer conv_in;
+  std::vector<BlockLayer> blocks;
+  std::vector<DenseLayer> mp;
+  DenseLayer ro;
+  std::vector<PrepJob> jobs;
+  int64_t prep_elems = 0, field_elems = 0, prep_total = 0;
+  void *pinned_jobs = nullptr;
+  size_t tsize = 4;                     // bytes per activation / operand element
+  // last save_acts forward (for nrx_backward)
+  const void *saved_ws = nullptr;
+  const Plan *saved_plan = nullptr;
+  std::mutex mu;
+};
+
+static void add_tensor(nrx_model *m, const std::string &name, std::vector<int> shape) {
+  TensorInfo t;
+  t.name = name;
+  t.off = m->n_w;
+  t.ndim = (int)shape.size();
+  int64_t n = 1;
+  for (int i = 0; i < 4; ++i) t.shape[i] = i < t.ndim ? shape[i] : 1;
+  for (int v : shape) n *= v;
+  m->tensors.push_back(t);
+  m->n_w += n;
+}
+
+static int64_t toff(nrx_model *m, const std::string &name) {
+  for (auto &t : m->tensors)
+    if (t.name == name) return t.off;
+  return -1;
+}
+
+extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **out) {
+  if (!cfg || !out) return fail(NRX_ERR_INVALID, "null argument");
+  const nrx_model_config &c = *cfg;
+  if (c.d != NRX_D) return fail(NRX_ERR_SHAPE, "d = %d: this build supports d = 128", c.d);
+  if (c.n_ant != 4 && c.n_ant != 8 && c.n_ant != 16) return fail(NRX_ERR_SHAPE, "n_ant %d not in {4, 8, 16}", c.n_ant);
+  if (c.n_blocks < 1 || c.n_blocks > 16) return fail(NRX_ERR_SHAPE, "n_blocks %d outside 1..16", c.n_blocks);
+  if (c.n_rounds < 0 || c.n_rounds > c.n_blocks) return fail(NRX_ERR_SHAPE, "n_rounds %d outside 0..n_blocks", c.n_rounds);
+  if (c.m_max != 2 && c.m_max != 4 && c.m_max != 6 && c.m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", c.m_max);
+  if (c.precision != NRX_FP32 && c.precision != NRX_BF16)
+    return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
+  auto m = std::make_unique<nrx_model>();
+  m->cfg = c;
+  m->tsize = c.precision == NRX_FP32 ? 4 : 2;
+  const int d = c.d, B = c.n_ant;
+  m->cx = std::max(32, 4 * B);
+  std::vector<int> mpb;
+  for (int r = 0; r < c.n_rounds; ++r) mpb.push_back((r * c.n_blocks) / c.n_rounds);
+  add_tensor(m.get(), "conv_in.w", {3, 3, 4 * B + 2, d});
+  add_tensor(m.get(), "conv_in.b", {d});
+  for (int i = 0; i < c.n_blocks; ++i) {
+    bool ismp = false;
+    for (int v : mpb) ismp = ismp || v == i;
+    const int cin = ismp ? 2 * d + 2 : d;
+    const std::string p = "blk" + std::to_string(i);
+    add_tensor(m.get(), p + ".conv_a.w", {3, 3, cin, d});
+    add_tensor(m.get(), p + ".conv_a.b", {d});
+    add_tensor(m.get(), p + ".ln.g", {d});
+    add_tensor(m.get(), p + ".ln.b", {d});
+    add_tensor(m.get(), p + ".conv_b.w", {3, 3, d, d});
+    add_tensor(m.get(), p + ".conv_b.b", {d});
+  }
+  for (int r = 0; r < c.n_rounds; ++r) {
+    const std::string p = "mp" + std::to_string(r);
+    add_tensor(m.get(), p + ".w1", {d, d});
+    add_tensor(m.get(), p + ".b1", {d});
+    add_tensor(m.get(), p + ".w2", {d, d});
+    add_tensor(m.get(), p + ".b2", {d});
+  }
+  add_tensor(m.get(), "readout.w1", {d, d});
+  add_tensor(m.get(), "readout.b1", {d});
+  add_tensor(m.get(), "readout.w2", {d, c.m_max});
+  add_tensor(m.get(), "readout.b2", {c.m_max});
+
+  // weight preparation jobs
+  const int KC = 64 / (int)m->tsize;
+  auto conv_job = [&](ConvLayer &L, int64_t w, int64_t b, int cin_real, int cin_total, int cin_pad, bool pe) {
+    L.w = w; L.b = b; L.cin_real = cin_real; L.cin_total = cin_total; L.n_chunks = cin_pad / KC;
+    L.prep = m->prep_elems;
+    PrepJob j{0, cin_real, cin_total, L.n_chunks, 0, 0, w, L.prep, (int64_t)cin_pad * 9 * 128};
+    m->jobs.push_back(j);
+    m->prep_elems += j.count;
+    if (pe) {
+      L.field = m->field_elems;
+      PrepJob f{2, cin_real, cin_total, 0, 0, 0, w, L.field, 2 * 3 * 14 * 128};
+      m->jobs.push_back(f);
+      m->field_elems += f.count;
+    }
+  };
+  auto dense_job = [&](int64_t w, int64_t &p) {
+    p = m->prep_elems;
+    PrepJob j{1, d, d, d / KC, 0, 0, w, p, (int64_t)d * 128};
+    m->jobs.push_back(j);
+    m->prep_elems += j.count;
+  };
+  conv_job(m->conv_in, toff(m.get(), "conv_in.w"), toff(m.get(), "conv_in.b"), 4 * B, 4 * B + 2, m->cx, true);
+  m->mp.resize(c.n_rounds);
+  for (int i = 0; i < c.n_blocks; ++i) {
+    const std::string p = "blk" + std::to_string(i);
+    BlockLayer L;
+    for (int r = 0; r < c.n_rounds; ++r)
+      if (mpb[r] == i) L.mp_round = r;
+    const bool isb = L.mp_round >= 0;
+    conv_job(L.a, toff(m.get(), p + ".conv_a.w"), toff(m.get(), p + ".conv_a.b"), isb ? 2 * d : d,
+             isb ? 2 * d + 2 : d, isb ? 2 * d : d, isb);
+    L.g = toff(m.get(), p + ".ln.g");
+    L.beta = toff(m.get(), p + ".ln.b");
+    conv_job(L.b, toff(m.get(), p + ".conv_b.w"), toff(m.get(), p + ".conv_b.b"), d, d, d, false);
+    m->blocks.push_back(L);
+  }
+  for (int r = 0; r < c.n_rounds; ++r) {
+    const std::string p = "mp" + std::to_string(r);
+    DenseLayer &L = m->mp[r];
+    L.w1 = toff(m.get(), p + ".w1"); L.b1 = toff(m.get(), p + ".b1");
+    L.w2 = toff(m.get(), p + ".w2"); L.b2 = toff(m.get(), p + ".b2");
+    dense_job(L.w1, L.p1);
+    dense_job(L.w2, L.p2);
+  }
+  m->ro.w1 = toff(m.get(), "readout.w1"); m->ro.b1 = toff(m.get(), "readout.b1");
+  m->ro.w2 = toff(m.get(), "readout.w2"); m->ro.b2 = toff(m.get(), "readout.b2");
+  dense_job(m->ro.w1, m->ro.p1);
+  // field jobs index a separate buffer; the prep kernel walks jobs in order over one index space
+  m->prep_total = 0;
+  for (auto &j : m->jobs) m->prep_total += j.count;
+  *out = m.release();
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  if (m->pinned_jobs) (void)hipHostFree(m->pinned_jobs);
+  delete m;
+  return NRX_OK;
+}
+
+extern "C" int64_t nrx_weight_count(const nrx_model *m) { return m ? m->n_w : -1; }
+
+extern "C" nrx_status nrx_weight_tensor(const nrx_model *m, int32_t idx, char *name, int32_t name_len, int64_t *offset,
+                                        int32_t *ndim, int32_t shape[4]) {
+  if (!m || idx < 0 || idx >= (int)m->tensors.size()) return fail(NRX_ERR_INVALID, "tensor index out of range");
+  const TensorInfo &t = m->tensors[idx];
+  if (name && name_len > 0) snprintf(name, name_len, "%s", t.name.c_str());
+  if (offset) *offset = t.off;
+  if (ndim) *ndim = t.ndim;
+  if (shape)
+    for (int i = 0; i < 4; ++i) shape[i] = t.shape[i];
+  return NRX_OK;
+}
+
+// -------------------------------------------------------- forward workspace --
+
+namespace {
+
+struct FwdLayout {
+  size_t meta, jobs, wprep, fields, dmrs, pairs, X;
+  std::vector<size_t> h;      // h_0 .. h_C (inference: one buffer)
+  std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
+  std::vector<size_t> stats;  // per block (training)
+  std::vector<size_t> agg, m1;  // per round (inference: one agg)
+  size_t q;                   // readout hidden (training)
+  size_t total;
+};
+
+FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
+  FwdLayout L;
+  const size_t ts = m->tsize;
+  const size_t act = align256((size_t)P->rows * NRX_D * ts);
+  size_t o = 0;
+  L.meta = o; o = align256(o + P->meta_bytes);
+  L.jobs = o; o = align256(o + sizeof(PrepJob) * m->jobs.size());
+  L.wprep = o; o = align256(o + (size_t)m->prep_elems * ts);
+  L.fields = o; o = align256(o + (size_t)std::max<int64_t>(m->field_elems, 1) * 4);
+  L.dmrs = o; o = align256(o + (size_t)P->dmrs_total * 8);
+  L.pairs = o; o = align256(o + (size_t)P->pairs_total * 8);
+  L.X = o; o = align256(o + (size_t)P->rows * m->cx * ts);
+  const int C = m->cfg.n_blocks, R = m->cfg.n_rounds;
+  if (!save) {
+    L.h.push_back(o); o += act;
+    L.a.push_back(o); o += act;
+    L.agg.push_back(o); o += act;
+    L.q = 0;
+  } else {
+    for (int i = 0; i <= C; ++i) { L.h.push_back(o); o += act; }
+    for (int i = 0; i < C; ++i) { L.z.push_back(o); o += act; }
+    for (int i = 0; i < C; ++i) { L.a.push_back(o); o += act; }
+    for (int i = 0; i < C; ++i) { L.stats.push_back(o); o = align256(o + (size_t)P->rows * 8); }
+    for (int r = 0; r < R; ++r) { L.agg.push_back(o); o += act; }
+    for (int r = 0; r < R; ++r) { L.m1.push_back(o); o += act; }
+    L.q = o; o += act;
+  }
+  L.total = o;
+  return L;
+}
+
+// pinned copy of the preparation job table (allocated on first use: model creation stays host-only)
+nrx_status model_pinned(nrx_model *m) {
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (m->pinned_jobs) return NRX_OK;
+  if (hipHostMalloc(&m->pinned_jobs, sizeof(PrepJob) * m->jobs.size(), hipHostMallocDefault) != hipSuccess)
+    return fail(NRX_ERR_HIP, "hipHostMalloc failed");
+  memcpy(m->pinned_jobs, m->jobs.data(), sizeof(PrepJob) * m->jobs.size());
+  return NRX_OK;
+}
+
+template <typename T>
+nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *y, float *h_ls,
+                        float *llr, bool save, char *ws, hipStream_t st) {
+  nrx_status ps = model_pinned(m);
+  if (ps != NRX_OK) return ps;
+  if (plan_upload(const_cast<Plan *>(P), ws + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
+  HIPCHK(hipMemcpyAsync(ws + L.jobs, m->pinned_jobs, sizeof(PrepJob) * m->jobs.size(), hipMemcpyHostToDevice, st));
+  const Dev D = dev_tables(P, ws + L.meta);
+  T *wprep = (T *)(ws + L.wprep);
+  float *fields = (float *)(ws + L.fields);
+  launch_prep<T>(w, (const PrepJob *)(ws + L.jobs), (int)m->jobs.size(), m->prep_total, wprep, fields, st);
+  float2 *dmrs = (float2 *)(ws + L.dmrs);
+  float2 *pairs = (float2 *)(ws + L.pairs);
+  launch_dmrs(D.geo, P->n, dmrs, st);
+  launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
+  T *X = (T *)(ws + L.X);
+  launch_features<T>(D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, m->cfg.n_ant, m->cx, X,
+                     (float2 *)h_ls, st);
+
+  const int grid_conv = std::min<int>((int)P->ct.size(), num_cu());
+  const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), num_cu() * 4);
+  auto buf = [&](size_t off) { return (T *)(ws + off); };
+
+  ConvArgs<T> a{};
+  a.geo = D.geo;
+  a.tiles = D.ct;
+  a.n_tiles = (int)P->ct.size();
+  // StateInit
+  a.src0 = X; a.c0 = m->cx; a.src1 = nullptr; a.c1 = 0;
+  a.w = wprep + m->conv_in.prep;
+  a.bias = w + m->conv_in.b;
+  a.pe = fields + m->conv_in.field;
+  a.out = buf(L.h[0]);
+  launch_conv<T>(a, EPI_STORE, CONV_MB, grid_conv, st);
+  const int C = m->cfg.n_blocks;
+  for (int i = 0; i < C; ++i) {
+    const BlockLayer &B = m->blocks[i];
+    T *h_in = buf(L.h[save ? i : 0]);
+    T *h_out = buf(L.h[save ? i + 1 : 0]);
+    T *abuf = buf(L.a[save ? i : 0]);
+    T *agg = nullptr;
+    if (B.mp_round >= 0) {
+      const int r = B.mp_round;
+      agg = buf(L.agg[save ? r : 0]);
+      MlpArgs<T> ma{};
+      ma.h = h_in;
+      ma.w1 = wprep + m->mp[r].p1;
+      ma.w2 = wprep + m->mp[r].p2;
+      ma.b1 = w + m->mp[r].b1;
+      ma.b2 = w + m->mp[r].b2;
+      ma.out = agg;
+      ma.save_m1 = save ? buf(L.m1[r]) : nullptr;
+      ma.geo = D.geo;
+      ma.tiles = D.mt;
+      ma.n_tiles = (int)P->mt.size();
+      launch_mp<T>(ma, grid_mlp, st);
+    }
+    ConvArgs<T> ca = a;
+    ca.src0 = h_in; ca.c0 = NRX_D;
+    ca.src1 = agg; ca.c1 = agg ? NRX_D : 0;
+    ca.w = wprep + B.a.prep;
+    ca.bias = w + B.a.b;
+    ca.pe = B.a.field >= 0 ? fields + B.a.field : nullptr;
+    ca.ln_g = w + B.g;
+    ca.ln_b = w + B.beta;
+    ca.out = abuf;
+    ca.save_z = save ? buf(L.z[i]) : nullptr;
+    ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
+    launch_conv<T>(ca, EPI_LN_RELU, CONV_MB, grid_conv, st);
+    ConvArgs<T> cb = a;
+    cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
+    cb.w = wprep + B.b.prep;
+    cb.bias = w + B.b.b;
+    cb.pe = nullptr;
+    cb.resid = h_in;
+    cb.out = h_out;
+    launch_conv<T>(cb, EPI_RESID, CONV_MB, grid_conv, st);
+  }
+  MlpArgs<T> ra{};
+  ra.h = buf(L.h[save ? C : 0]);
+  ra.w1 = wprep + m->ro.p1;
+  ra.b1 = w + m->ro.b1;
+  ra.b2 = w + m->ro.b2;
+  ra.w2f = w + m->ro.w2;
+  ra.save_m1 = save ? buf(L.q) : nullptr;
+  ra.llr = llr;
+  ra.m_max = m->cfg.m_max;
+  ra.geo = D.geo;
+  ra.tiles = D.rt;
+  ra.n_tiles = (int)P->rt.size();
+  launch_readout<T>(ra, grid_mlp, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+}  // namespace
+
+extern "C" size_t nrx_workspace_bytes(nrx_model *m, const nrx_slot_desc *slots, int32_t n, int32_t save_acts) {
+  if (!m) return 0;
+  Plan *P;
+  if (get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P) != NRX_OK) return 0;
+  return fwd_layout(m, P, save_acts != 0).total;
+}
+
+extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *y,
+                                  float *h_ls, float *llr, int32_t save_acts, void *ws, size_t ws_bytes,
+                                  hipStream_t st) {
+  if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const FwdLayout L = fwd_layout(m, P, save_acts != 0);
+  if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  if (m->cfg.precision == NRX_FP32)
+    s = forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, st);
+  else
+    s = forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, st);
+  if (s == NRX_OK && save_acts) {
+    std::lock_guard<std::mutex> lk(m->mu);
+    m->saved_ws = ws;
+    m->saved_plan = P;
+  }
+  return s;
+}
+
+extern "C" nrx_status nrx_backward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                   const float *dllr, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
+  (void)m; (void)w; (void)slots; (void)n; (void)dllr; (void)dw; (void)ws; (void)ws_bytes; (void)st;
+  return fail(NRX_ERR_UNSUPPORTED, "nrx_backward is not available in this build yet");
+}
+
+// --------------------------------------------------------- model-free calls --
+
+namespace {
+struct FrontLayout {
+  size_t meta, dmrs, pairs, h, total;
+};
+FrontLayout front_layout(const Plan *P, bool need_h) {
+  FrontLayout L;
+  size_t o = 0;
+  L.meta = o; o = align256(o + P->meta_bytes);
+  L.dmrs = o; o = align256(o + (size_t)P->dmrs_total * 8);
+  L.pairs = o; o = align256(o + (size_t)P->pairs_total * 8);
+  int64_t hel = 0;
+  for (auto &g : P->geo) hel += (int64_t)g.S * 14 * g.U * g.B;
+  L.h = o; o = align256(o + (need_h ? (size_t)hel * 8 : 0));
+  L.total = o;
+  return L;
+}
+// internal LS estimates use a packed h layout: slot offsets are recomputed
+}  // namespace
+
+extern "C" size_t lmmse_workspace_bytes(const nrx_slot_desc *slots, int32_t n) {
+  Plan *P;
+  if (get_plan(slots, n, 16, 8, 0, &P) != NRX_OK) return 0;
+  return front_layout(P, true).total + align256(sizeof(SlotGeo) * (size_t)n);
+}
+
+static nrx_status ls_into(const Plan *P, const FrontLayout &L, const float *y, float *h, const SlotGeo *geo_h,
+                          char *ws, hipStream_t st) {
+  const Dev D = dev_tables(P, ws + L.meta);
+  float2 *dmrs = (float2 *)(ws + L.dmrs);
+  float2 *pairs = (float2 *)(ws + L.pairs);
+  launch_dmrs(D.geo, P->n, dmrs, st);
+  launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
+  launch_features<float>(geo_h ? geo_h : D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, 16,
+                         0, (float *)nullptr, (float2 *)h, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_ls_estimate(const nrx_slot_desc *slots, int32_t n, const float *y, float *h, void *ws,
+                                      size_t ws_bytes, hipStream_t st) {
+  if (!y || !h || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, 16, 8, 0, &P);
+  if (s != NRX_OK) return s;
+  const FrontLayout L = front_layout(P, false);
+  if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  if (plan_upload(P, (char *)ws + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
+  return ls_into(P, L, y, h, nullptr, (char *)ws, st);
+}
+
+namespace {
+// geometry copy whose h offsets point into a packed internal buffer
+struct PackedGeo {
+  std::mutex mu;
+  std::map<const Plan *, void *> pinned;
+};
+PackedGeo g_packed;
+}  // namespace
+
+extern "C" nrx_status lmmse_demap(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y, const float *h,
+                                  const float *n0dev, float *llr, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
+  Plan *P;
+  nrx_status s = get_plan(slots, n, 16, m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const FrontLayout L = front_layout(P, h == nullptr);
+  const size_t need = L.total + align256(sizeof(SlotGeo) * (size_t)n);
+  if (ws_bytes < need) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  char *w = (char *)ws;
+  if (plan_upload(P, w + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
+  const Dev D = dev_tables(P, w + L.meta);
+  const SlotGeo *geo = D.geo;
+  const float *hh = h;
+  if (!h) {
+    // packed internal estimate: a geometry copy with h offsets into the workspace buffer
+    void *pg;
+    {
+      std::lock_guard<std::mutex> lk(g_packed.mu);
+      auto it = g_packed.pinned.find(P);
+      if (it == g_packed.pinned.end()) {
+        if (hipHostMalloc(&pg, sizeof(SlotGeo) * n, hipHostMallocDefault) != hipSuccess)
+          return fail(NRX_ERR_HIP, "hipHostMalloc failed");
+        SlotGeo *gp = (SlotGeo *)pg;
+        int64_t off = 0;
+        for (int i = 0; i < n; ++i) {
+          gp[i] = P->geo[i];
+          gp[i].h_off = off;
+          off += (int64_t)gp[i].S * 14 * gp[i].U * gp[i].B;
+        }
+        g_packed.pinned[P] = pg;
+      } else {
+        pg = it->second;
+      }
+    }
+    SlotGeo *gdev = (SlotGeo *)(w + L.total);
+    HIPCHK(hipMemcpyAsync(gdev, pg, sizeof(SlotGeo) * n, hipMemcpyHostToDevice, st));
+    s = ls_into(P, L, y, (float *)(w + L.h), gdev, w, st);
+    if (s != NRX_OK) return s;
+    geo = gdev;
+    hh = (const float *)(w + L.h);
+  }
+  launch_lmmse(geo, nullptr, P->n, P->max_re, m_max, (const float2 *)y, (const float2 *)hh, n0dev, llr, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" size_t nrx_bce_workspace_bytes(const nrx_slot_desc *slots, int32_t n, int32_t m_max) {
+  Plan *P;
+  if (get_plan(slots, n, 16, m_max, 0, &P) != NRX_OK) return 0;
+  const int64_t nb = (P->max_ute + 255) / 256;
+  return align256(P->meta_bytes) + align256((size_t)n * nb * 16);
+}
+
+extern "C" nrx_status nrx_bce(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *llr,
+                              const uint8_t *bits, float *dllr, double *loss, unsigned long long *nerr, void *ws,
+                              size_t ws_bytes, hipStream_t st) {
+  if (!llr || !bits || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
+  Plan *P;
+  nrx_status s = get_plan(slots, n, 16, m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const int64_t nb = (P->max_ute + 255) / 256;
+  const size_t need = align256(P->meta_bytes) + align256((size_t)n * nb * 16);
+  if (ws_bytes < need) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  if (P->n_data_bits <= 0) return fail(NRX_ERR_SHAPE, "no data bits");
+  char *w = (char *)ws;
+  if (plan_upload(P, w, st) != NRX_OK) return NRX_ERR_HIP;
+  const Dev D = dev_tables(P, w);
+  launch_bce(D.geo, nullptr, P->n, P->max_ute, m_max, llr, bits, dllr, (double *)(w + align256(P->meta_bytes)),
+             (int)nb, loss, nerr, 1.0 / (double)P->n_data_bits, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_adam(float *w, const float *g, float *mm, float *v, int64_t n, int64_t step, float lr,
+                               float beta1, float beta2, float eps, hipStream_t st) {
+  if (!w || !g || !mm || !v || n <= 0 || step < 1) return fail(NRX_ERR_INVALID, "bad Adam arguments");
+  const float c1 = 1.f - (float)pow((double)beta1, (double)step);
+  const float c2 = 1.f - (float)pow((double)beta2, (double)step);
+  launch_adam(w, g, mm, v, n, lr, beta1, beta2, eps, c1, c2, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+// ---------------------------------------------------------------- simulator --
+
+namespace {
+struct SimLayout {
+  size_t meta, dmrs, fd, graw, gmix, total;
+};
+SimLayout sim_layout(const Plan *P) {
+  SimLayout L;
+  size_t o = 0;
+  L.meta = o; o = align256(o + P->meta_bytes);
+  L.dmrs = o; o = align256(o + (size_t)P->dmrs_total * 8);
+  L.fd = o; o = align256(o + (size_t)P->n * 5 * 4);
+  L.graw = o; o = align256(o + (size_t)P->tap_off.back() * 8);
+  L.gmix = o; o = align256(o + (size_t)P->tap_off.back() * 8);
+  L.total = o;
+  return L;
+}
+nrx_status sim_check(const nrx_sim_config *c) {
+  if (!c) return fail(NRX_ERR_INVALID, "null sim config");
+  if (c->n_taps < 1 || c->n_taps > 32) return fail(NRX_ERR_SHAPE, "n_taps %d outside 1..32", c->n_taps);
+  if (c->tap_spacing_ns < 0 || c->tap_decay_ns <= 0.f) return fail(NRX_ERR_SHAPE, "bad delay profile");
+  if (c->rho < 0.f || c->rho >= 1.f) return fail(NRX_ERR_SHAPE, "rho outside [0, 1)");
+  if (c->scs_khz <= 0 || c->doppler_max_hz < 0.f) return fail(NRX_ERR_SHAPE, "bad scs / doppler");
+  return NRX_OK;
+}
+}  // namespace
+
+extern "C" size_t slot_sim_workspace_bytes(const nrx_sim_config *cfg, const nrx_slot_desc *slots, int32_t n) {
+  if (sim_check(cfg) != NRX_OK) return 0;
+  Plan *P;
+  if (get_plan(slots, n, 16, 8, cfg->n_taps, &P) != NRX_OK) return 0;
+  return sim_layout(P).total;
+}
+
+extern "C" nrx_status slot_sim(const nrx_sim_config *cfg, uint64_t seed, uint32_t batch_index,
+                               const nrx_slot_desc *slots, int32_t n, int32_t m_max, float *y, float *h_true,
+                               uint8_t *bits, float *snr_db, float *n0, void *ws, size_t ws_bytes, hipStream_t st) {
+  nrx_status s = sim_check(cfg);
+  if (s != NRX_OK) return s;
+  if (!y || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
+  Plan *P;
+  s = get_plan(slots, n, 16, m_max, cfg->n_taps, &P);
+  if (s != NRX_OK) return s;
+  const SimLayout L = sim_layout(P);
+  if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  char *w = (char *)ws;
+  if (plan_upload(P, w + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
+  const Dev D = dev_tables(P, w + L.meta);
+  float2 *dmrs = (float2 *)(w + L.dmrs);
+  launch_dmrs(D.geo, P->n, dmrs, st);
+  SimParams sp;
+  sp.n_taps = cfg->n_taps;
+  sp.tap_spacing_ns = cfg->tap_spacing_ns;
+  sp.scs_khz = cfg->scs_khz;
+  sp.tap_decay_ns = cfg->tap_decay_ns;
+  sp.doppler_max_hz = cfg->doppler_max_hz;
+  sp.rho = cfg->rho;
+  sp.snr_lo = cfg->snr_db_lo;
+  sp.snr_hi = cfg->snr_db_hi;
+  sp.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  sp.key1 = (uint32_t)(seed >> 32);
+  sp.batch = batch_index;
+  launch_sim(sp, D.geo, D.tap_off, P->n, P->max_re, P->max_ubl, m_max, dmrs, (float2 *)(w + L.graw),
+             (float2 *)(w + L.gmix), (float *)(w + L.fd), (float2 *)y, (float2 *)h_true, bits, snr_db, n0,
+             P->max_bits, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}

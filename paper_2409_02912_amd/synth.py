@@ -1,0 +1,57 @@
+"""Seeded synthetic inputs shared by tests, benchmark and training driver.
+
+Holds no receiver arithmetic: only random draws (network weights, batch shapes)
+and the workload configurations.  Slots themselves come from slot_sim.
+"""
+import numpy as np
+
+# Workloads (Rayleigh tapped-delay stand-ins for the paper's channels; see the design notes).
+WORKLOADS = {
+    # small single-UE case the oracle finishes in seconds
+    "c1": dict(n_slots=16, n_prb=4, n_ant=4, n_ue=1, m=2, n_taps=3, decay_ns=100.0, doppler=0.0, rho=0.0,
+               snr=(10.0, 10.0), d=128, n_blocks=2, n_rounds=0),
+    "c2": dict(n_slots=32, n_prb=273, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=100.0, rho=0.0,
+               snr=(0.0, 20.0), d=128, n_blocks=6, n_rounds=2),
+    "c3": dict(n_slots=64, n_prb=106, n_ant=16, n_ue=4, m=6, n_taps=24, decay_ns=305.02, doppler=0.0, rho=0.5,
+               snr=(5.0, 30.0), d=128, n_blocks=8, n_rounds=3),
+    "c5": dict(n_slots=64, n_prb=106, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
+               snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
+    # headline workload: 273 PRB, 4 UEs, 8 antennas, 16-QAM, batch 32
+    "m": dict(n_slots=32, n_prb=273, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
+              snr=(10.0, 10.0), d=128, n_blocks=6, n_rounds=2),
+}
+
+
+def he_weights(layout, seed, perturb=False):
+    """Flat fp32 weight vector: He-normal N(0, 2/fan_in) for conv/dense kernels (fan_in = all axes but the
+    last), zero biases, LN gamma 1 / beta 0.  perturb=True draws biases and LN parameters too (tests)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in layout:
+        n = int(np.prod(shape))
+        if len(shape) >= 2:
+            fan = int(np.prod(shape[:-1]))
+            v = rng.standard_normal(n) * np.sqrt(2.0 / fan)
+        elif name.endswith(".g"):
+            v = 1.0 + (0.1 * rng.standard_normal(n) if perturb else np.zeros(n))
+        else:
+            v = 0.1 * rng.standard_normal(n) if perturb else np.zeros(n)
+        parts.append(v)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def ragged_shapes(n_slots, seed, max_prb=273, ants=(4, 8, 16), mods=(2, 4, 6, 8)):
+    """Uneven batch: PRBs uniform in 4..max_prb, UEs 1..4, antennas and modulation per slot."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_slots):
+        u = int(rng.integers(1, 5))
+        out.append(dict(n_prb=int(rng.integers(4, max_prb + 1)), n_ant=int(rng.choice(ants)), n_ue=u,
+                        bits=[int(rng.choice(mods))] * u, slot_number=i % 20))
+    return out
+
+
+def uniform_shapes(w, n_slots=None, n_prb=None):
+    n = n_slots or w["n_slots"]
+    return [dict(n_prb=n_prb or w["n_prb"], n_ant=w["n_ant"], n_ue=w["n_ue"], bits=[w["m"]] * w["n_ue"],
+                 slot_number=i % 20) for i in range(n)]

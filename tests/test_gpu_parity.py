@@ -1,0 +1,179 @@
+"""GPU parity: every libnrx entry point against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from nrx_cases import (check_llr, log, oracle_batch, oracle_nrx, pack_bits, pack_complex, rel_err, sim_cfg_oracle,
+                       split_h, split_llr)
+from oracle import cgnn, nr, receiver
+from paper_2409_02912_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+L = pytest.importorskip("paper_2409_02912_amd.libnrx")
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda")
+
+
+def ws_tensor(nbytes):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+
+
+RAGGED = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 4], slot_number=3),
+          dict(n_prb=7, n_ant=8, n_ue=3, bits=[2, 4, 6], slot_number=7, n_id=5),
+          dict(n_prb=5, n_ant=8, n_ue=4, bits=[6, 6, 2, 4], slot_number=11, n_scid=1),
+          dict(n_prb=1, n_ant=2, n_ue=1, bits=[6], slot_number=19)]
+SIMCFG = dict(n_taps=12, decay_ns=487.42, doppler=100.0, rho=0.5, snr=(0.0, 20.0))
+
+
+def test_slot_sim_matches_oracle():
+    log("slot_sim: ragged 4 slots")
+    cfg_o = sim_cfg_oracle(SIMCFG)
+    ref = oracle_batch(RAGGED, cfg_o, 1234, 7, 6)
+    descs, sz = L.make_slots(RAGGED, 6)
+    cfg = L.sim_config(n_taps=12, tap_decay_ns=487.42, doppler_max_hz=100.0, rho=0.5, snr_db_lo=0, snr_db_hi=20)
+    y = torch.zeros(2 * sz["y"], dtype=torch.float32, device="cuda")
+    h = torch.zeros(2 * sz["h"], dtype=torch.float32, device="cuda")
+    bits = torch.zeros(sz["bits"], dtype=torch.uint8, device="cuda")
+    snr = torch.zeros(len(RAGGED), dtype=torch.float32, device="cuda")
+    n0 = torch.zeros(len(RAGGED), dtype=torch.float32, device="cuda")
+    ws = ws_tensor(L.slot_sim_workspace_bytes(cfg, descs))
+    L.slot_sim(cfg, 1234, 7, descs, 6, y, ws, h_true=h, bits=bits, snr_db=snr, n0=n0)
+    torch.cuda.synchronize()
+    assert np.array_equal(bits.cpu().numpy(), pack_bits(ref))
+    assert np.allclose(snr.cpu().numpy(), [r["snr_db"] for r in ref], atol=1e-4)
+    assert np.allclose(n0.cpu().numpy(), [r["n0"] for r in ref], rtol=1e-5)
+    yc = y.cpu().numpy().view(np.complex64)
+    hc = split_h(h.cpu().numpy().view(np.complex64), RAGGED)
+    o = 0
+    for i, r in enumerate(ref):
+        n = r["y"].size
+        assert rel_err(yc[o:o + n].reshape(r["y"].shape), r["y"]) < 2e-5, i
+        assert rel_err(hc[i], r["h"]) < 2e-5, i
+        o += n
+
+
+def _upload_batch(shapes, ref):
+    y = dev(pack_complex([r["y32"] for r in ref]))
+    return y
+
+
+def test_ls_estimate_matches_oracle():
+    log("ls_estimate: ragged 4 slots")
+    ref = oracle_batch(RAGGED, sim_cfg_oracle(SIMCFG), 99, 0, 6)
+    descs, sz = L.make_slots(RAGGED, 6)
+    y = _upload_batch(RAGGED, ref)
+    h = torch.zeros(2 * sz["h"], dtype=torch.float32, device="cuda")
+    ws = ws_tensor(L.lmmse_workspace_bytes(descs))
+    L.nrx_ls_estimate(descs, y, h, ws)
+    torch.cuda.synchronize()
+    hc = split_h(h.cpu().numpy().view(np.complex64), RAGGED)
+    for i, r in enumerate(ref):
+        assert rel_err(hc[i], receiver.ls_estimate(r["y32"], r["desc"])) < 1e-6, i
+
+
+@pytest.mark.parametrize("internal_ls", [False, True])
+def test_lmmse_matches_oracle(internal_ls):
+    log(f"lmmse_demap: ragged 4 slots, internal_ls={internal_ls}")
+    ref = oracle_batch(RAGGED, sim_cfg_oracle(SIMCFG), 5, 1, 6)
+    shapes = [dict(s, n0=r["n0_32"]) for s, r in zip(RAGGED, ref)]
+    descs, sz = L.make_slots(shapes, 6)
+    y = _upload_batch(RAGGED, ref)
+    hls = [receiver.ls_estimate(r["y32"], r["desc"]) for r in ref]
+    h = None if internal_ls else dev(pack_complex(hls))
+    llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+    ws = ws_tensor(L.lmmse_workspace_bytes(descs))
+    L.lmmse_demap(descs, 6, y, llr, ws, h=h)
+    torch.cuda.synchronize()
+    got = split_llr(llr.cpu().numpy(), RAGGED, 6)
+    for i, r in enumerate(ref):
+        exp = receiver.lmmse_demap(r["y32"], hls[i], r["n0_32"], r["desc"], 6)
+        for u in range(exp.shape[0]):
+            assert rel_err(got[i][u], exp[u]) < 1e-5, (i, u)
+        assert np.all(got[i][:, list(nr.DMRS_SYMBOLS)] == 0)
+
+
+def _nrx_case(shapes, net, prec, seed, tol, m_max):
+    log(f"nrx_forward: prec={prec} B={net.B} C={net.C} R={net.R} slots={len(shapes)}")
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
+    w = synth.he_weights(cgnn.layout(net), seed, perturb=True)
+    exp = oracle_nrx(w, net, ref_slots)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+    try:
+        descs, sz = L.make_slots(shapes, m_max)
+        y = _upload_batch(shapes, ref_slots)
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        hls = torch.zeros(2 * sz["h"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        L.nrx_forward(model, dev(w), descs, y, llr, ws, h_ls=hls)
+        torch.cuda.synchronize()
+        got = split_llr(llr.cpu().numpy(), shapes, m_max)
+        worst = 0
+        for i in range(len(shapes)):
+            worst = max(worst, check_llr(got[i], exp[i], tol))
+        log(f"  worst relative error {worst:.2e}")
+        hc = split_h(hls.cpu().numpy().view(np.complex64), shapes)
+        for i, r in enumerate(ref_slots):
+            assert rel_err(hc[i], receiver.ls_estimate(r["y32"], r["desc"])) < 1e-6
+    finally:
+        L.nrx_model_destroy(model)
+
+
+C1 = [dict(n_prb=4, n_ant=4, n_ue=1, bits=[2], slot_number=i) for i in range(16)]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_forward_single_ue(prec, tol):
+    _nrx_case(C1, cgnn.NetConfig(4, 128, 2, 0, 2), prec, 0, tol, 2)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_forward_ragged_multi_ue(prec, tol):
+    shapes = [s for s in RAGGED if s["n_ant"] <= 8]
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6)
+
+
+def test_bce_and_adam_match_oracle():
+    log("nrx_bce / nrx_adam")
+    shapes = RAGGED[:3]
+    ref = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 11, 0, 6)
+    descs, sz = L.make_slots(shapes, 6)
+    rng = np.random.default_rng(0)
+    llr_np = (3 * rng.standard_normal(sz["llr"])).astype(np.float32)
+    llr = dev(llr_np)
+    bits = dev(pack_bits(ref))
+    dllr = torch.zeros_like(llr)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nerr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = ws_tensor(L.nrx_bce_workspace_bytes(descs, 6))
+    L.nrx_bce(descs, 6, llr, bits, dllr, loss, nerr, ws)
+    torch.cuda.synchronize()
+    parts = split_llr(llr_np.astype(np.float64), shapes, 6)
+    tot, n, errs, grads = 0.0, 0, 0, []
+    for i, r in enumerate(ref):
+        lab, msk = cgnn.bit_labels_grid(r["bits"], r["desc"].n_sc, 6)
+        valid = msk * (np.arange(6) < np.array(r["desc"].bits_per_sym)[:, None, None, None])
+        tot += cgnn.bce_terms(parts[i], lab, valid).sum()
+        n += valid.sum()
+        errs += int((((parts[i] > 0) != (lab > 0.5)) * valid).sum())
+        grads.append((lab, valid))
+    assert abs(loss.item() - tot / n) <= 1e-12 * abs(tot / n)
+    assert int(nerr.item()) == errs
+    g = split_llr(dllr.cpu().numpy().astype(np.float64), shapes, 6)
+    for i in range(len(ref)):
+        lab, valid = grads[i]
+        assert rel_err(g[i], cgnn.bce_grad(parts[i], lab, valid, n)) < 1e-6
+    # Adam
+    wv = rng.standard_normal(1000).astype(np.float32)
+    gv = rng.standard_normal(1000).astype(np.float32)
+    mv = (0.1 * rng.standard_normal(1000)).astype(np.float32)
+    vv = np.abs(rng.standard_normal(1000)).astype(np.float32)
+    tw, tg, tm, tv = dev(wv), dev(gv), dev(mv), dev(vv)
+    L.nrx_adam(tw, tg, tm, tv, 3, lr=1e-3)
+    torch.cuda.synchronize()
+    ew, em, ev = cgnn.adam_step(wv.astype(np.float64), gv, mv, vv, 3)
+    assert np.allclose(tw.cpu().numpy(), ew, rtol=0, atol=1e-6)
+    assert np.allclose(tm.cpu().numpy(), em, rtol=1e-6, atol=1e-7)
+    assert np.allclose(tv.cpu().numpy(), ev, rtol=1e-6, atol=1e-7)
