@@ -43,6 +43,10 @@ class SimConfig(ctypes.Structure):
                 ("snr_db_hi", ctypes.c_float), ("scs_khz", ctypes.c_int32)]
 
 
+# torch must be loaded first: it ships its own HIP runtime (SONAME libamdhip64.so.7), and libnrx must bind
+# to that same runtime so that device pointers and streams created by torch are valid in the library.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2409_02912_amd/build.py "
                       "(the receiver has no fallback path)")
