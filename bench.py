@@ -1,0 +1,227 @@
+"""Throughput of the NRX forward pass on one MI355X.
+
+A step is one nrx_forward call (LS + interpolation, StateInit, CGNN iterations,
+readout, masking) over a batch of synthetic PUSCH slots already resident in
+HBM.  The headline workload is 273 PRB x 14 symbols, 4 UEs, 8 BS antennas,
+16-QAM, batch 32, CGNN width 128 / 6 blocks / 2 message-passing rounds; the
+timed precision is BF16 with the FP32 pass timed beside it at the same weights
+and slots, and the bit error rates of both and of LS + LMMSE reported.
+
+Prints one JSON line.  Only 1 GPU is supported.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NRX slots/s & REs/s at 273 PRB, 4 UE: BF16/FP8 vs FP32 at matched BER"
+PEAKS = {"bf16": 2.5e15, "fp32": 157.3e12, "fp8": 5.0e15}
+
+
+def flops_per_row(B, d, C, R, m_max):
+    """Algorithmic FLOPs per (UE, RE) row of the CGNN forward (multiply-add = 2)."""
+    mpb = [(r * C) // R for r in range(R)]
+    f = 2 * 9 * (4 * B + 2) * d                                   # StateInit
+    for i in range(C):
+        f += 2 * 9 * ((2 * d + 2) if i in mpb else d) * d         # conv_a
+        f += 2 * 9 * d * d                                        # conv_b
+    f += R * 2 * (2 * d * d)                                      # message MLPs
+    f += 2 * d * d + 2 * d * m_max                                # readout
+    return f
+
+
+def cpu_baseline(w, weights, net_args, budget_s):
+    """Times the FP64 oracle (LS + CGNN forward) on whole slots of the same workload."""
+    import numpy as np
+    from oracle import cgnn, receiver, slot_sim
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    net = cgnn.NetConfig(*net_args)
+    W = cgnn.unflatten(weights.astype(np.float64), net)
+    cfg = slot_sim.SimConfig(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
+                             rho=w["rho"], snr_db_lo=w["snr"][0], snr_db_hi=w["snr"][1])
+    n, t_total = 0, 0.0
+    while n < 1 or (t_total < budget_s and n < 4):
+        d = slot_sim.SlotDesc(w["n_prb"], w["n_ant"], w["n_ue"], [w["m"]] * w["n_ue"], slot_number=n)
+        r = slot_sim.simulate_slot(0, 0, n, cfg, d, w["m"])
+        t0 = time.perf_counter()
+        h = receiver.ls_estimate(r["y"], d)
+        cgnn.forward(W, net, r["y"], h, d.bits_per_sym)
+        t_total += time.perf_counter() - t0
+        n += 1
+    return {"value": n / t_total, "unit": "slots/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} slot(s) of {w['n_prb']} PRB x 14 x {w['n_ue']} UE x {w['n_ant']} ant, "
+                      f"fp64 numpy LS + CGNN forward, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="m")
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the NRX batch is data-parallel over slots with no exchange, "
+              "and multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_02912_amd import libnrx as L
+    from paper_2409_02912_amd import synth
+    from oracle import cgnn  # layout names only (weights are drawn by synth)
+
+    w = synth.WORKLOADS[args.workload]
+    shapes = synth.uniform_shapes(w)
+    m_max = w["m"]
+    descs, sz = L.make_slots(shapes, m_max)
+    n_slots = len(shapes)
+    net_args = (w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max)
+    layout = cgnn.layout(cgnn.NetConfig(*net_args))
+    trained = os.path.exists(args.weights)
+    weights = np.load(args.weights) if trained else synth.he_weights(layout, 0)
+    dw = torch.from_numpy(weights).cuda()
+
+    # synthetic slots resident in HBM
+    cfg = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
+                       snr_db_lo=w["snr"][0], snr_db_hi=w["snr"][1])
+    y = torch.empty(2 * sz["y"], dtype=torch.float32, device="cuda")
+    bits = torch.empty(sz["bits"], dtype=torch.uint8, device="cuda")
+    n0 = torch.empty(n_slots, dtype=torch.float32, device="cuda")
+    sws = torch.empty(L.slot_sim_workspace_bytes(cfg, descs), dtype=torch.uint8, device="cuda")
+    L.slot_sim(cfg, 0, 0, descs, m_max, y, sws, bits=bits, n0=n0)
+    del sws
+
+    results = {}
+    llrs = {}
+    for prec, name in ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32")):
+        model = L.nrx_model_create(*net_args, prec)
+        ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        steps = args.steps if name == "bf16" else args.fp32_steps
+        warm = args.warmup if name == "bf16" else 1
+        for _ in range(warm):
+            L.nrx_forward(model, dw, descs, y, llr, ws)
+        torch.cuda.synchronize()
+        L.nrx_profile_enable(model, True)
+        for c in range(len(L.KERNEL_CLASSES)):
+            L.nrx_profile_read(model, c, reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            L.nrx_forward(model, dw, descs, y, llr, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kern = {}
+        for c, cname in enumerate(L.KERNEL_CLASSES):
+            t, n = L.nrx_profile_read(model, c)
+            kern[cname] = {"ms_per_launch": t / max(n, 1), "launches_per_step": n / steps}
+        L.nrx_profile_enable(model, False)
+        results[name] = {"ms_per_step": ms, "kernels": kern}
+        llrs[name] = llr
+        # batch-1 latency (the real-time regime: no inter-slot batching)
+        d1, s1 = L.make_slots(shapes[:1], m_max)
+        ws1 = torch.empty(L.nrx_workspace_bytes(model, d1), dtype=torch.uint8, device="cuda")
+        l1 = torch.zeros(s1["llr"], dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            L.nrx_forward(model, dw, d1, y, l1, ws1)
+        torch.cuda.synchronize()
+        reps = 20 if name == "bf16" else 3
+        e0.record()
+        for _ in range(reps):
+            L.nrx_forward(model, dw, d1, y, l1, ws1)
+        e1.record()
+        torch.cuda.synchronize()
+        results[name]["batch1_ms"] = e0.elapsed_time(e1) / reps
+        del ws, ws1
+        L.nrx_model_destroy(model)
+
+    # bit errors: NRX (both precisions) and the LS + LMMSE judge on the same slots
+    bws = torch.empty(L.nrx_bce_workspace_bytes(descs, m_max), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nerr = torch.zeros(1, dtype=torch.int64, device="cuda")
+    n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in shapes)
+    ber = {}
+    for name, l in llrs.items():
+        L.nrx_bce(descs, m_max, l, bits, None, loss, nerr, bws)
+        torch.cuda.synchronize()
+        ber[name] = nerr.item() / n_bits
+    lws = torch.empty(L.lmmse_workspace_bytes(descs), dtype=torch.uint8, device="cuda")
+    llm = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.lmmse_demap(descs, m_max, y, llm, lws, n0=n0)
+    torch.cuda.synchronize()
+    lmmse_ms = (time.perf_counter() - t0) * 1e3
+    L.nrx_bce(descs, m_max, llm, bits, None, loss, nerr, bws)
+    torch.cuda.synchronize()
+    ber["lmmse"] = nerr.item() / n_bits
+    b32 = ber["fp32"]
+    tol = max(0.05 * b32, 3 * math.sqrt(max(b32 * (1 - b32), 1e-30) / n_bits))
+    rel_llr = (torch.linalg.vector_norm(llrs["bf16"] - llrs["fp32"]) /
+               torch.linalg.vector_norm(llrs["fp32"])).item()
+
+    S = 12 * w["n_prb"]
+    ms = results["bf16"]["ms_per_step"]
+    slots_s = n_slots / (ms * 1e-3)
+    fpr = flops_per_row(*net_args)
+    rows = S * 14 * w["n_ue"] * n_slots
+    # roofline of the dominant kernel: the residual-block 3x3 conv (128 -> 128 channels)
+    cb = results["bf16"]["kernels"]["conv_b"]["ms_per_launch"]
+    conv_flops = rows * 2 * 9 * w["d"] * w["d"]
+    achieved = conv_flops / (cb * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": slots_s,
+        "unit": "slots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{w['n_prb']} PRB x 14 sym, {w['n_ue']} UE, {w['n_ant']} ant, "
+                               f"{2 ** w['m']}-QAM, batch {n_slots} slots",
+                   "n_prb": w["n_prb"], "n_ue": w["n_ue"], "n_ant": w["n_ant"], "qam": 2 ** w["m"],
+                   "batch_slots": n_slots, "cgnn": {"d": w["d"], "blocks": w["n_blocks"], "mp_rounds": w["n_rounds"]},
+                   "weights": "trained (config-5 recipe)" if trained else "seeded He-init (untrained)"},
+        "res_per_s": slots_s * S * 14,
+        "tflops": fpr * rows / (ms * 1e-3) / 1e12,
+        "fp32": {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
+                 "ms_per_step": results["fp32"]["ms_per_step"]},
+        "speedup_bf16_vs_fp32": results["fp32"]["ms_per_step"] / ms,
+        "batch1_latency_ms": {"bf16": results["bf16"]["batch1_ms"], "fp32": results["fp32"]["batch1_ms"]},
+        "ber": {**ber, "n_bits": n_bits, "matched": abs(ber["bf16"] - b32) <= tol, "tolerance": tol},
+        "llr_rel_err_bf16_vs_fp32": rel_llr,
+        "lmmse_ms": lmmse_ms,
+        "kernels_bf16": results["bf16"]["kernels"],
+        "kernels_fp32": results["fp32"]["kernels"],
+        "roofline": {"bound": "mfma", "kernel": "conv3x3_kernel (residual conv_b, bf16)", "achieved": achieved / 1e12,
+                     "peak": PEAKS["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"],
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

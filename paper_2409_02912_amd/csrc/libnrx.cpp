@@ -258,6 +258,13 @@ struct nrx_model {
   int64_t prep_elems = 0, field_elems = 0, prep_total = 0;
   void *pinned_jobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
+  // per-class event timing (diagnostics)
+  bool profile = false;
+  struct Ev { int cls; hipEvent_t a, b; };
+  std::vector<Ev> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[NRX_K_NCLASS] = {0};
+  int64_t prof_n[NRX_K_NCLASS] = {0};
   // last save_acts forward (for nrx_backward)
   const void *saved_ws = nullptr;
   const Plan *saved_plan = nullptr;
@@ -381,6 +388,8 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
 
 extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
   if (!m) return fail(NRX_ERR_INVALID, "null model");
+  for (auto &e : m->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+  for (auto e : m->pool) (void)hipEventDestroy(e);
   if (m->pinned_jobs) (void)hipHostFree(m->pinned_jobs);
   delete m;
   return NRX_OK;
@@ -445,6 +454,30 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   return L;
 }
 
+// Brackets a launch with events when profiling is on.
+struct ProfMark {
+  nrx_model *m;
+  int cls;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  static hipEvent_t get(nrx_model *m) {
+    if (!m->pool.empty()) { hipEvent_t e = m->pool.back(); m->pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  ProfMark(nrx_model *mm, int c, hipStream_t s) : m(mm), cls(c), st(s) {
+    if (!m->profile) return;
+    a = get(m); b = get(m);
+    (void)hipEventRecord(a, st);
+  }
+  ~ProfMark() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    m->pending.push_back({cls, a, b});
+  }
+};
+
 // pinned copy of the preparation job table (allocated on first use: model creation stays host-only)
 nrx_status model_pinned(nrx_model *m) {
   std::lock_guard<std::mutex> lk(m->mu);
@@ -465,14 +498,17 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   const Dev D = dev_tables(P, ws + L.meta);
   T *wprep = (T *)(ws + L.wprep);
   float *fields = (float *)(ws + L.fields);
-  launch_prep<T>(w, (const PrepJob *)(ws + L.jobs), (int)m->jobs.size(), m->prep_total, wprep, fields, st);
   float2 *dmrs = (float2 *)(ws + L.dmrs);
   float2 *pairs = (float2 *)(ws + L.pairs);
-  launch_dmrs(D.geo, P->n, dmrs, st);
-  launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
   T *X = (T *)(ws + L.X);
-  launch_features<T>(D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, m->cfg.n_ant, m->cx, X,
-                     (float2 *)h_ls, st);
+  {
+    ProfMark pm(m, NRX_K_FRONTEND, st);
+    launch_prep<T>(w, (const PrepJob *)(ws + L.jobs), (int)m->jobs.size(), m->prep_total, wprep, fields, st);
+    launch_dmrs(D.geo, P->n, dmrs, st);
+    launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
+    launch_features<T>(D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, m->cfg.n_ant, m->cx,
+                       X, (float2 *)h_ls, st);
+  }
 
   const int grid_conv = std::min<int>((int)P->ct.size(), num_cu());
   const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), num_cu() * 4);
@@ -488,7 +524,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   a.bias = w + m->conv_in.b;
   a.pe = fields + m->conv_in.field;
   a.out = buf(L.h[0]);
-  launch_conv<T>(a, EPI_STORE, CONV_MB, grid_conv, st);
+  {
+    ProfMark pm(m, NRX_K_CONV_IN, st);
+    launch_conv<T>(a, EPI_STORE, CONV_MB, grid_conv, st);
+  }
   const int C = m->cfg.n_blocks;
   for (int i = 0; i < C; ++i) {
     const BlockLayer &B = m->blocks[i];
@@ -510,6 +549,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ma.geo = D.geo;
       ma.tiles = D.mt;
       ma.n_tiles = (int)P->mt.size();
+      ProfMark pm(m, NRX_K_MP, st);
       launch_mp<T>(ma, grid_mlp, st);
     }
     ConvArgs<T> ca = a;
@@ -523,7 +563,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ca.out = abuf;
     ca.save_z = save ? buf(L.z[i]) : nullptr;
     ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
-    launch_conv<T>(ca, EPI_LN_RELU, CONV_MB, grid_conv, st);
+    {
+      ProfMark pm(m, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, st);
+      launch_conv<T>(ca, EPI_LN_RELU, CONV_MB, grid_conv, st);
+    }
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
@@ -531,7 +574,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     cb.pe = nullptr;
     cb.resid = h_in;
     cb.out = h_out;
-    launch_conv<T>(cb, EPI_RESID, CONV_MB, grid_conv, st);
+    {
+      ProfMark pm(m, NRX_K_CONV_B, st);
+      launch_conv<T>(cb, EPI_RESID, CONV_MB, grid_conv, st);
+    }
   }
   MlpArgs<T> ra{};
   ra.h = buf(L.h[save ? C : 0]);
@@ -545,7 +591,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   ra.geo = D.geo;
   ra.tiles = D.rt;
   ra.n_tiles = (int)P->rt.size();
-  launch_readout<T>(ra, grid_mlp, st);
+  {
+    ProfMark pm(m, NRX_K_READOUT, st);
+    launch_readout<T>(ra, grid_mlp, st);
+  }
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }
@@ -578,6 +627,33 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
     m->saved_plan = P;
   }
   return s;
+}
+
+extern "C" nrx_status nrx_profile_enable(nrx_model *m, int32_t enable) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  std::lock_guard<std::mutex> lk(m->mu);
+  m->profile = enable != 0;
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_profile_read(nrx_model *m, int32_t cls, double *ms_total, int64_t *launches, int32_t reset) {
+  if (!m || cls < 0 || cls >= NRX_K_NCLASS) return fail(NRX_ERR_INVALID, "bad model or class");
+  std::lock_guard<std::mutex> lk(m->mu);
+  for (auto &e : m->pending) {
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    m->prof_ms[e.cls] += ms;
+    m->prof_n[e.cls] += 1;
+    m->pool.push_back(e.a);
+    m->pool.push_back(e.b);
+  }
+  m->pending.clear();
+  if (ms_total) *ms_total = m->prof_ms[cls];
+  if (launches) *launches = m->prof_n[cls];
+  if (reset)
+    for (int i = 0; i < NRX_K_NCLASS; ++i) { m->prof_ms[i] = 0; m->prof_n[i] = 0; }
+  return NRX_OK;
 }
 
 extern "C" nrx_status nrx_backward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,

@@ -74,6 +74,8 @@ _SIGS = {
     "slot_sim_workspace_bytes": (_sz, [ctypes.POINTER(SimConfig), _DESC, _i32]),
     "slot_sim": (_i32, [ctypes.POINTER(SimConfig), _u64, _u32, _DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _sz, _vp]),
+    "nrx_profile_enable": (_i32, [_vp, _i32]),
+    "nrx_profile_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "nrx_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -244,3 +246,19 @@ def slot_sim(cfg, seed, batch_index, slots, m_max, y, ws, h_true=None, bits=None
 
 def nrx_last_error():
     return _lib.nrx_last_error().decode()
+
+
+# ------------------------------------------------------------ diagnostics ---
+
+NRX_K_FRONTEND, NRX_K_CONV_IN, NRX_K_CONV_A, NRX_K_CONV_A_MP, NRX_K_CONV_B, NRX_K_MP, NRX_K_READOUT = range(7)
+KERNEL_CLASSES = ("frontend", "conv_in", "conv_a", "conv_a_mp", "conv_b", "mp", "readout")
+
+
+def nrx_profile_enable(model, enable=True):
+    _check(_lib.nrx_profile_enable(model, int(enable)))
+
+
+def nrx_profile_read(model, cls, reset=False):
+    ms, n = ctypes.c_double(), _i64()
+    _check(_lib.nrx_profile_read(model, cls, ctypes.byref(ms), ctypes.byref(n), int(reset)))
+    return float(ms.value), int(n.value)
