@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -108,12 +110,17 @@ def main():
 
     results = {}
     llrs = {}
-    for prec, name in ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32")):
+    passes = ((L.NRX_BF16, "bf16"),) if args.bf16_only else ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32"))
+    for prec, name in passes:
         model = L.nrx_model_create(*net_args, prec)
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         steps = args.steps if name == "bf16" else args.fp32_steps
         warm = args.warmup if name == "bf16" else 1
+        if not args.no_autotune:
+            L.nrx_autotune(model, dw, descs, y, llr, ws)
+        results.setdefault("variants", {})[name] = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0]
+                                                    for c in L.CONV_CLASSES}
         for _ in range(warm):
             L.nrx_forward(model, dw, descs, y, llr, ws)
         torch.cuda.synchronize()
@@ -134,6 +141,10 @@ def main():
         L.nrx_profile_enable(model, False)
         results[name] = {"ms_per_step": ms, "kernels": kern}
         llrs[name] = llr
+        if args.bf16_only:
+            results[name]["batch1_ms"] = None
+            L.nrx_model_destroy(model)
+            continue
         # batch-1 latency (the real-time regime: no inter-slot batching)
         d1, s1 = L.make_slots(shapes[:1], m_max)
         ws1 = torch.empty(L.nrx_workspace_bytes(model, d1), dtype=torch.uint8, device="cuda")
@@ -171,10 +182,16 @@ def main():
     L.nrx_bce(descs, m_max, llm, bits, None, loss, nerr, bws)
     torch.cuda.synchronize()
     ber["lmmse"] = nerr.item() / n_bits
-    b32 = ber["fp32"]
-    tol = max(0.05 * b32, 3 * math.sqrt(max(b32 * (1 - b32), 1e-30) / n_bits))
-    rel_llr = (torch.linalg.vector_norm(llrs["bf16"] - llrs["fp32"]) /
-               torch.linalg.vector_norm(llrs["fp32"])).item()
+    if "fp32" in llrs:
+        b32 = ber["fp32"]
+        tol = max(0.05 * b32, 3 * math.sqrt(max(b32 * (1 - b32), 1e-30) / n_bits))
+        ber["matched"] = abs(ber["bf16"] - b32) <= tol
+        ber["tolerance"] = tol
+        rel_llr = (torch.linalg.vector_norm(llrs["bf16"] - llrs["fp32"]) /
+                   torch.linalg.vector_norm(llrs["fp32"])).item()
+    else:
+        rel_llr = None
+    ber["n_bits"] = n_bits
 
     S = 12 * w["n_prb"]
     ms = results["bf16"]["ms_per_step"]
@@ -205,19 +222,20 @@ def main():
                    "weights": "trained (config-5 recipe)" if trained else "seeded He-init (untrained)"},
         "res_per_s": slots_s * S * 14,
         "tflops": fpr * rows / (ms * 1e-3) / 1e12,
-        "fp32": {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
-                 "ms_per_step": results["fp32"]["ms_per_step"]},
-        "speedup_bf16_vs_fp32": results["fp32"]["ms_per_step"] / ms,
-        "batch1_latency_ms": {"bf16": results["bf16"]["batch1_ms"], "fp32": results["fp32"]["batch1_ms"]},
-        "ber": {**ber, "n_bits": n_bits, "matched": abs(ber["bf16"] - b32) <= tol, "tolerance": tol},
+        "ber": ber,
         "llr_rel_err_bf16_vs_fp32": rel_llr,
         "lmmse_ms": lmmse_ms,
+        "conv_variants": results.get("variants"),
         "kernels_bf16": results["bf16"]["kernels"],
-        "kernels_fp32": results["fp32"]["kernels"],
+        "batch1_latency_ms": {k: results[k]["batch1_ms"] for k in llrs},
         "roofline": {"bound": "mfma", "kernel": "conv3x3_kernel (residual conv_b, bf16)", "achieved": achieved / 1e12,
                      "peak": PEAKS["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"],
                      "traffic": None},
     }
+    if "fp32" in results:
+        out["fp32"] = {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
+                       "ms_per_step": results["fp32"]["ms_per_step"], "kernels": results["fp32"]["kernels"]}
+        out["speedup_bf16_vs_fp32"] = results["fp32"]["ms_per_step"] / ms
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)

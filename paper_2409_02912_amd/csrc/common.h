@@ -43,8 +43,9 @@ __device__ __forceinline__ void st16(void *p, v16 v) { *reinterpret_cast<v16 *>(
 // MFMA on one 16x16 output block.  D layout (all variants): lane l holds rows
 // 4*(l/16)+i, i = 0..3, of column l%16.
 //   bf16 16x16x32: lane l holds A[l%16][8*(l/16) .. +7] and B[8*(l/16) .. +7][l%16]
-//   fp32 16x16x4 : lane l holds A[l%16][l/16] and B[l/16][l%16]; four k-steps are
-//                  packed in one 16-byte fragment (k = 4*q + l/16, q = 0..3)
+//   fp32 16x16x4 : lane l holds A[l%16][l/16] and B[l/16][l%16]; a 16-byte fragment
+//                  (channels 4*(l/16) .. +3 of a 16-channel chunk) feeds four k-steps,
+//                  step q taking channel 4*(l/16) + q, so chunks keep natural order
 __device__ __forceinline__ f32x4_t mfma_bf16(v16 a, v16 b, f32x4_t c) {
   bf16x8_t av, bv;
   __builtin_memcpy(&av, &a, 16);
@@ -69,11 +70,9 @@ template <> struct mma<bf16_t> {
   __device__ static __forceinline__ f32x4_t run(v16 a, v16 b, f32x4_t c) { return mfma_bf16(a, b, c); }
 };
 
-// Physical position of logical channel k inside a 64-byte K chunk so that each
-// lane's fragment is one contiguous 16-byte load (identity for bf16).
-template <typename T> __host__ __device__ __forceinline__ int kperm(int k);
-template <> __host__ __device__ __forceinline__ int kperm<bf16_t>(int k) { return k; }
-template <> __host__ __device__ __forceinline__ int kperm<float>(int k) { return (k & 3) * 4 + (k >> 2); }
+// LDS rows of 64 bytes hold four 16-byte pieces; piece p of row h sits in slot
+// p ^ swz(h) so that 16 consecutive rows read at the same piece hit distinct banks.
+__host__ __device__ __forceinline__ int swz(int h) { return (h >> 1) & 3; }
 
 // Output-channel permutation used by every MFMA GEMM here: n-block nb, column j
 // of the MFMA output holds channel 8*j + nb, so a lane owns 8 consecutive

@@ -25,17 +25,25 @@ struct ConvArgs {
   int n_tiles;
 };
 
+struct ConvVariant {
+  int mb;     // MFMA m-blocks (16 rows) per wave: tile = 64 * mb rows
+  int occ;    // waves per SIMD the kernel is built for
+  int pref;   // weights prefetched one tap ahead
+};
+#define NRX_CONV_VARIANTS 4
+extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
+
 template <typename T>
-void launch_conv(const ConvArgs<T> &a, int epi, int mb, int grid, hipStream_t st);
+void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream_t st);
 
 // Weight preparation: fp32 master -> MFMA operand layouts and PE fields.
 struct PrepJob {
-  int32_t kind;        // 0 conv, 1 dense, 2 PE field, 3 conv transposed+flipped (dgrad)
+  int32_t kind;        // 0 conv, 1 dense, 2 PE field, 3 conv transposed+flipped (dgrad), 4 narrow dense
   int32_t cin_real;    // input channels present in the master tensor (conv: without PE)
   int32_t cin_total;   // input channels of the master tensor (incl. PE channels)
   int32_t n_chunks;    // K chunks of the prepped operand
   int32_t cin_first;   // first master input channel used (dgrad slices)
-  int32_t pad;
+  int32_t n_out;       // output columns of the master tensor (narrow dense: m_max)
   int64_t src;         // element offset into the master weights
   int64_t dst;         // element offset into the prepped (T) or field (fp32) buffer
   int64_t count;       // prepped elements of this job
@@ -59,9 +67,8 @@ void launch_features(const SlotGeo *geo, const int64_t *re_base, int n_slots, in
 template <typename T>
 struct MlpArgs {
   const T *h;               // [rows][128]
-  const T *w1, *w2;         // prepped dense [chunk][nb][16][KC] (w2 unused by the readout)
+  const T *w1, *w2;         // prepped dense [chunk][nb][16][KC]; readout w2: [chunk][16][KC]
   const float *b1, *b2;     // [128] / [m_max]
-  const float *w2f;         // readout second layer, fp32 master [128][m_max]
   T *out;                   // MP: aggregated messages [rows][128]
   T *save_m1;               // MP/readout hidden activations (training) or null
   float *llr;               // readout output

@@ -8,13 +8,15 @@
 // block of memory.
 //
 // Work decomposition
-//   workgroup = 4 waves, one tile of 64*MB consecutive rows of one slot
+//   workgroup = 4 waves, one tile of 64*MB consecutive rows of one slot; the
+//               tile shape (MB, waves per SIMD, prefetch) is a compiled variant
 //   wave      = 16*MB rows x all 128 output channels (MB x 8 MFMA blocks)
 //   K loop    = input-channel chunks of 64 bytes; per chunk the halo block is
-//               staged global -> registers -> LDS (double buffered, next chunk
-//               loaded while the current one is consumed) and reused by all
-//               nine taps; weights go global -> VGPRs directly (prefetched one
-//               tap ahead), since every wave needs all 128 output columns.
+//               copied global -> LDS by buffer DMA (double buffered, the next
+//               chunk in flight while the current one is consumed) and reused by
+//               all nine taps; weights go global -> VGPRs directly (optionally
+//               prefetched one tap ahead), since every wave needs all 128 output
+//               columns.  LDS rows are XOR-swizzled in 16-byte pieces.
 //   t edges   = taps reaching t = -1 or t = 14 read a zero LDS row;
 //               s edges = halo rows outside the slot are staged as zeros.
 //   epilogue  = bias (+ positional-encoding field) -> store, or LayerNorm over
@@ -26,7 +28,7 @@
 
 namespace {
 
-constexpr int PITCH = 80;  // bytes per LDS row: 64 data + 16 pad
+constexpr int ROWB = 64;   // bytes per LDS row (one 64-byte K chunk of one activation row)
 
 __host__ __device__ constexpr int halo_rows_max(int tile_rows) {
   int best = 0;
@@ -34,17 +36,19 @@ __host__ __device__ constexpr int halo_rows_max(int tile_rows) {
     int v = ((tile_rows - 1) / (14 * U) + 4) * 14 * U;
     best = v > best ? v : best;
   }
-  return best;
+  return (best + 15) / 16 * 16;
 }
 
-template <typename T, int MB, int EPI>
-__global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <typename T, int MB, int EPI, int OCC, bool PREF>
+__global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
   constexpr int TILE = 64 * MB;
-  constexpr int HMAX = halo_rows_max(TILE);
-  constexpr int ZROW = HMAX;                     // all-zero row
-  constexpr int KC = 64 / (int)sizeof(T);        // channels per chunk
-  constexpr int UNITS = (HMAX * 4 + 255) / 256;  // 16-byte staging units per thread
-  __shared__ __align__(16) unsigned char lds[2][(HMAX + 1) * PITCH];
+  constexpr int HMAX = halo_rows_max(TILE);       // rows staged per chunk, multiple of 16
+  constexpr int ZROW = HMAX;                       // all-zero row
+  constexpr int KC = 64 / (int)sizeof(T);          // channels per chunk
+  constexpr int NINS = HMAX / 16;                  // 1 KB DMA instructions per chunk
+  __shared__ __align__(16) unsigned char lds[2][(HMAX + 1) * ROWB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -52,16 +56,21 @@ __global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
   const int lr = lane & 15;   // MFMA row (A) / column (B, D) index
   const int lk = lane >> 4;   // MFMA k-group (A, B) / row-group (D)
 
-  if (tid < 2 * (PITCH / 16)) {
+  if (tid < 8) {
     v16 z = {{0, 0, 0, 0}};
-    st16(&lds[tid / (PITCH / 16)][ZROW * PITCH + (tid % (PITCH / 16)) * 16], z);
+    st16(&lds[tid >> 2][ZROW * ROWB + (tid & 3) * 16], z);
   }
 
   const int cin = a.c0 + a.c1;
   const int nch = cin / KC;
   int buf = 0;
 
-  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
+  // give the workgroups of one XCD consecutive tiles (their halos overlap and
+  // then hit in that XCD's L2).  gridDim.x is a multiple of 8.
+  const int G = gridDim.x;
+  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  for (int tile = lb; tile < a.n_tiles; tile += G) {
     const Tile tl = a.tiles[tile];
     const SlotGeo g = a.geo[tl.slot];
     const int U = g.U, S = g.S;
@@ -69,54 +78,38 @@ __global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
     const int s_first = tl.row0 / rps;
     const int s_last = (tl.row0 + tl.nrows - 1) / rps;
     const int halo = (s_last - s_first + 3) * rps;
-    const int64_t g0 = g.row_base + (int64_t)(s_first - 1) * rps;   // global row of halo row 0
+    const int rel0 = (s_first - 1) * rps;         // slot-relative row of halo row 0
 
     // per-lane A-row geometry for each m-block
     int hc[MB], tt[MB];
-    bool rv[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
       int r = wave * 16 * MB + mb * 16 + lr;
-      rv[mb] = r < tl.nrows;
       int R = tl.row0 + r;
       int s = R / rps;
       int t = (R - s * rps) / U;
-      tt[mb] = t;
-      hc[mb] = R - (s_first - 1) * rps;
+      tt[mb] = r < tl.nrows ? t : -1;            // -1 marks rows past the tile
+      hc[mb] = R - rel0;
     }
 
-    v16 stg[UNITS];
-    auto stage_load = [&](int c) {
+    // Halo staging by buffer -> LDS DMA: rows outside the slot fall outside the
+    // buffer range and read as zero (the conv's zero padding in s).
+    auto stage = [&](int c, int b) {
       const T *src;
       int cs, coff;
       if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
       else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
+      const T *base = src + g.row_base * cs + coff;
+      const int nrec = S * rps * cs * (int)sizeof(T);
+      __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, nrec, 0x00020000);
 #pragma unroll
-      for (int q = 0; q < UNITS; ++q) {
-        int unit = tid + q * 256;
-        int h = unit >> 2, piece = unit & 3;
-        int s = s_first - 1 + h / rps;
-        v16 v = {{0, 0, 0, 0}};
-        if (h < halo && s >= 0 && s < S)
-          v = ld16(src + (g0 + h) * cs + coff + piece * (16 / (int)sizeof(T)));
-        stg[q] = v;
-      }
-    };
-    auto stage_store = [&](int b) {
-#pragma unroll
-      for (int q = 0; q < UNITS; ++q) {
-        int unit = tid + q * 256;
-        int h = unit >> 2, piece = unit & 3;
-        if (h < halo) {
-          unsigned char *row = &lds[b][h * PITCH];
-          if constexpr (sizeof(T) == 2) {
-            st16(row + piece * 16, stg[q]);
-          } else {
-            // fp32: logical channel 4*piece+e goes to position kperm = 4*e + piece
-            float *rf = reinterpret_cast<float *>(row);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) rf[4 * e + piece] = __uint_as_float(stg[q].w[e]);
-          }
+      for (int j = 0; j < (NINS + 3) / 4; ++j) {
+        const int ins = wave + 4 * j;
+        if (ins < NINS && ins * 16 < halo) {
+          const int h = ins * 16 + (lane >> 2);
+          const int piece = (lane & 3) ^ swz(h);
+          const uint32_t voff = (uint32_t)((rel0 + h) * cs * (int)sizeof(T) + piece * 16);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)&lds[b][ins * 16 * ROWB], 16, voff, 0, 0, 0);
         }
       }
     };
@@ -127,9 +120,9 @@ __global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    stage_load(0);
+    stage(0, buf ^ 1);
     buf ^= 1;
-    stage_store(buf);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     // weight fragment pointer for (chunk, tap, nb): prepped [chunk][tap][nb][16][KC]
@@ -141,35 +134,43 @@ __global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
     };
 
     v16 bcur[8], bnxt[8];
-    load_b(0, 0, bcur);
+    if constexpr (PREF) load_b(0, 0, bcur);
     for (int c = 0; c < nch; ++c) {
-      if (c + 1 < nch) stage_load(c + 1);
-      const unsigned char *lb = &lds[buf][lk * 16];
-#pragma unroll
+      if (c + 1 < nch) stage(c + 1, buf ^ 1);
+      const unsigned char *lds_c = &lds[buf][0];
+      // rolled: unrolling lets the scheduler hoist weight loads of later taps
+      // and exceed the register budget of the 2-waves/SIMD variants
+#pragma unroll 1
       for (int tap = 0; tap < 9; ++tap) {
-        if (tap < 8) load_b(c, tap + 1, bnxt);
-        else if (c + 1 < nch) load_b(c + 1, 0, bnxt);
+        if constexpr (PREF) {
+          if (tap < 8) load_b(c, tap + 1, bnxt);
+          else if (c + 1 < nch) load_b(c + 1, 0, bnxt);
+        } else {
+          load_b(c, tap, bcur);
+        }
         const int di = tap / 3 - 1, dj = tap % 3 - 1;
         const int off = di * rps + dj * U;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
-          bool ok = rv[mb] && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
-          int row = ok ? hc[mb] + off : ZROW;
-          v16 af = ld16(lb + row * PITCH);
+          const bool ok = tt[mb] >= 0 && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
+          const int row = ok ? hc[mb] + off : ZROW;
+          const v16 af = ld16(lds_c + row * ROWB + ((lk ^ swz(row)) << 4));
 #pragma unroll
           for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = mma<T>::run(af, bcur[nb], acc[mb][nb]);
         }
+        if constexpr (PREF) {
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) bcur[nb] = bnxt[nb];
+          for (int nb = 0; nb < 8; ++nb) bcur[nb] = bnxt[nb];
+        }
       }
       if (c + 1 < nch) {
         buf ^= 1;
-        stage_store(buf);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
       }
     }
 
-    // ---------------------------------------------------------- epilogue --
+// ---------------------------------------------------------- epilogue --
     const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
     float bias[8];
 #pragma unroll
@@ -228,16 +229,32 @@ __global__ __launch_bounds__(256, 1) void conv3x3_kernel(ConvArgs<T> a) {
 
 }  // namespace
 
+// Compiled shapes: rows per wave (16*MB), waves per SIMD, B-operand prefetch.
+// The autotuner in the host library times them per layer kind.
+const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
+    {4, 1, 1},   // 256-row tiles, 1 wave/SIMD, weights prefetched one tap ahead
+    {4, 2, 0},   // 256-row tiles, 2 waves/SIMD, no prefetch
+    {2, 2, 1},   // 128-row tiles, 2 waves/SIMD, prefetch
+    {2, 2, 0},   // 128-row tiles, 2 waves/SIMD, no prefetch
+};
+
 template <typename T>
-void launch_conv(const ConvArgs<T> &a, int epi, int mb, int grid, hipStream_t st) {
+void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream_t st) {
   dim3 blk(256);
-#define NRX_CONV_CASE(MBV, E)                                              \
-  if (mb == MBV && epi == E) {                                             \
-    hipLaunchKernelGGL((conv3x3_kernel<T, MBV, E>), dim3(grid), blk, 0, st, a); \
-    return;                                                                \
+#define NRX_CONV_CASE(V, MBV, OCCV, PF)                                                        \
+  if (variant == V) {                                                                         \
+    if (epi == EPI_STORE)                                                                     \
+      hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_STORE, OCCV, PF>), dim3(grid), blk, 0, st, a); \
+    else if (epi == EPI_LN_RELU)                                                              \
+      hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_RELU, OCCV, PF>), dim3(grid), blk, 0, st, a); \
+    else                                                                                      \
+      hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_RESID, OCCV, PF>), dim3(grid), blk, 0, st, a); \
+    return;                                                                                   \
   }
-  NRX_CONV_CASE(7, EPI_STORE) NRX_CONV_CASE(7, EPI_LN_RELU) NRX_CONV_CASE(7, EPI_RESID)
-  NRX_CONV_CASE(4, EPI_STORE) NRX_CONV_CASE(4, EPI_LN_RELU) NRX_CONV_CASE(4, EPI_RESID)
+  NRX_CONV_CASE(0, 4, 1, true)
+  NRX_CONV_CASE(1, 4, 2, false)
+  NRX_CONV_CASE(2, 2, 2, true)
+  NRX_CONV_CASE(3, 2, 2, false)
 #undef NRX_CONV_CASE
 }
 

@@ -7,11 +7,11 @@
 // MFMA (hidden activations pass through LDS to change from the output to the
 // operand layout), and the cross-UE sum is read back from LDS.
 //
-// ReadoutLLRs (Sec. II-A): l = W2 ReLU(W1 h + b1) + b2 with d -> d -> m_max; the
-// first layer runs on MFMA, the second (m_max <= 8 outputs) as per-lane partial
-// dot products over the lane's 8 channels reduced across the 16 lanes of a row.
-// Outputs j >= m_u are written as 0 (masking, Sec. III) in the [u][t][s][j]
-// layout.
+// ReadoutLLRs (Sec. II-A): l = W2 ReLU(W1 h + b1) + b2 with d -> d -> m_max; both
+// layers run on MFMA (the second as one 16-column block, outputs j >= m_max
+// having zero weights), the hidden layer passing through LDS.  Outputs
+// j >= m_u are written as 0 (masking, Sec. III) in the [u][t][s][j] layout, lane
+// j of a row writing output j.
 #include "common.h"
 #include "internal.h"
 
@@ -24,15 +24,7 @@ constexpr int MLP_MB = 2;
 template <typename T>
 __device__ __forceinline__ v16 afrag_global(const T *row, int c, int lk) {
   constexpr int KC = 64 / (int)sizeof(T);
-  if constexpr (sizeof(T) == 2) {
-    return ld16(row + c * KC + lk * 8);
-  } else {
-    // fp32: the lane needs logical channels 4q + lk, q = 0..3
-    v16 v;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v.w[q] = __float_as_uint(row[c * KC + 4 * q + lk]);
-    return v;
-  }
+  return ld16(row + c * KC + lk * (KC / 4));
 }
 
 // acc[mb][nb] += A(rows) x W for a 128-deep K; A comes from `afn(mb, c)`.
@@ -59,23 +51,15 @@ __device__ __forceinline__ void gemm128(f32x4_t (&acc)[MLP_MB][8], const T *w, i
   }
 }
 
-// LDS staging of a 128-row x 128-channel tile in operand layout: row pitch of
-// 128 elements + 16 bytes, K chunks contiguous, channels permuted with kperm.
+// LDS staging of a 128-row x 128-channel tile in operand layout: natural
+// channel order, row pitch of 128 elements + 16 bytes.
 template <typename T>
 struct OpTile {
   static constexpr int KC = 64 / (int)sizeof(T);
   static constexpr int PITCHB = NRX_D * (int)sizeof(T) + 16;
   __device__ static __forceinline__ void put8(unsigned char *lds, int row, int ch0, const float *v) {
     T *r = reinterpret_cast<T *>(lds + row * PITCHB);
-    if constexpr (sizeof(T) == 2) {
-      pack8<T>::store(r + ch0, v);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int ch = ch0 + e;
-        r[(ch / KC) * KC + kperm<T>(ch % KC)] = v[e];
-      }
-    }
+    pack8<T>::store(r + ch0, v);
   }
   __device__ static __forceinline__ v16 frag(const unsigned char *lds, int row, int c, int lk) {
     return ld16(lds + row * PITCHB + c * 64 + lk * 16);
@@ -157,15 +141,14 @@ __global__ __launch_bounds__(256) void mp_kernel(MlpArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
+  constexpr int KC = 64 / (int)sizeof(T);
+  constexpr int NCH = NRX_D / KC;
+  __shared__ __align__(16) unsigned char lds[MLP_ROWS * OpTile<T>::PITCHB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int ch0 = 8 * lr;
   const int M = a.m_max;
-  float w2[8][8];
-#pragma unroll
-  for (int nb = 0; nb < 8; ++nb)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) w2[nb][j] = j < M ? a.w2f[(ch0 + nb) * M + j] : 0.f;
+  const float b2 = lr < M ? a.b2[lr] : 0.f;
 
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const Tile tl = a.tiles[tile];
@@ -177,7 +160,7 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
       r = r < tl.nrows ? r : 0;
       return afrag_global<T>(a.h + (gbase + r) * NRX_D, c, lk);
     });
-    const int U = g.U, S = g.S;
+    // hidden layer -> LDS (operand layout) for the second GEMM
 #pragma unroll
     for (int mb = 0; mb < MLP_MB; ++mb)
 #pragma unroll
@@ -193,26 +176,39 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
 #pragma unroll
           for (int nb = 0; nb < 8; ++nb) q[nb] = bf2f(f2bf(q[nb]));
         }
-        const bool valid = r < tl.nrows;
-        if (a.save_m1 && valid) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, q);
-        float o[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          float p = 0.f;
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) p += q[nb] * w2[nb][j];
-          o[j] = row_sum16(p);
-        }
-        if (valid && lr == 0) {
-          const int R = tl.row0 + r;
-          const int s = R / (14 * U);
-          const int rem = R - s * 14 * U;
-          const int t = rem / U, u = rem - t * U;
-          const int mu = g.m[u];
-          float *dst = a.llr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
-          for (int j = 0; j < M; ++j) dst[j] = j < mu ? o[j] + a.b2[j] : 0.f;
-        }
+        OpTile<T>::put8(lds, r, ch0, q);
+        if (a.save_m1 && r < tl.nrows) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, q);
       }
+    __syncthreads();
+    // second layer: one 16-column MFMA block (outputs j < m_max, rest zero weights)
+    f32x4_t o[MLP_MB];
+#pragma unroll
+    for (int mb = 0; mb < MLP_MB; ++mb) o[mb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const v16 bf = ld16(a.w2 + (c * 16 + lr) * KC + lk * (KC / 4));
+#pragma unroll
+      for (int mb = 0; mb < MLP_MB; ++mb)
+        o[mb] = mma<T>::run(OpTile<T>::frag(lds, wave * 16 * MLP_MB + mb * 16 + lr, c, lk), bf, o[mb]);
+    }
+    const int U = g.U, S = g.S;
+    if (lr < M) {
+#pragma unroll
+      for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
+          if (r < tl.nrows) {
+            const int R = tl.row0 + r;
+            const int s = R / (14 * U);
+            const int rem = R - s * 14 * U;
+            const int t = rem / U, u = rem - t * U;
+            const int mu = a.geo[tl.slot].m[u];
+            a.llr[g.llr_off + (((int64_t)u * 14 + t) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
+          }
+        }
+    }
+    __syncthreads();   // LDS reads done before the next tile overwrites it
   }
 }
 

@@ -62,8 +62,14 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
     fields[J.dst + k] = acc;
     return;
   }
-  const int p = k % KC;
-  const int kl = sizeof(T) == 4 ? ((p & 3) * 4 + (p >> 2)) : p;   // inverse of kperm (an involution)
+  const int kl = k % KC;   // channel within the K chunk (natural order)
+  if (J.kind == 4) {
+    // narrow dense [chunk][16][KC]: column j = output j (zero beyond n_out)
+    const int j = (k / KC) % 16, chunk = k / (16 * KC);
+    const int c = chunk * KC + kl;
+    wprep[J.dst + k] = elem<T>::from_f(j < J.n_out ? w[J.src + (int64_t)c * J.n_out + j] : 0.f);
+    return;
+  }
   const int j = (k / KC) % 16, nb = (k / (16 * KC)) % 8;
   const int n = nperm(nb, j);
   float v = 0.f;

@@ -47,9 +47,10 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 namespace {
 
-constexpr int CONV_MB = 4;                 // conv tile = 64 * CONV_MB rows
-constexpr int CONV_TILE = 64 * CONV_MB;
 constexpr int MLP_TILE = 128;
+constexpr int N_TILE_SIZES = 2;            // conv tiles of 128 and 256 rows (MB = 2, 4)
+inline int tile_size_index(int mb) { return mb == 2 ? 0 : 1; }
+inline int tile_rows_of_index(int i) { return i == 0 ? 128 : 256; }
 
 struct TensorInfo {
   std::string name;
@@ -79,13 +80,13 @@ struct DenseLayer {
 struct Plan {
   int n = 0;
   std::vector<SlotGeo> geo;
-  std::vector<Tile> ct, mt, rt;
+  std::vector<Tile> ct[N_TILE_SIZES], mt, rt;
   std::vector<int64_t> pair_off, tap_off;
   int64_t rows = 0, max_rows = 0, max_re = 0, max_pairs = 0, max_ute = 0, max_bits = 0;
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
   // device table blob
-  size_t off_geo = 0, off_ct = 0, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
+  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
   ~Plan() {
@@ -154,8 +155,11 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
     g.dmrs_off = dm;
     P->geo.push_back(g);
     const int64_t rows = (int64_t)g.S * 14 * g.U;
-    for (int64_t r = 0; r < rows; r += CONV_TILE)
-      P->ct.push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(CONV_TILE, rows - r), 0});
+    for (int k = 0; k < N_TILE_SIZES; ++k) {
+      const int tr = tile_rows_of_index(k);
+      for (int64_t r = 0; r < rows; r += tr)
+        P->ct[k].push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(tr, rows - r), 0});
+    }
     const int mtr = (MLP_TILE / g.U) * g.U;
     for (int64_t r = 0; r < rows; r += mtr)
       P->mt.push_back(Tile{i, (int32_t)r, (int32_t)std::min<int64_t>(mtr, rows - r), 0});
@@ -186,7 +190,7 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->pairs_total = pr;
   size_t o = 0;
   P->off_geo = o; o = align256(o + sizeof(SlotGeo) * P->geo.size());
-  P->off_ct = o; o = align256(o + sizeof(Tile) * P->ct.size());
+  for (int k = 0; k < N_TILE_SIZES; ++k) { P->off_ct[k] = o; o = align256(o + sizeof(Tile) * P->ct[k].size()); }
   P->off_mt = o; o = align256(o + sizeof(Tile) * P->mt.size());
   P->off_rt = o; o = align256(o + sizeof(Tile) * P->rt.size());
   P->off_pair = o; o = align256(o + sizeof(int64_t) * P->pair_off.size());
@@ -195,7 +199,7 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->blob.assign(o, 0);
   char *b = P->blob.data();
   memcpy(b + P->off_geo, P->geo.data(), sizeof(SlotGeo) * P->geo.size());
-  memcpy(b + P->off_ct, P->ct.data(), sizeof(Tile) * P->ct.size());
+  for (int k = 0; k < N_TILE_SIZES; ++k) memcpy(b + P->off_ct[k], P->ct[k].data(), sizeof(Tile) * P->ct[k].size());
   memcpy(b + P->off_mt, P->mt.data(), sizeof(Tile) * P->mt.size());
   memcpy(b + P->off_rt, P->rt.data(), sizeof(Tile) * P->rt.size());
   memcpy(b + P->off_pair, P->pair_off.data(), sizeof(int64_t) * P->pair_off.size());
@@ -221,13 +225,19 @@ nrx_status plan_upload(Plan *P, char *dst, hipStream_t st) {
 
 struct Dev {
   const SlotGeo *geo;
-  const Tile *ct, *mt, *rt;
+  const Tile *ct[N_TILE_SIZES], *mt, *rt;
   const int64_t *pair_off, *tap_off;
 };
 
 Dev dev_tables(const Plan *P, char *ws) {
-  return Dev{(const SlotGeo *)(ws + P->off_geo), (const Tile *)(ws + P->off_ct), (const Tile *)(ws + P->off_mt),
-             (const Tile *)(ws + P->off_rt), (const int64_t *)(ws + P->off_pair), (const int64_t *)(ws + P->off_tap)};
+  Dev d;
+  d.geo = (const SlotGeo *)(ws + P->off_geo);
+  for (int k = 0; k < N_TILE_SIZES; ++k) d.ct[k] = (const Tile *)(ws + P->off_ct[k]);
+  d.mt = (const Tile *)(ws + P->off_mt);
+  d.rt = (const Tile *)(ws + P->off_rt);
+  d.pair_off = (const int64_t *)(ws + P->off_pair);
+  d.tap_off = (const int64_t *)(ws + P->off_tap);
+  return d;
 }
 
 int g_num_cu = 0;
@@ -258,6 +268,8 @@ struct nrx_model {
   int64_t prep_elems = 0, field_elems = 0, prep_total = 0;
   void *pinned_jobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
+  // conv kernel variant per layer class (autotuned; indices into kConvVariants)
+  int conv_variant[NRX_K_NCLASS] = {0, 0, 0, 0, 0, 0, 0};
   // per-class event timing (diagnostics)
   bool profile = false;
   struct Ev { int cls; hipEvent_t a, b; };
@@ -379,6 +391,12 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   m->ro.w1 = toff(m.get(), "readout.w1"); m->ro.b1 = toff(m.get(), "readout.b1");
   m->ro.w2 = toff(m.get(), "readout.w2"); m->ro.b2 = toff(m.get(), "readout.b2");
   dense_job(m->ro.w1, m->ro.p1);
+  {
+    m->ro.p2 = m->prep_elems;
+    PrepJob j{4, d, d, d / KC, 0, c.m_max, m->ro.w2, m->ro.p2, (int64_t)d * 16};
+    m->jobs.push_back(j);
+    m->prep_elems += j.count;
+  }
   // field jobs index a separate buffer; the prep kernel walks jobs in order over one index space
   m->prep_total = 0;
   for (auto &j : m->jobs) m->prep_total += j.count;
@@ -510,24 +528,30 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
                        X, (float2 *)h_ls, st);
   }
 
-  const int grid_conv = std::min<int>((int)P->ct.size(), num_cu());
   const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), num_cu() * 4);
+  // launch one conv of layer class cls with its selected variant
+  auto conv = [&](ConvArgs<T> ca, int epi, int cls) {
+    const int v = m->conv_variant[cls];
+    const ConvVariant &cv = kConvVariants[v];
+    const int ti = tile_size_index(cv.mb);
+    ca.tiles = D.ct[ti];
+    ca.n_tiles = (int)P->ct[ti].size();
+    int grid = std::min<int>(ca.n_tiles, num_cu() * cv.occ);
+    grid = (grid + 7) / 8 * 8;    // the kernel's XCD-aware order needs a multiple of 8
+    ProfMark pm(m, cls, st);
+    launch_conv<T>(ca, epi, v, grid, st);
+  };
   auto buf = [&](size_t off) { return (T *)(ws + off); };
 
   ConvArgs<T> a{};
   a.geo = D.geo;
-  a.tiles = D.ct;
-  a.n_tiles = (int)P->ct.size();
   // StateInit
   a.src0 = X; a.c0 = m->cx; a.src1 = nullptr; a.c1 = 0;
   a.w = wprep + m->conv_in.prep;
   a.bias = w + m->conv_in.b;
   a.pe = fields + m->conv_in.field;
   a.out = buf(L.h[0]);
-  {
-    ProfMark pm(m, NRX_K_CONV_IN, st);
-    launch_conv<T>(a, EPI_STORE, CONV_MB, grid_conv, st);
-  }
+  conv(a, EPI_STORE, NRX_K_CONV_IN);
   const int C = m->cfg.n_blocks;
   for (int i = 0; i < C; ++i) {
     const BlockLayer &B = m->blocks[i];
@@ -563,10 +587,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ca.out = abuf;
     ca.save_z = save ? buf(L.z[i]) : nullptr;
     ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
-    {
-      ProfMark pm(m, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, st);
-      launch_conv<T>(ca, EPI_LN_RELU, CONV_MB, grid_conv, st);
-    }
+    conv(ca, EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A);
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
@@ -574,17 +595,14 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     cb.pe = nullptr;
     cb.resid = h_in;
     cb.out = h_out;
-    {
-      ProfMark pm(m, NRX_K_CONV_B, st);
-      launch_conv<T>(cb, EPI_RESID, CONV_MB, grid_conv, st);
-    }
+    conv(cb, EPI_RESID, NRX_K_CONV_B);
   }
   MlpArgs<T> ra{};
   ra.h = buf(L.h[save ? C : 0]);
   ra.w1 = wprep + m->ro.p1;
   ra.b1 = w + m->ro.b1;
   ra.b2 = w + m->ro.b2;
-  ra.w2f = w + m->ro.w2;
+  ra.w2 = wprep + m->ro.p2;
   ra.save_m1 = save ? buf(L.q) : nullptr;
   ra.llr = llr;
   ra.m_max = m->cfg.m_max;
@@ -653,6 +671,102 @@ extern "C" nrx_status nrx_profile_read(nrx_model *m, int32_t cls, double *ms_tot
   if (launches) *launches = m->prof_n[cls];
   if (reset)
     for (int i = 0; i < NRX_K_NCLASS; ++i) { m->prof_ms[i] = 0; m->prof_n[i] = 0; }
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_conv_variant(nrx_model *m, int32_t cls, int32_t variant, int32_t *current,
+                                       int32_t *n_variants) {
+  if (!m || cls < NRX_K_CONV_IN || cls > NRX_K_CONV_B) return fail(NRX_ERR_INVALID, "bad model or class");
+  if (variant >= NRX_CONV_VARIANTS) return fail(NRX_ERR_INVALID, "variant %d out of range", variant);
+  if (variant >= 0) m->conv_variant[cls] = variant;
+  if (current) *current = m->conv_variant[cls];
+  if (n_variants) *n_variants = NRX_CONV_VARIANTS;
+  return NRX_OK;
+}
+
+namespace {
+const char *kClassName[NRX_K_NCLASS] = {"frontend", "conv_in", "conv_a", "conv_a_mp", "conv_b", "mp", "readout"};
+
+std::string tune_key(const nrx_model *m, const Plan *P, int cls) {
+  int maxu = 0;
+  for (auto &g : P->geo) maxu = std::max(maxu, g.U);
+  char b[256];
+  snprintf(b, sizeof b, "gfx950|%s|%s|rows=%lld|slots=%d|maxU=%d|B=%d", m->cfg.precision == NRX_FP32 ? "fp32" : "bf16",
+           kClassName[cls], (long long)P->rows, P->n, maxu, m->cfg.n_ant);
+  return b;
+}
+}  // namespace
+
+extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                   const float *y, float *llr, void *ws, size_t ws_bytes, const char *cache_path,
+                                   hipStream_t st) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const int classes[4] = {NRX_K_CONV_IN, NRX_K_CONV_A, NRX_K_CONV_A_MP, NRX_K_CONV_B};
+  // cached choices
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "r");
+    int found = 0, pick[NRX_K_NCLASS];
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        for (int c : classes) {
+          const std::string k = "\"key\": \"" + tune_key(m, P, c) + "\"";
+          const char *q = strstr(line, k.c_str());
+          const char *vq = strstr(line, "\"variant\": ");
+          if (q && vq) {
+            int v = atoi(vq + 11);
+            if (v >= 0 && v < NRX_CONV_VARIANTS) { pick[c] = v; found |= 1 << c; }
+          }
+        }
+      }
+      fclose(f);
+    }
+    bool all = true;
+    for (int c : classes) all = all && (found >> c & 1);
+    if (all) {
+      for (int c : classes) m->conv_variant[c] = pick[c];
+      return NRX_OK;
+    }
+  }
+  const bool prof_was = m->profile;
+  double best[NRX_K_NCLASS];
+  int bestv[NRX_K_NCLASS];
+  for (int c = 0; c < NRX_K_NCLASS; ++c) { best[c] = 1e30; bestv[c] = m->conv_variant[c]; }
+  for (int v = 0; v < NRX_CONV_VARIANTS; ++v) {
+    for (int c : classes) m->conv_variant[c] = v;
+    m->profile = false;
+    s = nrx_forward(m, w, slots, n, y, nullptr, llr, 0, ws, ws_bytes, st);   // warm-up
+    if (s != NRX_OK) { m->profile = prof_was; return s; }
+    m->profile = true;
+    for (int c = 0; c < NRX_K_NCLASS; ++c) nrx_profile_read(m, c, nullptr, nullptr, 1);
+    for (int r = 0; r < 2; ++r) {
+      s = nrx_forward(m, w, slots, n, y, nullptr, llr, 0, ws, ws_bytes, st);
+      if (s != NRX_OK) { m->profile = prof_was; return s; }
+    }
+    for (int c : classes) {
+      double ms;
+      int64_t cnt;
+      s = nrx_profile_read(m, c, &ms, &cnt, 0);
+      if (s != NRX_OK) { m->profile = prof_was; return s; }
+      if (cnt > 0 && ms / cnt < best[c]) { best[c] = ms / cnt; bestv[c] = v; }
+    }
+    nrx_profile_read(m, 0, nullptr, nullptr, 1);
+  }
+  m->profile = prof_was;
+  for (int c : classes) m->conv_variant[c] = bestv[c];
+  if (cache_path) {
+    FILE *f = fopen(cache_path, "a");
+    if (f) {
+      for (int c : classes)
+        if (best[c] < 1e30)
+          fprintf(f, "{\"key\": \"%s\", \"variant\": %d, \"ms\": %.4f}\n", tune_key(m, P, c).c_str(), bestv[c],
+                  best[c]);
+      fclose(f);
+    }
+  }
   return NRX_OK;
 }
 

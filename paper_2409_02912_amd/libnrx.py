@@ -76,6 +76,8 @@ _SIGS = {
                         _sz, _vp]),
     "nrx_profile_enable": (_i32, [_vp, _i32]),
     "nrx_profile_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
+    "nrx_autotune": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _sz, ctypes.c_char_p, _vp]),
+    "nrx_conv_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "nrx_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -262,3 +264,23 @@ def nrx_profile_read(model, cls, reset=False):
     ms, n = ctypes.c_double(), _i64()
     _check(_lib.nrx_profile_read(model, cls, ctypes.byref(ms), ctypes.byref(n), int(reset)))
     return float(ms.value), int(n.value)
+
+
+def nrx_autotune(model, w, slots, y, llr, ws, cache_path=None, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_autotune(model, _ptr(w), arr, n, _ptr(y), _ptr(llr), _ptr(ws), ws.numel() * ws.element_size(),
+                             cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def nrx_conv_variant(model, cls, variant=-1):
+    cur, nv = _i32(), _i32()
+    _check(_lib.nrx_conv_variant(model, cls, variant, ctypes.byref(cur), ctypes.byref(nv)))
+    return int(cur.value), int(nv.value)
+
+
+CONV_CLASSES = (NRX_K_CONV_IN, NRX_K_CONV_A, NRX_K_CONV_A_MP, NRX_K_CONV_B)
+
+
+def set_all_conv_variants(model, variant):
+    for c in CONV_CLASSES:
+        nrx_conv_variant(model, c, variant)

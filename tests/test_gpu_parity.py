@@ -95,8 +95,8 @@ def test_lmmse_matches_oracle(internal_ls):
         assert np.all(got[i][:, list(nr.DMRS_SYMBOLS)] == 0)
 
 
-def _nrx_case(shapes, net, prec, seed, tol, m_max):
-    log(f"nrx_forward: prec={prec} B={net.B} C={net.C} R={net.R} slots={len(shapes)}")
+def _nrx_case(shapes, net, prec, seed, tol, m_max, variants=(0,)):
+    log(f"nrx_forward: prec={prec} B={net.B} C={net.C} R={net.R} slots={len(shapes)} variants={variants}")
     ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
     w = synth.he_weights(cgnn.layout(net), seed, perturb=True)
     exp = oracle_nrx(w, net, ref_slots)
@@ -107,13 +107,16 @@ def _nrx_case(shapes, net, prec, seed, tol, m_max):
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         hls = torch.zeros(2 * sz["h"], dtype=torch.float32, device="cuda")
         ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
-        L.nrx_forward(model, dev(w), descs, y, llr, ws, h_ls=hls)
-        torch.cuda.synchronize()
-        got = split_llr(llr.cpu().numpy(), shapes, m_max)
-        worst = 0
-        for i in range(len(shapes)):
-            worst = max(worst, check_llr(got[i], exp[i], tol))
-        log(f"  worst relative error {worst:.2e}")
+        for v in variants:
+            L.set_all_conv_variants(model, v)
+            llr.zero_()
+            L.nrx_forward(model, dev(w), descs, y, llr, ws, h_ls=hls)
+            torch.cuda.synchronize()
+            got = split_llr(llr.cpu().numpy(), shapes, m_max)
+            worst = 0
+            for i in range(len(shapes)):
+                worst = max(worst, check_llr(got[i], exp[i], tol))
+            log(f"  conv variant {v}: worst relative error {worst:.2e}")
         hc = split_h(hls.cpu().numpy().view(np.complex64), shapes)
         for i, r in enumerate(ref_slots):
             assert rel_err(hc[i], receiver.ls_estimate(r["y32"], r["desc"])) < 1e-6
@@ -132,7 +135,7 @@ def test_nrx_forward_single_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6)
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=(0, 1, 2, 3))
 
 
 def test_bce_and_adam_match_oracle():
