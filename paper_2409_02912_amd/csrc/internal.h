@@ -5,7 +5,7 @@
 
 #include "common.h"
 
-enum { EPI_STORE = 0, EPI_LN_RELU = 1, EPI_RESID = 2 };
+enum { EPI_STORE = 0, EPI_LN_RELU = 1, EPI_RESID = 2, EPI_LN_BWD = 3 };
 
 template <typename T>
 struct ConvArgs {
@@ -18,8 +18,9 @@ struct ConvArgs {
   const float *ln_g, *ln_b; // [128] (EPI_LN_RELU)
   const T *resid;           // [rows][128] (EPI_RESID)
   T *out;                   // [rows][128]
-  T *save_z;                // pre-LN output (EPI_LN_RELU, training) or null
-  float *save_stats;        // [rows][2] mean, rstd (EPI_LN_RELU, training)
+  T *save_z;                // pre-LN output (EPI_LN_RELU, training; input of EPI_LN_BWD) or null
+  float *save_stats;        // [rows][2] mean, rstd (EPI_LN_RELU, training; input of EPI_LN_BWD)
+  float *ln_part;           // EPI_LN_BWD: per-workgroup [256] partial sums of dL/dgamma, dL/dbeta
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;
@@ -38,7 +39,8 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
 
 // Weight preparation: fp32 master -> MFMA operand layouts and PE fields.
 struct PrepJob {
-  int32_t kind;        // 0 conv, 1 dense, 2 PE field, 3 conv transposed+flipped (dgrad), 4 narrow dense
+  int32_t kind;        // 0 conv, 1 dense, 2 PE field, 3 conv transposed+flipped (dgrad), 4 narrow dense,
+                       // 5 dense transposed
   int32_t cin_real;    // input channels present in the master tensor (conv: without PE)
   int32_t cin_total;   // input channels of the master tensor (incl. PE channels)
   int32_t n_chunks;    // K chunks of the prepped operand
@@ -95,6 +97,61 @@ struct SimParams {
 void launch_sim(const SimParams &p, const SlotGeo *geo, const int64_t *tap_off, int n_slots, int64_t max_re,
                 int max_ubl, int m_max, const float2 *dmrs, float2 *g_raw, float2 *g_mix, float *fd_n0, float2 *y,
                 float2 *h_true, uint8_t *bits, float *snr_db, float *n0, int64_t max_bits, hipStream_t st);
+
+// Backward pass.
+template <typename T>
+struct WgradArgs {
+  const T *src0, *src1;     // layer input [rows][c0] / [rows][c1] (channel concatenation)
+  int c0, c1;
+  const T *dy;              // output gradient [rows][128]
+  const SlotGeo *geo;
+  const Tile *tiles;        // row tiles of the batch (partitioned among workgroups)
+  int n_tiles, n_part;      // n_part: row partitions (multiple of 8)
+  int n_taps, tap0;         // taps tap0 .. tap0 + n_taps - 1 (dense layers: 1 tap, the centre)
+  int n_slices;             // 128-channel input slices
+  float *partials;          // [n_part][n_taps * n_slices][128][128]
+};
+template <typename T>
+void launch_wgrad(const WgradArgs<T> &a, hipStream_t st);
+void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
+                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st);
+template <typename T>
+void launch_colsum(const T *dy, const SlotGeo *geo, int n_slots, float *partial, hipStream_t st);
+void launch_bias_pe(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
+                    float *dw, hipStream_t st);
+void launch_ln_reduce(const float *part, int n, int64_t g_off, int64_t b_off, float *dw, hipStream_t st);
+
+template <typename T>
+struct MpBwdArgs {
+  const T *dagg, *m1;       // [rows][128]
+  const T *w1t, *w2t;       // transposed prepped dense weights
+  T *dmsg, *dm1;            // outputs for the weight gradients
+  T *dh;                    // updated in place
+  const SlotGeo *geo;
+  const Tile *tiles;
+  int n_tiles;
+};
+template <typename T>
+void launch_mp_bwd(const MpBwdArgs<T> &a, int grid, hipStream_t st);
+
+template <typename T>
+struct RoBwdArgs {
+  const float *dllr;        // llr layout
+  const T *q;               // saved hidden (post ReLU) [rows][128]
+  const float *w2;          // master readout w2 [128][m_max]
+  const T *w1t;             // transposed prepped readout w1
+  T *dr;                    // hidden-layer gradient [rows][128] (for dW1)
+  T *dh;                    // gradient w.r.t. the final state [rows][128]
+  float *part;              // per-workgroup [1032] partials of dW2 (128 x 8) and db2 (8)
+  int m_max;
+  const SlotGeo *geo;
+  const Tile *tiles;
+  int n_tiles;
+};
+template <typename T>
+void launch_readout_bwd(const RoBwdArgs<T> &a, int grid, hipStream_t st);
+void launch_readout_w2_reduce(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off, float *dw,
+                              hipStream_t st);
 
 // Training kernels.
 void launch_bce(const SlotGeo *geo, const int64_t *re_base, int n_slots, int64_t n_re, int m_max,

@@ -1,0 +1,533 @@
+// Backward pass of the CGNN (training, Sec. II-B): weight gradients and the
+// backward of message passing and readout.  The data gradients of the 3x3
+// convolutions reuse the forward kernel with flipped, transposed weights.
+//
+// Weight gradient of a 3x3 convolution (split-K over rows, deterministic):
+//   dW[tap][c][o] = sum_rows X[neighbour(row, tap)][c] * dY[row][o]
+// A workgroup owns one (row partition, tap, 128-channel input slice) and keeps
+// the 128x128 block in MFMA accumulators.  Per 32-row step it stages X (shifted
+// by the tap, zero outside the grid) and dY transposed into LDS, so that the
+// MFMA operands (K = rows) are contiguous 16-byte fragments.  Partition results
+// are summed in a fixed order by a separate kernel.
+//
+// Biases and the folded positional-encoding weights need column sums of dY per
+// (symbol t, subcarrier parity relative to the UE's CDM group, edge class):
+// the PE bias field has exactly that structure, so its weight gradient is the
+// same small table contracted with those sums.
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int RS = 32;                  // rows per staging step
+constexpr int TP = RS + 8;              // LDS pitch (elements) of the transposed tiles
+
+template <typename T>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs<T> a) {
+  __shared__ __align__(16) T xt[128 * TP];
+  __shared__ __align__(16) T dt[128 * TP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  constexpr int KF = mma<T>::KF;        // K rows per 16-byte fragment
+  // XCD-aware job order: consecutive logical ids (same XCD) share a partition
+  const int G = gridDim.x;
+  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int njob = a.n_taps * a.n_slices;
+  const int part = lb / njob, job = lb % njob;
+  const int tap = a.tap0 + job / a.n_slices, slice = job % a.n_slices;
+  const int di = tap / 3 - 1, dj = tap % 3 - 1;
+  const T *src;
+  int cs, coff;
+  if (slice * 128 < a.c0) { src = a.src0; cs = a.c0; coff = slice * 128; }
+  else { src = a.src1; cs = a.c1; coff = slice * 128 - a.c0; }
+  const int cwidth = cs - coff < 128 ? cs - coff : 128;
+
+  f32x4_t acc[2][8];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 8; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = (int)((int64_t)a.n_tiles * part / a.n_part);
+  const int t1 = (int)((int64_t)a.n_tiles * (part + 1) / a.n_part);
+  // staging roles: thread -> (row i of the step, 16-channel group g)
+  const int si = tid >> 3, sg = tid & 7;
+  for (int ti = t0; ti < t1; ++ti) {
+    const Tile tl = a.tiles[ti];
+    const SlotGeo g = a.geo[tl.slot];
+    const int U = g.U, S = g.S, rps = 14 * U;
+    for (int k0 = 0; k0 < tl.nrows; k0 += RS) {
+      const int r = k0 + si;                       // row within the tile
+      float xv[16], dv[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { xv[e] = 0.f; dv[e] = 0.f; }
+      if (r < tl.nrows) {
+        const int R = tl.row0 + r;
+        const int s = R / rps, t = (R - s * rps) / U;
+        const int64_t grow = g.row_base + R;
+        pack8<T>::load(a.dy + grow * NRX_D + 16 * sg, dv);
+        pack8<T>::load(a.dy + grow * NRX_D + 16 * sg + 8, dv + 8);
+        const int sn = s + di, tn = t + dj;
+        if (sn >= 0 && sn < S && tn >= 0 && tn < 14 && 16 * sg < cwidth) {
+          const int64_t nrow = grow + di * rps + dj * U;
+          pack8<T>::load(src + nrow * cs + coff + 16 * sg, xv);
+          pack8<T>::load(src + nrow * cs + coff + 16 * sg + 8, xv + 8);
+        }
+      }
+      __syncthreads();   // previous step's fragment reads are done
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        xt[(16 * sg + e) * TP + si] = elem<T>::from_f(xv[e]);
+        dt[(16 * sg + e) * TP + si] = elem<T>::from_f(dv[e]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int f = 0; f < RS / KF; ++f) {
+        v16 bfr[8];
+#pragma unroll
+        for (int n = 0; n < 8; ++n)
+          bfr[n] = ld16(&dt[(n * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const v16 af = ld16(&xt[((2 * wave + m) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+#pragma unroll
+          for (int n = 0; n < 8; ++n) acc[m][n] = mma<T>::run(af, bfr[n], acc[m][n]);
+        }
+      }
+    }
+  }
+  // partial [part][job][c 128][o 128]; D layout: lane holds c = 4*lk + i, o = lr (per block)
+  float *dst = a.partials + ((int64_t)part * njob + job) * 128 * 128;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[((2 * wave + m) * 16 + 4 * lk + i) * 128 + n * 16 + lr] = acc[m][n][i];
+}
+
+// dw[layout] = sum over partitions, fixed order
+__global__ void wgrad_reduce_kernel(const float *partials, int n_part, int n_taps, int tap0, int n_slices,
+                                    int cin_real, int cin_total, int conv, int64_t dst_off, float *dw) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int njob = n_taps * n_slices;
+  if (e >= (int64_t)njob * 128 * 128) return;
+  const int o = e % 128, c = (e / 128) % 128, job = e / (128 * 128);
+  const int tap = tap0 + job / n_slices, slice = job % n_slices;
+  const int cg = slice * 128 + c;
+  if (cg >= cin_real) return;
+  double s = 0.0;
+  for (int p = 0; p < n_part; ++p) s += partials[((int64_t)p * njob + job) * 128 * 128 + c * 128 + o];
+  const int64_t idx = conv ? ((int64_t)tap * cin_total + cg) * 128 + o : (int64_t)cg * 128 + o;
+  dw[dst_off + idx] = (float)s;
+}
+
+// Column sums of dY per (slot, t, class = parity*3 + edge): partial[slot][t][6][128].
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_kernel(const T *dy, const SlotGeo *geo, float *partial) {
+  __shared__ float red[16][6 * 128];
+  const int slot = blockIdx.x, t = blockIdx.y;
+  const SlotGeo g = geo[slot];
+  const int cg = threadIdx.x & 15, rl = threadIdx.x >> 4;   // 8-channel group, row lane
+  float acc[6][8];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[c][k] = 0.f;
+  const int n = g.S * g.U;
+  for (int q = rl; q < n; q += 16) {
+    const int s = q / g.U, u = q - s * g.U;
+    const int par = (s - (u >> 1)) & 1;
+    const int edge = s == 0 ? 1 : (s == g.S - 1 ? 2 : 0);
+    const int cls = par * 3 + edge;
+    float v[8];
+    pack8<T>::load(dy + (g.row_base + ((int64_t)s * 14 + t) * g.U + u) * NRX_D + 8 * cg, v);
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (c == cls)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[c][k] += v[k];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[rl][c * 128 + 8 * cg + k] = acc[c][k];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 6 * 128; e += 256) {
+    float sum = 0.f;
+    for (int k = 0; k < 16; ++k) sum += red[k][e];
+    partial[((int64_t)slot * 14 + t) * 6 * 128 + e] = sum;
+  }
+}
+
+__device__ float pe_t_val(int t) {
+  float d[14], mean = 0.f;
+  for (int k = 0; k < 14; ++k) {
+    int x = k - NRX_DMRS0, y = k - NRX_DMRS1;
+    x = x < 0 ? -x : x;
+    y = y < 0 ? -y : y;
+    d[k] = (float)(x < y ? x : y);
+    mean += d[k];
+  }
+  mean /= 14.f;
+  float var = 0.f;
+  for (int k = 0; k < 14; ++k) var += (d[k] - mean) * (d[k] - mean);
+  return (d[t] - mean) / sqrtf(var / 14.f);
+}
+
+// Bias gradient (sum of all classes) and, for layers with a folded PE, the PE
+// weight gradients.  One thread per output channel o.
+__global__ void bias_pe_kernel(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total,
+                               int pe_ch, float *dw) {
+  const int o = threadIdx.x;
+  float cs[14][6];
+  for (int t = 0; t < 14; ++t)
+    for (int c = 0; c < 6; ++c) {
+      double s = 0.0;
+      for (int sl = 0; sl < n_slots; ++sl) s += partial[((int64_t)sl * 14 + t) * 768 + c * 128 + o];
+      cs[t][c] = (float)s;
+    }
+  double b = 0.0;
+  for (int t = 0; t < 14; ++t)
+    for (int c = 0; c < 6; ++c) b += cs[t][c];
+  dw[bias_off + o] = (float)b;
+  if (pe_w_off < 0) return;
+  for (int i = 0; i < 3; ++i) {
+    const int di = i - 1;
+    for (int j = 0; j < 3; ++j) {
+      const int dj = j - 1;
+      double gt = 0.0, gf = 0.0;
+      for (int t = 0; t < 14; ++t) {
+        const int tt = t + dj;
+        if (tt < 0 || tt >= 14) continue;
+        const float pt = pe_t_val(tt);
+        for (int par = 0; par < 2; ++par)
+          for (int edge = 0; edge < 3; ++edge) {
+            if ((edge == 1 && di < 0) || (edge == 2 && di > 0)) continue;
+            const float pf = ((par + di) & 1) ? 1.f : -1.f;
+            const float v = cs[t][par * 3 + edge];
+            gt += (double)v * pt;
+            gf += (double)v * pf;
+          }
+      }
+      const int64_t w = pe_w_off + ((int64_t)(i * 3 + j) * cin_total + pe_ch) * 128 + o;
+      dw[w] = (float)gt;
+      dw[w + 128] = (float)gf;
+    }
+  }
+}
+
+// LayerNorm parameter gradients from per-workgroup partials [n][256].
+__global__ void ln_reduce_kernel(const float *part, int n, int64_t g_off, int64_t b_off, float *dw) {
+  const int c = threadIdx.x;   // 0..255
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += part[(int64_t)k * 256 + c];
+  if (c < 128) dw[g_off + c] = (float)s;
+  else dw[b_off + c - 128] = (float)s;
+}
+
+// --------------------------------------------------------------- MP / readout
+
+template <typename T>
+struct OpTileB {
+  static constexpr int PITCHB = NRX_D * (int)sizeof(T) + 16;
+};
+
+// acc += A x W (128-deep K); A fragments from LDS tile rows, W prepped dense.
+template <typename T>
+__device__ __forceinline__ void gemm_lds(f32x4_t (&acc)[2][8], const unsigned char *lds, int wave, const T *w,
+                                         int lr, int lk) {
+  constexpr int KC = 64 / (int)sizeof(T);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int n = 0; n < 8; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const T *wl = w + lr * KC + lk * (KC / 4);
+#pragma unroll 2
+  for (int c = 0; c < NRX_D / KC; ++c) {
+    v16 bf[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) bf[n] = ld16(wl + (size_t)(c * 8 + n) * 16 * KC);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const v16 af = ld16(lds + (wave * 32 + m * 16 + lr) * OpTileB<T>::PITCHB + c * 64 + lk * 16);
+#pragma unroll
+      for (int n = 0; n < 8; ++n) acc[m][n] = mma<T>::run(af, bf[n], acc[m][n]);
+    }
+  }
+}
+
+// MP backward for one round.  In: dagg (dL/dagg), m1 (saved hidden), h.
+// dmsg_v = sum_{u != v} dagg_u; dm1 = (dmsg W2^T) [m1 > 0]; dh += dm1 W1^T.
+// Writes dmsg and dm1 (for the weight gradients) and updates dh in place.
+template <typename T>
+__global__ __launch_bounds__(256) void mp_bwd_kernel(MpBwdArgs<T> a) {
+  constexpr int PB = OpTileB<T>::PITCHB;
+  constexpr int MSG_PITCH = NRX_D + 4;
+  __shared__ __align__(16) unsigned char lds[128 * MSG_PITCH * 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4, ch0 = 8 * lr;
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const int64_t gbase = g.row_base + tl.row0;
+    const int U = g.U;
+    __syncthreads();
+    // stage dagg (fp32) to LDS
+    float *dg = reinterpret_cast<float *>(lds);
+    for (int e = tid; e < tl.nrows * 16; e += 256) {
+      const int r = e >> 4, c8 = (e & 15) * 8;
+      float v[8];
+      pack8<T>::load(a.dagg + (gbase + r) * NRX_D + c8, v);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) dg[r * MSG_PITCH + c8 + k] = v[k];
+    }
+    __syncthreads();
+    // dmsg for every row (each thread: one row, 8 channels), kept in registers
+    float dm[8][8];
+    int rows_of[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      rows_of[q] = -1;
+      if (e < tl.nrows * 16) {
+        const int r = e >> 4, c8 = (e & 15) * 8;
+        const int u = r % U, re0 = r - u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dm[q][k] = 0.f;
+        for (int o = 0; o < U; ++o) {
+          if (o == u) continue;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dm[q][k] += dg[(re0 + o) * MSG_PITCH + c8 + k];
+        }
+        rows_of[q] = e;
+      }
+    }
+    __syncthreads();
+    // dmsg -> global (weight gradient input) and LDS (operand layout for dmsg W2^T)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = rows_of[q];
+      if (e >= 0) {
+        const int r = e >> 4, c8 = (e & 15) * 8;
+        pack8<T>::store(a.dmsg + (gbase + r) * NRX_D + c8, dm[q]);
+        pack8<T>::store(reinterpret_cast<T *>(lds + r * PB) + c8, dm[q]);
+      }
+    }
+    // zero rows past the tile so the MFMA reads defined values
+    for (int e = tid; e < (128 - tl.nrows) * 16; e += 256) {
+      const int r = tl.nrows + (e >> 4), c8 = (e & 15) * 8;
+      float z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      pack8<T>::store(reinterpret_cast<T *>(lds + r * PB) + c8, z);
+    }
+    __syncthreads();
+    f32x4_t acc[2][8];
+    gemm_lds<T>(acc, lds, wave, a.w2t, lr, lk);
+    __syncthreads();
+    // dm1 = acc [m1 > 0] -> global + LDS
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 32 + m * 16 + 4 * lk + i;
+        const bool valid = r < tl.nrows;
+        float mv[8], v[8];
+        if (valid) pack8<T>::load(a.m1 + (gbase + r) * NRX_D + ch0, mv);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) v[n] = (valid && mv[n] > 0.f) ? acc[m][n][i] : 0.f;
+        if (sizeof(T) == 2) {
+#pragma unroll
+          for (int n = 0; n < 8; ++n) v[n] = bf2f(f2bf(v[n]));
+        }
+        if (valid) pack8<T>::store(a.dm1 + (gbase + r) * NRX_D + ch0, v);
+        pack8<T>::store(reinterpret_cast<T *>(lds + r * PB) + ch0, v);
+      }
+    __syncthreads();
+    gemm_lds<T>(acc, lds, wave, a.w1t, lr, lk);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 32 + m * 16 + 4 * lk + i;
+        if (r < tl.nrows) {
+          float hv[8];
+          pack8<T>::load(a.dh + (gbase + r) * NRX_D + ch0, hv);
+#pragma unroll
+          for (int n = 0; n < 8; ++n) hv[n] += acc[m][n][i];
+          pack8<T>::store(a.dh + (gbase + r) * NRX_D + ch0, hv);
+        }
+      }
+  }
+}
+
+// Readout backward.  dl (llr layout, masked to j < m_u) -> dr = (dl W2^T) [q > 0],
+// dh = dr W1^T.  Per-workgroup partials of dW2 = q^T dl and db2 = sum dl.
+template <typename T>
+__global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
+  constexpr int PB = OpTileB<T>::PITCHB;
+  __shared__ __align__(16) unsigned char lds[128 * PB];
+  __shared__ float red[4][8 * 128 + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4, ch0 = 8 * lr;
+  const int M = a.m_max;
+  float w2[8][8];
+#pragma unroll
+  for (int n = 0; n < 8; ++n)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w2[n][j] = j < M ? a.w2[(ch0 + n) * M + j] : 0.f;
+  float pw[8][8], pb[8];   // this lane's dW2 rows (its 8 channels) and db2
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    pb[n] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pw[n][j] = 0.f;
+  }
+  for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const int64_t gbase = g.row_base + tl.row0;
+    const int U = g.U, S = g.S;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 32 + m * 16 + 4 * lk + i;
+        const bool valid = r < tl.nrows;
+        float dl[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dl[j] = 0.f;
+        float qv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (valid) {
+          const int R = tl.row0 + r;
+          const int s = R / (14 * U);
+          const int rem = R - s * 14 * U;
+          const int t = rem / U, u = rem - t * U;
+          const int mu = a.geo[tl.slot].m[u];
+          const float *src = a.dllr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) dl[j] = (j < M && j < mu) ? src[j] : 0.f;
+          pack8<T>::load(a.q + (gbase + r) * NRX_D + ch0, qv);
+        }
+        float dr[8];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+          float x = 0.f;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x += dl[j] * w2[n][j];
+          dr[n] = qv[n] > 0.f ? x : 0.f;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) pw[n][j] += qv[n] * dl[j];
+        }
+        if (lr == 0) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) pb[j] += dl[j];
+        }
+        if (sizeof(T) == 2) {
+#pragma unroll
+          for (int n = 0; n < 8; ++n) dr[n] = bf2f(f2bf(dr[n]));
+        }
+        if (valid) pack8<T>::store(a.dr + (gbase + r) * NRX_D + ch0, dr);
+        pack8<T>::store(reinterpret_cast<T *>(lds + r * PB) + ch0, dr);
+      }
+    __syncthreads();
+    f32x4_t acc[2][8];
+    gemm_lds<T>(acc, lds, wave, a.w1t, lr, lk);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 32 + m * 16 + 4 * lk + i;
+        if (r < tl.nrows) {
+          float v[8];
+#pragma unroll
+          for (int n = 0; n < 8; ++n) v[n] = acc[m][n][i];
+          pack8<T>::store(a.dh + (gbase + r) * NRX_D + ch0, v);
+        }
+      }
+  }
+  // reduce dW2 / db2 over the 4 row groups, then the 4 waves
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      pw[n][j] += __shfl_xor(pw[n][j], 16, 64);
+      pw[n][j] += __shfl_xor(pw[n][j], 32, 64);
+    }
+    pb[n] += __shfl_xor(pb[n], 16, 64);
+    pb[n] += __shfl_xor(pb[n], 32, 64);
+  }
+  if (lk == 0) {
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[wave][(ch0 + n) * 8 + j] = pw[n][j];
+    if (lr == 0)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[wave][1024 + j] = pb[j];
+  }
+  __syncthreads();
+  for (int e = tid; e < 1032; e += 256)
+    a.part[(int64_t)blockIdx.x * 1032 + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+}
+
+__global__ void readout_w2_reduce_kernel(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off,
+                                         float *dw) {
+  const int e = threadIdx.x + blockIdx.x * blockDim.x;   // 0..1031
+  if (e >= 1032) return;
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) s += part[(int64_t)k * 1032 + e];
+  if (e < 1024) {
+    const int c = e / 8, j = e % 8;
+    if (j < m_max) dw[w2_off + c * m_max + j] = (float)s;
+  } else if (e - 1024 < m_max) {
+    dw[b2_off + e - 1024] = (float)s;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_wgrad(const WgradArgs<T> &a, hipStream_t st) {
+  const int grid = a.n_part * a.n_taps * a.n_slices;
+  hipLaunchKernelGGL(wgrad_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
+                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st) {
+  const int64_t n = (int64_t)n_taps * n_slices * 128 * 128;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, partials, n_part,
+                     n_taps, tap0, n_slices, cin_real, cin_total, conv, dst_off, dw);
+}
+template <typename T>
+void launch_colsum(const T *dy, const SlotGeo *geo, int n_slots, float *partial, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel<T>, dim3(n_slots, 14), dim3(256), 0, st, dy, geo, partial);
+}
+void launch_bias_pe(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
+                    float *dw, hipStream_t st) {
+  hipLaunchKernelGGL(bias_pe_kernel, dim3(1), dim3(128), 0, st, partial, n_slots, bias_off, pe_w_off, cin_total,
+                     pe_ch, dw);
+}
+void launch_ln_reduce(const float *part, int n, int64_t g_off, int64_t b_off, float *dw, hipStream_t st) {
+  hipLaunchKernelGGL(ln_reduce_kernel, dim3(1), dim3(256), 0, st, part, n, g_off, b_off, dw);
+}
+template <typename T>
+void launch_mp_bwd(const MpBwdArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(mp_bwd_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+template <typename T>
+void launch_readout_bwd(const RoBwdArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(readout_bwd_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+void launch_readout_w2_reduce(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off, float *dw,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(readout_w2_reduce_kernel, dim3(5), dim3(256), 0, st, part, n, m_max, w2_off, b2_off, dw);
+}
+
+template void launch_wgrad<float>(const WgradArgs<float> &, hipStream_t);
+template void launch_wgrad<bf16_t>(const WgradArgs<bf16_t> &, hipStream_t);
+template void launch_colsum<float>(const float *, const SlotGeo *, int, float *, hipStream_t);
+template void launch_colsum<bf16_t>(const bf16_t *, const SlotGeo *, int, float *, hipStream_t);
+template void launch_mp_bwd<float>(const MpBwdArgs<float> &, int, hipStream_t);
+template void launch_mp_bwd<bf16_t>(const MpBwdArgs<bf16_t> &, int, hipStream_t);
+template void launch_readout_bwd<float>(const RoBwdArgs<float> &, int, hipStream_t);
+template void launch_readout_bwd<bf16_t>(const RoBwdArgs<bf16_t> &, int, hipStream_t);

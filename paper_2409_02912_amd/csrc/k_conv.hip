@@ -64,6 +64,9 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
   const int cin = a.c0 + a.c1;
   const int nch = cin / KC;
   int buf = 0;
+  float lnp[EPI == EPI_LN_BWD ? 16 : 1];   // this lane's dgamma / dbeta partial sums (EPI_LN_BWD)
+#pragma unroll
+  for (int k = 0; k < (EPI == EPI_LN_BWD ? 16 : 1); ++k) lnp[k] = 0.f;
 
   // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs, so
   // give the workgroups of one XCD consecutive tiles (their halos overlap and
@@ -170,8 +173,46 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
       }
     }
 
-// ---------------------------------------------------------- epilogue --
+    // ---------------------------------------------------------- epilogue --
     const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
+    if constexpr (EPI == EPI_LN_BWD) {
+      // acc = dL/da with a = ReLU(LN(z)); resid holds a, save_z holds z, save_stats (mean, rstd).
+      // dz = rstd (dzhat - mean(dzhat) - zhat mean(dzhat zhat)), dzhat = g * dn, dn = da [a > 0]
+      float gam[8];
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) gam[nb] = a.ln_g[ch0 + nb];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+          const bool valid = r < tl.nrows;
+          const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
+          float av[8], zv[8];
+          pack8<T>::load(a.resid + grow * NRX_D + ch0, av);
+          pack8<T>::load(a.save_z + grow * NRX_D + ch0, zv);
+          const float mean = a.save_stats[2 * grow], rstd = a.save_stats[2 * grow + 1];
+          float dn[8], zh[8], dzh[8], s1 = 0.f, s2 = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            dn[nb] = (valid && av[nb] > 0.f) ? acc[mb][nb][i] : 0.f;
+            zh[nb] = (zv[nb] - mean) * rstd;
+            dzh[nb] = dn[nb] * gam[nb];
+            s1 += dzh[nb];
+            s2 += dzh[nb] * zh[nb];
+            lnp[nb] += dn[nb] * zh[nb];
+            lnp[8 + nb] += dn[nb];
+          }
+          s1 = row_sum16(s1) * (1.0f / NRX_D);
+          s2 = row_sum16(s2) * (1.0f / NRX_D);
+          float dz[8];
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) dz[nb] = rstd * (dzh[nb] - s1 - zh[nb] * s2);
+          if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, dz);
+        }
+      }
+      continue;
+    }
     float bias[8];
 #pragma unroll
     for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
@@ -225,6 +266,25 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
       }
     }
   }
+  if constexpr (EPI == EPI_LN_BWD) {
+    // reduce over the 4 row groups of a wave, then over the 4 waves (fixed order)
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lnp[k] += __shfl_xor(lnp[k], 16, 64);
+      lnp[k] += __shfl_xor(lnp[k], 32, 64);
+    }
+    __syncthreads();
+    float *red = reinterpret_cast<float *>(&lds[0][0]);   // [4 waves][256]
+    if (lk == 0) {
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        red[wave * 256 + 8 * lr + nb] = lnp[nb];
+        red[wave * 256 + 128 + 8 * lr + nb] = lnp[8 + nb];
+      }
+    }
+    __syncthreads();
+    a.ln_part[(int64_t)blockIdx.x * 256 + tid] = red[tid] + red[256 + tid] + red[512 + tid] + red[768 + tid];
+  }
 }
 
 }  // namespace
@@ -247,8 +307,10 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_STORE, OCCV, PF>), dim3(grid), blk, 0, st, a); \
     else if (epi == EPI_LN_RELU)                                                              \
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_RELU, OCCV, PF>), dim3(grid), blk, 0, st, a); \
-    else                                                                                      \
+    else if (epi == EPI_RESID)                                                                \
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_RESID, OCCV, PF>), dim3(grid), blk, 0, st, a); \
+    else                                                                                      \
+      hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_BWD, OCCV, PF>), dim3(grid), blk, 0, st, a); \
     return;                                                                                   \
   }
   NRX_CONV_CASE(0, 4, 1, true)

@@ -77,6 +77,11 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
     const int chunk = k / (128 * KC);
     const int c = chunk * KC + kl;
     if (c < J.cin_real) v = w[J.src + (int64_t)c * NRX_D + n];
+  } else if (J.kind == 5) {
+    // transposed dense: B[k = c][n] = W[n][c]
+    const int chunk = k / (128 * KC);
+    const int c = chunk * KC + kl;
+    v = w[J.src + (int64_t)n * NRX_D + c];
   } else {
     const int tap = (k / (128 * KC)) % 9, chunk = k / (1152 * KC);
     const int c = chunk * KC + kl;

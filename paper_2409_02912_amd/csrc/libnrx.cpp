@@ -70,11 +70,14 @@ struct BlockLayer {
   ConvLayer a, b;
   int64_t g = 0, beta = 0;
   int mp_round = -1;            // message-passing round before this block, or -1
+  // backward: prepped data-gradient weights (offsets in the backward prepped buffer)
+  int64_t bg_b = 0, bg_a_h = 0, bg_a_agg = -1;
 };
 
 struct DenseLayer {
   int64_t w1 = 0, b1 = 0, w2 = 0, b2 = 0;
   int64_t p1 = 0, p2 = -1;      // prepped offsets
+  int64_t t1 = -1, t2 = -1;     // backward: prepped transposed weights
 };
 
 struct Plan {
@@ -267,6 +270,9 @@ struct nrx_model {
   std::vector<PrepJob> jobs;
   int64_t prep_elems = 0, field_elems = 0, prep_total = 0;
   void *pinned_jobs = nullptr;
+  std::vector<PrepJob> bjobs;           // backward weight preparation
+  int64_t bprep_elems = 0;
+  void *pinned_bjobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
   // conv kernel variant per layer class (autotuned; indices into kConvVariants)
   int conv_variant[NRX_K_NCLASS] = {0, 0, 0, 0, 0, 0, 0};
@@ -397,6 +403,24 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     m->jobs.push_back(j);
     m->prep_elems += j.count;
   }
+  // backward jobs: flipped/transposed conv weights and transposed dense weights
+  auto bjob = [&](int kind, int64_t src, int cin_total, int cin_first, int64_t count) {
+    const int64_t off = m->bprep_elems;
+    m->bjobs.push_back(PrepJob{kind, d, cin_total, d / KC, cin_first, 0, src, off, count});
+    m->bprep_elems += count;
+    return off;
+  };
+  for (int i = 0; i < c.n_blocks; ++i) {
+    BlockLayer &L = m->blocks[i];
+    L.bg_b = bjob(3, L.b.w, d, 0, 9LL * 128 * d);
+    L.bg_a_h = bjob(3, L.a.w, L.a.cin_total, 0, 9LL * 128 * d);
+    if (L.mp_round >= 0) L.bg_a_agg = bjob(3, L.a.w, L.a.cin_total, d, 9LL * 128 * d);
+  }
+  for (int r = 0; r < c.n_rounds; ++r) {
+    m->mp[r].t1 = bjob(5, m->mp[r].w1, d, 0, (int64_t)d * 128);
+    m->mp[r].t2 = bjob(5, m->mp[r].w2, d, 0, (int64_t)d * 128);
+  }
+  m->ro.t1 = bjob(5, m->ro.w1, d, 0, (int64_t)d * 128);
   // field jobs index a separate buffer; the prep kernel walks jobs in order over one index space
   m->prep_total = 0;
   for (auto &j : m->jobs) m->prep_total += j.count;
@@ -406,6 +430,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
 
 extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
   if (!m) return fail(NRX_ERR_INVALID, "null model");
+  if (m->pinned_bjobs) (void)hipHostFree(m->pinned_bjobs);
   for (auto &e : m->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : m->pool) (void)hipEventDestroy(e);
   if (m->pinned_jobs) (void)hipHostFree(m->pinned_jobs);
@@ -438,8 +463,14 @@ struct FwdLayout {
   std::vector<size_t> stats;  // per block (training)
   std::vector<size_t> agg, m1;  // per round (inference: one agg)
   size_t q;                   // readout hidden (training)
+  // backward (training layout only)
+  size_t bjobs = 0, bprep = 0, zero = 0, dh = 0, dz = 0, dagg = 0, dmsg = 0, dm1 = 0, dr = 0;
+  size_t wpart = 0, cpart = 0, lpart = 0, rpart = 0;
   size_t total;
 };
+
+constexpr int WGRAD_PARTS = 64;       // row partitions of the weight-gradient kernel (multiple of 8)
+constexpr int BWD_GRID_MAX = 4096;    // bound on per-workgroup partial buffers
 
 FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   FwdLayout L;
@@ -467,6 +498,19 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     for (int r = 0; r < R; ++r) { L.agg.push_back(o); o += act; }
     for (int r = 0; r < R; ++r) { L.m1.push_back(o); o += act; }
     L.q = o; o += act;
+    L.bjobs = o; o = align256(o + sizeof(PrepJob) * m->bjobs.size());
+    L.bprep = o; o = align256(o + (size_t)m->bprep_elems * ts);
+    L.zero = o; o = align256(o + 128 * 4);
+    L.dh = o; o += act;
+    L.dz = o; o += act;
+    L.dagg = o; o += act;
+    L.dmsg = o; o += act;
+    L.dm1 = o; o += act;
+    L.dr = o; o += act;
+    L.wpart = o; o = align256(o + (size_t)WGRAD_PARTS * 9 * 2 * 128 * 128 * 4);
+    L.cpart = o; o = align256(o + (size_t)P->n * 14 * 768 * 4);
+    L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
+    L.rpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 1032 * 4);
   }
   L.total = o;
   return L;
@@ -770,10 +814,164 @@ extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_
   return NRX_OK;
 }
 
+namespace {
+
+template <typename T>
+nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *dllr,
+                         float *dw, char *ws, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (!m->pinned_bjobs) {
+      if (hipHostMalloc(&m->pinned_bjobs, sizeof(PrepJob) * m->bjobs.size(), hipHostMallocDefault) != hipSuccess)
+        return fail(NRX_ERR_HIP, "hipHostMalloc failed");
+      memcpy(m->pinned_bjobs, m->bjobs.data(), sizeof(PrepJob) * m->bjobs.size());
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ws + L.bjobs, m->pinned_bjobs, sizeof(PrepJob) * m->bjobs.size(), hipMemcpyHostToDevice, st));
+  const Dev D = dev_tables(P, ws + L.meta);
+  T *bp = (T *)(ws + L.bprep);
+  launch_prep<T>(w, (const PrepJob *)(ws + L.bjobs), (int)m->bjobs.size(), m->bprep_elems, bp, nullptr, st);
+  HIPCHK(hipMemsetAsync(ws + L.zero, 0, 128 * 4, st));
+  auto buf = [&](size_t off) { return (T *)(ws + off); };
+  const float *zero = (const float *)(ws + L.zero);
+  float *wpart = (float *)(ws + L.wpart), *cpart = (float *)(ws + L.cpart);
+  float *lpart = (float *)(ws + L.lpart), *rpart = (float *)(ws + L.rpart);
+  const int C = m->cfg.n_blocks;
+  const int d = NRX_D;
+  const int ti256 = tile_size_index(4);
+  const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), std::min(num_cu() * 4, BWD_GRID_MAX));
+
+  auto wgrad = [&](const T *src0, int c0, const T *src1, int c1, const T *dy, bool conv, int cin_real, int cin_total,
+                   int64_t dst) {
+    WgradArgs<T> a{};
+    a.src0 = src0; a.c0 = c0; a.src1 = src1; a.c1 = c1;
+    a.dy = dy;
+    a.geo = D.geo;
+    a.tiles = D.ct[ti256];
+    a.n_tiles = (int)P->ct[ti256].size();
+    a.n_part = WGRAD_PARTS;
+    a.n_taps = conv ? 9 : 1;
+    a.tap0 = conv ? 0 : 4;
+    a.n_slices = (c0 + c1 + 127) / 128;
+    a.partials = wpart;
+    launch_wgrad<T>(a, st);
+    launch_wgrad_reduce(wpart, WGRAD_PARTS, a.n_taps, a.tap0, a.n_slices, cin_real, cin_total, conv ? 1 : 0, dst, dw,
+                        st);
+  };
+  auto bias = [&](const T *dy, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch) {
+    launch_colsum<T>(dy, D.geo, P->n, cpart, st);
+    launch_bias_pe(cpart, P->n, bias_off, pe_w_off, cin_total, pe_ch, dw, st);
+  };
+  auto dgrad = [&](const T *src, const T *wt, int epi, int cls, T *out, const T *resid, const T *z, const float *stats,
+                   const float *g) {
+    ConvArgs<T> a{};
+    a.src0 = src; a.c0 = d; a.src1 = nullptr; a.c1 = 0;
+    a.w = wt;
+    a.bias = zero;
+    a.pe = nullptr;
+    a.ln_g = g;
+    a.resid = resid;
+    a.out = out;
+    a.save_z = const_cast<T *>(z);
+    a.save_stats = const_cast<float *>(stats);
+    a.ln_part = lpart;
+    a.geo = D.geo;
+    const int v = m->conv_variant[cls];
+    const ConvVariant &cv = kConvVariants[v];
+    const int ti = tile_size_index(cv.mb);
+    a.tiles = D.ct[ti];
+    a.n_tiles = (int)P->ct[ti].size();
+    int grid = std::min<int>(a.n_tiles, std::min(num_cu() * cv.occ, BWD_GRID_MAX));
+    grid = (grid + 7) / 8 * 8;
+    launch_conv<T>(a, epi, v, grid, st);
+    return grid;
+  };
+
+  T *dh = buf(L.dh), *dz = buf(L.dz);
+  // readout
+  {
+    RoBwdArgs<T> a{};
+    a.dllr = dllr;
+    a.q = buf(L.q);
+    a.w2 = w + m->ro.w2;
+    a.w1t = bp + m->ro.t1;
+    a.dr = buf(L.dr);
+    a.dh = dh;
+    a.part = rpart;
+    a.m_max = m->cfg.m_max;
+    a.geo = D.geo;
+    a.tiles = D.rt;
+    a.n_tiles = (int)P->rt.size();
+    launch_readout_bwd<T>(a, grid_mlp, st);
+    launch_readout_w2_reduce(rpart, grid_mlp, m->cfg.m_max, m->ro.w2, m->ro.b2, dw, st);
+    wgrad(buf(L.h[C]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro.w1);
+    bias(buf(L.dr), m->ro.b1, -1, 0, 0);
+  }
+  for (int i = C - 1; i >= 0; --i) {
+    const BlockLayer &B = m->blocks[i];
+    T *h_in = buf(L.h[i]);
+    T *a_i = buf(L.a[i]);
+    // conv_b: h_{i+1} = h_i + conv_b(a_i)
+    wgrad(a_i, d, nullptr, 0, dh, true, d, d, B.b.w);
+    bias(dh, B.b.b, -1, 0, 0);
+    const int gl = dgrad(dh, bp + B.bg_b, EPI_LN_BWD, NRX_K_CONV_B, dz, a_i, buf(L.z[i]), (const float *)(ws + L.stats[i]),
+                         w + B.g);
+    launch_ln_reduce(lpart, gl, B.g, B.beta, dw, st);
+    // conv_a on [h_i (, agg_r)] (+ PE)
+    if (B.mp_round >= 0) {
+      const int r = B.mp_round;
+      T *agg = buf(L.agg[r]);
+      wgrad(h_in, d, agg, d, dz, true, 2 * d, B.a.cin_total, B.a.w);
+      bias(dz, B.a.b, B.a.w, B.a.cin_total, 2 * d);
+      dgrad(dz, bp + B.bg_a_h, EPI_RESID, NRX_K_CONV_A_MP, dh, dh, nullptr, nullptr, nullptr);
+      dgrad(dz, bp + B.bg_a_agg, EPI_STORE, NRX_K_CONV_A_MP, buf(L.dagg), nullptr, nullptr, nullptr, nullptr);
+      MpBwdArgs<T> ma{};
+      ma.dagg = buf(L.dagg);
+      ma.m1 = buf(L.m1[r]);
+      ma.w1t = bp + m->mp[r].t1;
+      ma.w2t = bp + m->mp[r].t2;
+      ma.dmsg = buf(L.dmsg);
+      ma.dm1 = buf(L.dm1);
+      ma.dh = dh;
+      ma.geo = D.geo;
+      ma.tiles = D.mt;
+      ma.n_tiles = (int)P->mt.size();
+      launch_mp_bwd<T>(ma, grid_mlp, st);
+      wgrad(buf(L.m1[r]), d, nullptr, 0, buf(L.dmsg), false, d, d, m->mp[r].w2);
+      bias(buf(L.dmsg), m->mp[r].b2, -1, 0, 0);
+      wgrad(h_in, d, nullptr, 0, buf(L.dm1), false, d, d, m->mp[r].w1);
+      bias(buf(L.dm1), m->mp[r].b1, -1, 0, 0);
+    } else {
+      wgrad(h_in, d, nullptr, 0, dz, true, d, d, B.a.w);
+      bias(dz, B.a.b, -1, 0, 0);
+      dgrad(dz, bp + B.bg_a_h, EPI_RESID, NRX_K_CONV_A, dh, dh, nullptr, nullptr, nullptr);
+    }
+  }
+  // StateInit (no data gradient needed)
+  const int B4 = 4 * m->cfg.n_ant;
+  wgrad(buf(L.X), m->cx, nullptr, 0, dh, true, B4, B4 + 2, m->conv_in.w);
+  bias(dh, m->conv_in.b, m->conv_in.w, B4 + 2, B4);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+}  // namespace
+
 extern "C" nrx_status nrx_backward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
                                    const float *dllr, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
-  (void)m; (void)w; (void)slots; (void)n; (void)dllr; (void)dw; (void)ws; (void)ws_bytes; (void)st;
-  return fail(NRX_ERR_UNSUPPORTED, "nrx_backward is not available in this build yet");
+  if (!m || !w || !dllr || !dw || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  {
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (m->saved_ws != ws || m->saved_plan != P)
+      return fail(NRX_ERR_INVALID, "no save_acts forward of this batch on this workspace");
+  }
+  const FwdLayout L = fwd_layout(m, P, true);
+  if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  if (m->cfg.precision == NRX_FP32) return backward_impl<float>(m, P, L, w, dllr, dw, (char *)ws, st);
+  return backward_impl<bf16_t>(m, P, L, w, dllr, dw, (char *)ws, st);
 }
 
 // --------------------------------------------------------- model-free calls --

@@ -180,3 +180,57 @@ def test_bce_and_adam_match_oracle():
     assert np.allclose(tw.cpu().numpy(), ew, rtol=0, atol=1e-6)
     assert np.allclose(tm.cpu().numpy(), em, rtol=1e-6, atol=1e-7)
     assert np.allclose(tv.cpu().numpy(), ev, rtol=1e-6, atol=1e-7)
+
+
+def _grad_case(prec, tol, seed=21):
+    shapes = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
+              dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 2], slot_number=2)]
+    m_max = 4
+    net = cgnn.NetConfig(4, 128, 3, 1, m_max)
+    log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R}")
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
+    w = synth.he_weights(cgnn.layout(net), seed, perturb=True)
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    rng = np.random.default_rng(seed)
+    descs, sz = L.make_slots(shapes, m_max)
+    dllr_np = rng.standard_normal(sz["llr"]).astype(np.float32)
+    dparts = split_llr(dllr_np.astype(np.float64), shapes, m_max)
+    G = {k: np.zeros_like(v) for k, v in W.items()}
+    for i, r in enumerate(ref_slots):
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True)
+        g = cgnn.backward(W, net, cache, dparts[i])
+        for k in G:
+            G[k] += g[k]
+    ref = cgnn.flatten(G, net)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+    try:
+        y = _upload_batch(shapes, ref_slots)
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
+        dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
+        wt = dev(w)
+        L.nrx_forward(model, wt, descs, y, llr, ws, save_acts=True)
+        L.nrx_backward(model, wt, descs, dev(dllr_np), dw, ws)
+        torch.cuda.synchronize()
+        got = dw.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got)), "gradient entries left unwritten"
+        e = rel_err(got, ref)
+        log(f"  gradient relative error (all weights) {e:.2e}")
+        off = 0
+        for name, shape in cgnn.layout(net):
+            n = int(np.prod(shape))
+            et = rel_err(got[off:off + n], ref[off:off + n])
+            assert et <= tol, f"{name}: relative error {et:.3e}"
+            off += n
+        assert e <= tol
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_nrx_backward_fp32_matches_oracle():
+    _grad_case(0, 1e-4)
+
+
+def test_nrx_backward_bf16_close_to_oracle():
+    _grad_case(1, 5e-2)
