@@ -1,0 +1,180 @@
+"""Training of the neural receiver on slots generated on the GPU (Sec. II-B).
+
+Every step draws a fresh batch of slots with slot_sim (batch index = step, so a
+run is a pure function of the seed and resumes bit-exactly from a checkpoint),
+runs nrx_forward keeping activations, the BCE loss on the coded bits of the data
+REs (nrx_bce, fp64 reduction), nrx_backward and one Adam step on the fp32 master
+weights.  All work is enqueued on one stream; the host only reads the loss every
+`log_every` steps.
+
+    python -m paper_2409_02912_amd.train --workload c5 --steps 2000 --out weights.npy
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2409_02912_amd import libnrx as L  # noqa: E402
+from paper_2409_02912_amd import synth  # noqa: E402
+
+
+def weight_layout(model):
+    return [(n, s) for n, _, s in L.weight_layout(model)]
+
+
+class Trainer:
+    def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None):
+        import torch
+        self.torch = torch
+        self.w = w
+        self.seed = seed
+        self.lr = lr
+        self.m_max = w["m"]
+        self.shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
+        self.descs, sz = L.make_slots(self.shapes, self.m_max)
+        snr = snr or w["snr"]
+        self.sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
+                                rho=w["rho"], snr_db_lo=snr[0], snr_db_hi=snr[1])
+        self.model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], self.m_max, precision)
+        dev = "cuda"
+        self.params = torch.from_numpy(synth.he_weights(weight_layout(self.model), seed)).to(dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.y = torch.empty(2 * sz["y"], dtype=torch.float32, device=dev)
+        self.bits = torch.empty(sz["bits"], dtype=torch.uint8, device=dev)
+        self.llr = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
+        self.dllr = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.nerr = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws = torch.empty(L.nrx_workspace_bytes(self.model, self.descs, save_acts=True), dtype=torch.uint8,
+                              device=dev)
+        self.sws = torch.empty(L.slot_sim_workspace_bytes(self.sim, self.descs), dtype=torch.uint8, device=dev)
+        self.bws = torch.empty(L.nrx_bce_workspace_bytes(self.descs, self.m_max), dtype=torch.uint8, device=dev)
+        self.step = 0
+        self.n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in self.shapes)
+
+    def load(self, path):
+        z = np.load(path, allow_pickle=False)
+        self.params.copy_(self.torch.from_numpy(z["w"]))
+        self.m.copy_(self.torch.from_numpy(z["m"]))
+        self.v.copy_(self.torch.from_numpy(z["v"]))
+        self.step = int(z["step"])
+
+    def save(self, path):
+        np.savez(path, w=self.params.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 step=np.int64(self.step))
+
+    def train_step(self):
+        L.slot_sim(self.sim, self.seed, self.step, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
+        L.nrx_forward(self.model, self.params, self.descs, self.y, self.llr, self.ws, save_acts=True)
+        L.nrx_bce(self.descs, self.m_max, self.llr, self.bits, self.dllr, self.loss, self.nerr, self.bws)
+        L.nrx_backward(self.model, self.params, self.descs, self.dllr, self.grad, self.ws)
+        self.step += 1
+        L.nrx_adam(self.params, self.grad, self.m, self.v, self.step, lr=self.lr)
+
+    def close(self):
+        L.nrx_model_destroy(self.model)
+
+
+def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None):
+    """BER of the NRX and of LS + LMMSE on held-out slots (a seed not used in training) at a fixed SNR."""
+    import torch
+    m_max = w["m"]
+    shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
+    descs, sz = L.make_slots(shapes, m_max)
+    sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
+                       snr_db_lo=snr_db, snr_db_hi=snr_db)
+    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision)
+    try:
+        dev = "cuda"
+        params = w_params if isinstance(w_params, torch.Tensor) else torch.from_numpy(w_params).to(dev)
+        y = torch.empty(2 * sz["y"], dtype=torch.float32, device=dev)
+        bits = torch.empty(sz["bits"], dtype=torch.uint8, device=dev)
+        n0 = torch.empty(len(shapes), dtype=torch.float32, device=dev)
+        llr = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
+        ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device=dev)
+        sws = torch.empty(L.slot_sim_workspace_bytes(sim, descs), dtype=torch.uint8, device=dev)
+        bws = torch.empty(L.nrx_bce_workspace_bytes(descs, m_max), dtype=torch.uint8, device=dev)
+        lws = torch.empty(L.lmmse_workspace_bytes(descs), dtype=torch.uint8, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        nerr = torch.zeros(1, dtype=torch.int64, device=dev)
+        n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in shapes)
+        e_nrx = e_lmmse = 0
+        bce = 0.0
+        for b in range(batches):
+            L.slot_sim(sim, seed, b, descs, m_max, y, sws, bits=bits, n0=n0)
+            L.nrx_forward(model, params, descs, y, llr, ws)
+            L.nrx_bce(descs, m_max, llr, bits, None, loss, nerr, bws)
+            torch.cuda.synchronize()
+            e_nrx += nerr.item()
+            bce += loss.item()
+            L.lmmse_demap(descs, m_max, y, llr, lws, n0=n0)
+            L.nrx_bce(descs, m_max, llr, bits, None, loss, nerr, bws)
+            torch.cuda.synchronize()
+            e_lmmse += nerr.item()
+        n = batches * n_bits
+        return {"ber_nrx": e_nrx / n, "ber_lmmse": e_lmmse / n, "bce_nrx": bce / batches, "n_bits": n}
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--n-prb", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--ckpt", default=None, help="checkpoint (.npz) to resume from and to write")
+    ap.add_argument("--out", default=None, help="write the trained fp32 weights (.npy)")
+    ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--ckpt-every", type=int, default=500)
+    ap.add_argument("--time-limit", type=float, default=1e9, help="stop (and checkpoint) after this many seconds")
+    ap.add_argument("--eval-batches", type=int, default=0)
+    ap.add_argument("--eval-snr", type=float, default=10.0)
+    args = ap.parse_args()
+    import torch
+    w = synth.WORKLOADS[args.workload]
+    prec = L.NRX_BF16 if args.precision == "bf16" else L.NRX_FP32
+    tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb)
+    if args.ckpt and os.path.exists(args.ckpt):
+        tr.load(args.ckpt)
+        print(json.dumps({"resumed_at": tr.step}), flush=True)
+    t0 = time.time()
+    start = tr.step
+    while tr.step < args.steps:
+        tr.train_step()
+        if tr.step % args.log_every == 0 or tr.step == args.steps:
+            torch.cuda.synchronize()
+            el = time.time() - t0
+            print(json.dumps({"step": tr.step, "loss": tr.loss.item(), "ber": tr.nerr.item() / tr.n_bits,
+                              "s_per_step": el / max(tr.step - start, 1)}), flush=True)
+        if args.ckpt and tr.step % args.ckpt_every == 0:
+            tr.save(args.ckpt)
+        if time.time() - t0 > args.time_limit:
+            break
+    torch.cuda.synchronize()
+    if args.ckpt:
+        tr.save(args.ckpt)
+    if args.out:
+        np.save(args.out, tr.params.cpu().numpy())
+    if args.eval_batches:
+        r = evaluate(tr.params, w, seed=args.seed + 1000003, batches=args.eval_batches, snr_db=args.eval_snr,
+                     precision=prec, batch=args.batch, n_prb=args.n_prb)
+        print(json.dumps({"eval": r, "snr_db": args.eval_snr, "step": tr.step}), flush=True)
+    tr.close()
+
+
+if __name__ == "__main__":
+    main()
