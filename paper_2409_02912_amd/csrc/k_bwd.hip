@@ -19,16 +19,25 @@
 
 namespace {
 
-constexpr int RS = 32;                  // rows per staging step
+constexpr int RS = 64;                  // rows per staging step
 constexpr int TP = RS + 8;              // LDS pitch (elements) of the transposed tiles
 
+// Staging role of a thread: 4 consecutive rows (4*rg ..) x 8 consecutive channels (8*cg ..).
+// Lanes of a wave vary over rg first, so the transposed 4-row LDS stores of one
+// channel from 16 lanes form one contiguous 128-byte run.
 template <typename T>
-__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs<T> a) {
-  __shared__ __align__(16) T xt[128 * TP];
-  __shared__ __align__(16) T dt[128 * TP];
+struct WgStage {
+  float x[4][8], d[4][8];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
+  __shared__ __align__(16) T xt[2][128 * TP];
+  __shared__ __align__(16) T dt[2][128 * TP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  constexpr int KF = mma<T>::KF;        // K rows per 16-byte fragment
+  const int wm = wave >> 1, wn = wave & 1;   // 2 x 2 wave grid over the 128 x 128 block
+  constexpr int KF = mma<T>::KF;            // K rows per 16-byte fragment
   // XCD-aware job order: consecutive logical ids (same XCD) share a partition
   const int G = gridDim.x;
   const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -41,69 +50,98 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs<T> a) {
   if (slice * 128 < a.c0) { src = a.src0; cs = a.c0; coff = slice * 128; }
   else { src = a.src1; cs = a.c1; coff = slice * 128 - a.c0; }
   const int cwidth = cs - coff < 128 ? cs - coff : 128;
+  const int rg = tid & 15, cg = tid >> 4;
 
-  f32x4_t acc[2][8];
+  f32x4_t acc[4][4];
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < 8; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < 4; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   const int t0 = (int)((int64_t)a.n_tiles * part / a.n_part);
   const int t1 = (int)((int64_t)a.n_tiles * (part + 1) / a.n_part);
-  // staging roles: thread -> (row i of the step, 16-channel group g)
-  const int si = tid >> 3, sg = tid & 7;
-  for (int ti = t0; ti < t1; ++ti) {
-    const Tile tl = a.tiles[ti];
+
+  // the (tile, row offset) steps of this partition, walked in order
+  int ti = t0, k0 = 0;
+  auto load = [&](int tix, int kk, WgStage<T> &stg) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { stg.x[q][e] = 0.f; stg.d[q][e] = 0.f; }
+    const Tile tl = a.tiles[tix];
     const SlotGeo g = a.geo[tl.slot];
     const int U = g.U, S = g.S, rps = 14 * U;
-    for (int k0 = 0; k0 < tl.nrows; k0 += RS) {
-      const int r = k0 + si;                       // row within the tile
-      float xv[16], dv[16];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) { xv[e] = 0.f; dv[e] = 0.f; }
+    for (int q = 0; q < 4; ++q) {
+      const int r = kk + 4 * rg + q;
       if (r < tl.nrows) {
         const int R = tl.row0 + r;
         const int s = R / rps, t = (R - s * rps) / U;
         const int64_t grow = g.row_base + R;
-        pack8<T>::load(a.dy + grow * NRX_D + 16 * sg, dv);
-        pack8<T>::load(a.dy + grow * NRX_D + 16 * sg + 8, dv + 8);
+        pack8<T>::load(a.dy + grow * NRX_D + 8 * cg, stg.d[q]);
         const int sn = s + di, tn = t + dj;
-        if (sn >= 0 && sn < S && tn >= 0 && tn < 14 && 16 * sg < cwidth) {
-          const int64_t nrow = grow + di * rps + dj * U;
-          pack8<T>::load(src + nrow * cs + coff + 16 * sg, xv);
-          pack8<T>::load(src + nrow * cs + coff + 16 * sg + 8, xv + 8);
-        }
+        if (sn >= 0 && sn < S && tn >= 0 && tn < 14 && 8 * cg < cwidth)
+          pack8<T>::load(src + (grow + di * rps + dj * U) * cs + coff + 8 * cg, stg.x[q]);
       }
-      __syncthreads();   // previous step's fragment reads are done
+    }
+  };
+  auto store = [&](int b, const WgStage<T> &stg) {
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        xt[(16 * sg + e) * TP + si] = elem<T>::from_f(xv[e]);
-        dt[(16 * sg + e) * TP + si] = elem<T>::from_f(dv[e]);
-      }
-      __syncthreads();
+    for (int e = 0; e < 8; ++e) {
+      T xv[4], dv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { xv[q] = elem<T>::from_f(stg.x[q][e]); dv[q] = elem<T>::from_f(stg.d[q][e]); }
+      T *xp = &xt[b][(8 * cg + e) * TP + 4 * rg];
+      T *dp = &dt[b][(8 * cg + e) * TP + 4 * rg];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { xp[q] = xv[q]; dp[q] = dv[q]; }
+    }
+  };
+  auto advance = [&](int &tix, int &kk) {
+    kk += RS;
+    if (kk >= a.tiles[tix].nrows) { ++tix; kk = 0; }
+  };
+
+  if (ti < t1) {
+    WgStage<T> stg;
+    load(ti, k0, stg);
+    int b = 0;
+    store(b, stg);
+    __syncthreads();
+    while (ti < t1) {
+      int nti = ti, nk = k0;
+      advance(nti, nk);
+      const bool more = nti < t1;
+      if (more) load(nti, nk, stg);          // next step in flight during the MFMAs
 #pragma unroll
       for (int f = 0; f < RS / KF; ++f) {
-        v16 bfr[8];
+        v16 bfr[4];
 #pragma unroll
-        for (int n = 0; n < 8; ++n)
-          bfr[n] = ld16(&dt[(n * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+        for (int n = 0; n < 4; ++n)
+          bfr[n] = ld16(&dt[b][((4 * wn + n) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const v16 af = ld16(&xt[((2 * wave + m) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+        for (int m = 0; m < 4; ++m) {
+          const v16 af = ld16(&xt[b][((4 * wm + m) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
 #pragma unroll
-          for (int n = 0; n < 8; ++n) acc[m][n] = mma<T>::run(af, bfr[n], acc[m][n]);
+          for (int n = 0; n < 4; ++n) acc[m][n] = mma<T>::run(af, bfr[n], acc[m][n]);
         }
       }
+      if (more) store(b ^ 1, stg);
+      __syncthreads();
+      b ^= 1;
+      ti = nti;
+      k0 = nk;
     }
   }
   // partial [part][job][c 128][o 128]; D layout: lane holds c = 4*lk + i, o = lr (per block)
   float *dst = a.partials + ((int64_t)part * njob + job) * 128 * 128;
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < 8; ++n)
+    for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dst[((2 * wave + m) * 16 + 4 * lk + i) * 128 + n * 16 + lr] = acc[m][n][i];
+      for (int i = 0; i < 4; ++i)
+        dst[((4 * wm + m) * 16 + 4 * lk + i) * 128 + (4 * wn + n) * 16 + lr] = acc[m][n][i];
 }
 
 // dw[layout] = sum over partitions, fixed order
@@ -160,61 +198,64 @@ __global__ __launch_bounds__(256) void colsum_kernel(const T *dy, const SlotGeo 
   }
 }
 
-__device__ float pe_t_val(int t) {
-  float d[14], mean = 0.f;
-  for (int k = 0; k < 14; ++k) {
+__device__ __forceinline__ float pe_t_val(int t) {
+  // standardised distance (in symbols) to the nearest DMRS symbol; statistics over the 14 symbols
+  auto dist = [](int k) {
     int x = k - NRX_DMRS0, y = k - NRX_DMRS1;
     x = x < 0 ? -x : x;
     y = y < 0 ? -y : y;
-    d[k] = (float)(x < y ? x : y);
-    mean += d[k];
-  }
-  mean /= 14.f;
-  float var = 0.f;
-  for (int k = 0; k < 14; ++k) var += (d[k] - mean) * (d[k] - mean);
-  return (d[t] - mean) / sqrtf(var / 14.f);
+    return (float)(x < y ? x : y);
+  };
+  float mean = 0.f, var = 0.f;
+#pragma unroll
+  for (int k = 0; k < 14; ++k) mean += dist(k);
+  mean *= (1.f / 14.f);
+#pragma unroll
+  for (int k = 0; k < 14; ++k) var += (dist(k) - mean) * (dist(k) - mean);
+  return (dist(t) - mean) / sqrtf(var * (1.f / 14.f));
 }
 
-// Bias gradient (sum of all classes) and, for layers with a folded PE, the PE
-// weight gradients.  One thread per output channel o.
-__global__ void bias_pe_kernel(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total,
-                               int pe_ch, float *dw) {
-  const int o = threadIdx.x;
-  float cs[14][6];
-  for (int t = 0; t < 14; ++t)
-    for (int c = 0; c < 6; ++c) {
-      double s = 0.0;
-      for (int sl = 0; sl < n_slots; ++sl) s += partial[((int64_t)sl * 14 + t) * 768 + c * 128 + o];
-      cs[t][c] = (float)s;
-    }
-  double b = 0.0;
-  for (int t = 0; t < 14; ++t)
-    for (int c = 0; c < 6; ++c) b += cs[t][c];
-  dw[bias_off + o] = (float)b;
+// Sum of the per-slot class column sums over slots (fixed order): red[t][768].
+__global__ void colsum_reduce_kernel(const float *partial, int n_slots, float *red) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;   // t * 768 + class * 128 + o
+  if (e >= 14 * 768) return;
+  const int t = e / 768, k = e % 768;
+  double s = 0.0;
+  for (int sl = 0; sl < n_slots; ++sl) s += partial[((int64_t)sl * 14 + t) * 768 + k];
+  red[e] = (float)s;
+}
+
+// Bias gradient (sum of all classes; block 9) and, for layers with a folded PE,
+// the PE weight gradients of tap blockIdx.x (blocks 0..8).  Thread = output channel.
+__global__ void bias_pe_kernel(const float *red, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
+                               float *dw) {
+  const int o = threadIdx.x, tap = blockIdx.x;
+  if (tap == 9) {
+    double b = 0.0;
+    for (int k = 0; k < 14 * 6; ++k) b += red[k * 128 + o];
+    dw[bias_off + o] = (float)b;
+    return;
+  }
   if (pe_w_off < 0) return;
-  for (int i = 0; i < 3; ++i) {
-    const int di = i - 1;
-    for (int j = 0; j < 3; ++j) {
-      const int dj = j - 1;
-      double gt = 0.0, gf = 0.0;
-      for (int t = 0; t < 14; ++t) {
-        const int tt = t + dj;
-        if (tt < 0 || tt >= 14) continue;
-        const float pt = pe_t_val(tt);
-        for (int par = 0; par < 2; ++par)
-          for (int edge = 0; edge < 3; ++edge) {
-            if ((edge == 1 && di < 0) || (edge == 2 && di > 0)) continue;
-            const float pf = ((par + di) & 1) ? 1.f : -1.f;
-            const float v = cs[t][par * 3 + edge];
-            gt += (double)v * pt;
-            gf += (double)v * pf;
-          }
+  const int di = tap / 3 - 1, dj = tap % 3 - 1;
+  double gt = 0.0, gf = 0.0;
+  for (int t = 0; t < 14; ++t) {
+    const int tt = t + dj;
+    if (tt < 0 || tt >= 14) continue;
+    const float pt = pe_t_val(tt);
+    for (int par = 0; par < 2; ++par) {
+      const float pf = ((par + di) & 1) ? 1.f : -1.f;
+      for (int edge = 0; edge < 3; ++edge) {
+        if ((edge == 1 && di < 0) || (edge == 2 && di > 0)) continue;
+        const double v = red[t * 768 + (par * 3 + edge) * 128 + o];
+        gt += v * pt;
+        gf += v * pf;
       }
-      const int64_t w = pe_w_off + ((int64_t)(i * 3 + j) * cin_total + pe_ch) * 128 + o;
-      dw[w] = (float)gt;
-      dw[w + 128] = (float)gf;
     }
   }
+  const int64_t w = pe_w_off + ((int64_t)tap * cin_total + pe_ch) * 128 + o;
+  dw[w] = (float)gt;
+  dw[w + 128] = (float)gf;
 }
 
 // LayerNorm parameter gradients from per-workgroup partials [n][256].
@@ -504,7 +545,10 @@ void launch_colsum(const T *dy, const SlotGeo *geo, int n_slots, float *partial,
 }
 void launch_bias_pe(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
                     float *dw, hipStream_t st) {
-  hipLaunchKernelGGL(bias_pe_kernel, dim3(1), dim3(128), 0, st, partial, n_slots, bias_off, pe_w_off, cin_total,
+  // the reduced table lives right after the per-slot partials
+  float *red = const_cast<float *>(partial) + (int64_t)n_slots * 14 * 768;
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((14 * 768 + 255) / 256), dim3(256), 0, st, partial, n_slots, red);
+  hipLaunchKernelGGL(bias_pe_kernel, dim3(10), dim3(128), 0, st, (const float *)red, bias_off, pe_w_off, cin_total,
                      pe_ch, dw);
 }
 void launch_ln_reduce(const float *part, int n, int64_t g_off, int64_t b_off, float *dw, hipStream_t st) {

@@ -17,20 +17,21 @@
 
 namespace {
 
-__device__ float pe_t_value(int t) {
-  float mean = 0.f;
-  float d[14];
-  for (int k = 0; k < 14; ++k) {
-    int a = k - NRX_DMRS0, b = k - NRX_DMRS1;
-    a = a < 0 ? -a : a;
-    b = b < 0 ? -b : b;
-    d[k] = (float)(a < b ? a : b);
-    mean += d[k];
-  }
-  mean /= 14.f;
-  float var = 0.f;
-  for (int k = 0; k < 14; ++k) var += (d[k] - mean) * (d[k] - mean);
-  return (d[t] - mean) / sqrtf(var / 14.f);
+__device__ __forceinline__ float pe_t_value(int t) {
+  // standardised distance (in symbols) to the nearest DMRS symbol; statistics over the 14 symbols
+  auto dist = [](int k) {
+    int x = k - NRX_DMRS0, y = k - NRX_DMRS1;
+    x = x < 0 ? -x : x;
+    y = y < 0 ? -y : y;
+    return (float)(x < y ? x : y);
+  };
+  float mean = 0.f, var = 0.f;
+#pragma unroll
+  for (int k = 0; k < 14; ++k) mean += dist(k);
+  mean *= (1.f / 14.f);
+#pragma unroll
+  for (int k = 0; k < 14; ++k) var += (dist(k) - mean) * (dist(k) - mean);
+  return (dist(t) - mean) / sqrtf(var * (1.f / 14.f));
 }
 
 template <typename T>

@@ -275,7 +275,7 @@ struct nrx_model {
   void *pinned_bjobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
   // conv kernel variant per layer class (autotuned; indices into kConvVariants)
-  int conv_variant[NRX_K_NCLASS] = {0, 0, 0, 0, 0, 0, 0};
+  int conv_variant[NRX_K_NCLASS] = {1, 1, 1, 1, 1, 1, 1};
   // per-class event timing (diagnostics)
   bool profile = false;
   struct Ev { int cls; hipEvent_t a, b; };
@@ -508,7 +508,7 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.dm1 = o; o += act;
     L.dr = o; o += act;
     L.wpart = o; o = align256(o + (size_t)WGRAD_PARTS * 9 * 2 * 128 * 128 * 4);
-    L.cpart = o; o = align256(o + (size_t)P->n * 14 * 768 * 4);
+    L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
     L.rpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 1032 * 4);
   }

@@ -238,3 +238,23 @@ def test_nrx_backward_bf16_close_to_oracle():
     # bf16 stores activations and gradients with 8 significant bits; the bound is a regression bound on the
     # mixed-precision training gradient (direction within a few degrees), not a parity claim
     _grad_case(1, 0.12, 0.99)
+
+
+def test_training_reduces_loss():
+    """A short run of the training loop (GPU slots, BCE, backward, Adam) learns: the BCE falls from ln 2."""
+    from paper_2409_02912_amd.train import Trainer
+    log("training: workload t, 400 steps")
+    tr = Trainer(synth.WORKLOADS["t"], L.NRX_BF16, seed=5, lr=1e-3)
+    try:
+        first = None
+        for k in range(400):
+            tr.train_step()
+            if k == 0:
+                torch.cuda.synchronize()
+                first = tr.loss.item()
+        torch.cuda.synchronize()
+        last, ber = tr.loss.item(), tr.nerr.item() / tr.n_bits
+        log(f"  loss {first:.3f} -> {last:.3f}, ber {ber:.3f}")
+        assert first > 0.6 and last < 0.55 and ber < 0.3
+    finally:
+        tr.close()
