@@ -258,3 +258,17 @@ def test_training_reduces_loss():
         assert first > 0.6 and last < 0.55 and ber < 0.3
     finally:
         tr.close()
+
+
+def test_trained_nrx_beats_lmmse():
+    """The trained network (committed weights, 12k steps of workload t) against LS + LMMSE on held-out slots."""
+    import os
+    from paper_2409_02912_amd.train import evaluate
+    path = os.path.join(os.path.dirname(L.LIB_PATH), "weights", "nrx_t.npy")
+    w = np.load(path, allow_pickle=False)
+    log("trained NRX vs LS+LMMSE: workload t, 5 dB, held-out seed")
+    r = evaluate(w, synth.WORKLOADS["t"], seed=777, batches=8, snr_db=5.0)
+    b1, b2, n = r["ber_nrx"], r["ber_lmmse"], r["n_bits"]
+    sd = np.sqrt(b2 * (1 - b2) / n)
+    log(f"  BER nrx {b1:.4f}  lmmse {b2:.4f}  bits {n}")
+    assert b1 < b2 - 5 * sd
