@@ -38,11 +38,9 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
   const int lr = lane & 15, lk = lane >> 4;
   const int wm = wave >> 1, wn = wave & 1;   // 2 x 2 wave grid over the 128 x 128 block
   constexpr int KF = mma<T>::KF;            // K rows per 16-byte fragment
-  // XCD-aware job order: consecutive logical ids (same XCD) share a partition
-  const int G = gridDim.x;
-  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  // one round of workgroups: block -> (partition, job); every block has the same amount of rows
   const int njob = a.n_taps * a.n_slices;
-  const int part = lb / njob, job = lb % njob;
+  const int part = blockIdx.x / njob, job = blockIdx.x % njob;
   const int tap = a.tap0 + job / a.n_slices, slice = job % a.n_slices;
   const int di = tap / 3 - 1, dj = tap % 3 - 1;
   const T *src;
@@ -61,58 +59,75 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
   const int t0 = (int)((int64_t)a.n_tiles * part / a.n_part);
   const int t1 = (int)((int64_t)a.n_tiles * (part + 1) / a.n_part);
 
-  // the (tile, row offset) steps of this partition, walked in order
-  int ti = t0, k0 = 0;
-  auto load = [&](int tix, int kk, WgStage<T> &stg) {
+  // cursor over the 64-row steps of the partition; tile geometry kept in registers
+  struct Cur {
+    int ti, k0, nrows, row0, U, S;
+    int64_t base;
+  };
+  auto set_tile = [&](Cur &c, int ti) {
+    c.ti = ti;
+    c.k0 = 0;
+    if (ti < t1) {
+      const Tile tl = a.tiles[ti];
+      const SlotGeo &g = a.geo[tl.slot];
+      c.nrows = tl.nrows;
+      c.row0 = tl.row0;
+      c.U = g.U;
+      c.S = g.S;
+      c.base = g.row_base;
+    }
+  };
+  auto next = [&](Cur &c) {
+    c.k0 += RS;
+    if (c.k0 >= c.nrows) set_tile(c, c.ti + 1);
+  };
+  auto load = [&](const Cur &c, WgStage<T> &stg) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int e = 0; e < 8; ++e) { stg.x[q][e] = 0.f; stg.d[q][e] = 0.f; }
-    const Tile tl = a.tiles[tix];
-    const SlotGeo g = a.geo[tl.slot];
-    const int U = g.U, S = g.S, rps = 14 * U;
+    if (c.ti >= t1) return;
+    const int rps = 14 * c.U;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = kk + 4 * rg + q;
-      if (r < tl.nrows) {
-        const int R = tl.row0 + r;
-        const int s = R / rps, t = (R - s * rps) / U;
-        const int64_t grow = g.row_base + R;
+      const int r = c.k0 + 4 * rg + q;
+      if (r < c.nrows) {
+        const int R = c.row0 + r;
+        const int s = R / rps, t = (R - s * rps) / c.U;
+        const int64_t grow = c.base + R;
         pack8<T>::load(a.dy + grow * NRX_D + 8 * cg, stg.d[q]);
         const int sn = s + di, tn = t + dj;
-        if (sn >= 0 && sn < S && tn >= 0 && tn < 14 && 8 * cg < cwidth)
-          pack8<T>::load(src + (grow + di * rps + dj * U) * cs + coff + 8 * cg, stg.x[q]);
+        if (sn >= 0 && sn < c.S && tn >= 0 && tn < 14 && 8 * cg < cwidth)
+          pack8<T>::load(src + (grow + di * rps + dj * c.U) * cs + coff + 8 * cg, stg.x[q]);
       }
     }
   };
   auto store = [&](int b, const WgStage<T> &stg) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      T xv[4], dv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) { xv[q] = elem<T>::from_f(stg.x[q][e]); dv[q] = elem<T>::from_f(stg.d[q][e]); }
       T *xp = &xt[b][(8 * cg + e) * TP + 4 * rg];
       T *dp = &dt[b][(8 * cg + e) * TP + 4 * rg];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) { xp[q] = xv[q]; dp[q] = dv[q]; }
+      for (int q = 0; q < 4; ++q) { xp[q] = elem<T>::from_f(stg.x[q][e]); dp[q] = elem<T>::from_f(stg.d[q][e]); }
     }
   };
-  auto advance = [&](int &tix, int &kk) {
-    kk += RS;
-    if (kk >= a.tiles[tix].nrows) { ++tix; kk = 0; }
-  };
 
-  if (ti < t1) {
-    WgStage<T> stg;
-    load(ti, k0, stg);
-    int b = 0;
-    store(b, stg);
+  // pipeline: LDS buffer b holds step k; registers hold steps k+1 (stg[1-p]) and k+2 (being loaded)
+  Cur c0, c1, c2;
+  set_tile(c0, t0);
+  if (c0.ti < t1) {
+    c1 = c0;
+    next(c1);
+    c2 = c1;
+    if (c2.ti < t1) next(c2);
+    WgStage<T> s0, s1;
+    load(c0, s0);
+    store(0, s0);
+    load(c1, s1);
     __syncthreads();
-    while (ti < t1) {
-      int nti = ti, nk = k0;
-      advance(nti, nk);
-      const bool more = nti < t1;
-      if (more) load(nti, nk, stg);          // next step in flight during the MFMAs
+    int b = 0;
+    while (c0.ti < t1) {
+      load(c2, s0);                              // step k+2 in flight
 #pragma unroll
       for (int f = 0; f < RS / KF; ++f) {
         v16 bfr[4];
@@ -126,11 +141,17 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
           for (int n = 0; n < 4; ++n) acc[m][n] = mma<T>::run(af, bfr[n], acc[m][n]);
         }
       }
-      if (more) store(b ^ 1, stg);
+      if (c1.ti < t1) store(b ^ 1, s1);          // step k+1 into the other buffer
       __syncthreads();
       b ^= 1;
-      ti = nti;
-      k0 = nk;
+      c0 = c1;
+      c1 = c2;
+      if (c2.ti < t1) next(c2);
+      // rotate register stages: s1 <- s0 (step k+2 becomes k+1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) { s1.x[q][e] = s0.x[q][e]; s1.d[q][e] = s0.d[q][e]; }
     }
   }
   // partial [part][job][c 128][o 128]; D layout: lane holds c = 4*lk + i, o = lr (per block)

@@ -469,7 +469,7 @@ struct FwdLayout {
   size_t total;
 };
 
-constexpr int WGRAD_PARTS = 64;       // row partitions of the weight-gradient kernel (multiple of 8)
+constexpr int WGRAD_PARTS = 512;      // bound on row partitions of the weight-gradient kernel
 constexpr int BWD_GRID_MAX = 4096;    // bound on per-workgroup partial buffers
 
 FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
@@ -507,7 +507,7 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.dmsg = o; o += act;
     L.dm1 = o; o += act;
     L.dr = o; o += act;
-    L.wpart = o; o = align256(o + (size_t)WGRAD_PARTS * 9 * 2 * 128 * 128 * 4);
+    L.wpart = o; o = align256(o + (size_t)2 * num_cu() * 128 * 128 * 4);   // partitions x jobs <= 2 blocks per CU
     L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
     L.rpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 1032 * 4);
@@ -849,13 +849,14 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.geo = D.geo;
     a.tiles = D.ct[ti256];
     a.n_tiles = (int)P->ct[ti256].size();
-    a.n_part = WGRAD_PARTS;
     a.n_taps = conv ? 9 : 1;
     a.tap0 = conv ? 0 : 4;
     a.n_slices = (c0 + c1 + 127) / 128;
+    // one round of workgroups (2 per CU), all with the same number of rows
+    a.n_part = std::max(1, std::min(WGRAD_PARTS, (2 * num_cu()) / (a.n_taps * a.n_slices)));
     a.partials = wpart;
     launch_wgrad<T>(a, st);
-    launch_wgrad_reduce(wpart, WGRAD_PARTS, a.n_taps, a.tap0, a.n_slices, cin_real, cin_total, conv ? 1 : 0, dst, dw,
+    launch_wgrad_reduce(wpart, a.n_part, a.n_taps, a.tap0, a.n_slices, cin_real, cin_total, conv ? 1 : 0, dst, dw,
                         st);
   };
   auto bias = [&](const T *dy, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch) {
