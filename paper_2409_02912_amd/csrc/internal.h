@@ -29,9 +29,9 @@ struct ConvArgs {
 struct ConvVariant {
   int mb;     // MFMA m-blocks (16 rows) per wave: tile = 64 * mb rows
   int occ;    // waves per SIMD the kernel is built for
-  int pref;   // weights prefetched one tap ahead
+  int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS
 };
-#define NRX_CONV_VARIANTS 4
+#define NRX_CONV_VARIANTS 5
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
 
 template <typename T>

@@ -26,6 +26,10 @@
 #include "common.h"
 #include "internal.h"
 
+#ifndef NRX_LDS_MB
+#define NRX_LDS_MB 6
+#endif
+
 namespace {
 
 constexpr int ROWB = 64;   // bytes per LDS row (one 64-byte K chunk of one activation row)
@@ -40,6 +44,127 @@ __host__ __device__ constexpr int halo_rows_max(int tile_rows) {
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
+
+// Epilogue of one tile: bias (+ PE field) -> store | LayerNorm + ReLU | residual
+// add | LayerNorm backward.  Lane owns channels 8*lr .. +7 of rows 4*lk + i.
+template <typename T, int MB, int EPI>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &tl, const SlotGeo &g,
+                                              f32x4_t (&acc)[MB][8], int wave, int lr, int lk, float *lnp) {
+  const int U = g.U, S = g.S, rps = 14 * U;
+  const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
+  if constexpr (EPI == EPI_LN_BWD) {
+    // acc = dL/da with a = ReLU(LN(z)); resid holds a, save_z holds z, save_stats (mean, rstd).
+    // dz = rstd (dzhat - mean(dzhat) - zhat mean(dzhat zhat)), dzhat = g * dn, dn = da [a > 0]
+    float gam[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) gam[nb] = a.ln_g[ch0 + nb];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+        const bool valid = r < tl.nrows;
+        const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
+        float av[8], zv[8];
+        pack8<T>::load(a.resid + grow * NRX_D + ch0, av);
+        pack8<T>::load(a.save_z + grow * NRX_D + ch0, zv);
+        const float mean = a.save_stats[2 * grow], rstd = a.save_stats[2 * grow + 1];
+        float dn[8], zh[8], dzh[8], s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          dn[nb] = (valid && av[nb] > 0.f) ? acc[mb][nb][i] : 0.f;
+          zh[nb] = (zv[nb] - mean) * rstd;
+          dzh[nb] = dn[nb] * gam[nb];
+          s1 += dzh[nb];
+          s2 += dzh[nb] * zh[nb];
+          lnp[nb] += dn[nb] * zh[nb];
+          lnp[8 + nb] += dn[nb];
+        }
+        s1 = row_sum16(s1) * (1.0f / NRX_D);
+        s2 = row_sum16(s2) * (1.0f / NRX_D);
+        float dz[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) dz[nb] = rstd * (dzh[nb] - s1 - zh[nb] * s2);
+        if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, dz);
+      }
+    }
+    return;
+  }
+  float bias[8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+      const bool valid = r < tl.nrows;
+      const int R = tl.row0 + (valid ? r : 0);
+      const int s = R / rps;
+      const int rem = R - s * rps;
+      const int t = rem / U, u = rem - (rem / U) * U;
+      const int64_t grow = g.row_base + R;
+      float v[8];
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
+      if (a.pe) {
+        int par = (s - (u >> 1)) & 1;
+        int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
+        const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
+      }
+      if constexpr (EPI == EPI_LN_RELU) {
+        float sm = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) sm += v[nb];
+        const float mean = row_sum16(sm) * (1.0f / NRX_D);
+        float sq = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
+        const float var = row_sum16(sq) * (1.0f / NRX_D);
+        const float rstd = 1.0f / sqrtf(var + 1e-5f);
+        if (valid && a.save_z) {
+          pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
+          if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
+        }
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
+          v[nb] = n > 0.f ? n : 0.f;
+        }
+      } else if constexpr (EPI == EPI_RESID) {
+        float rsd[8];
+        if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
+      }
+      if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
+    }
+  }
+}
+
+// Final dgamma/dbeta reduction of the LayerNorm-backward epilogue (after the tile loop).
+template <int EPI>
+__device__ __forceinline__ void conv_ln_reduce(float *lnp, float *red, float *out, int tid, int wave, int lr, int lk) {
+  if constexpr (EPI == EPI_LN_BWD) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lnp[k] += __shfl_xor(lnp[k], 16, 64);
+      lnp[k] += __shfl_xor(lnp[k], 32, 64);
+    }
+    __syncthreads();
+    if (lk == 0) {
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        red[wave * 256 + 8 * lr + nb] = lnp[nb];
+        red[wave * 256 + 128 + 8 * lr + nb] = lnp[8 + nb];
+      }
+    }
+    __syncthreads();
+    out[(int64_t)blockIdx.x * 256 + tid] = red[tid] + red[256 + tid] + red[512 + tid] + red[768 + tid];
+  }
+}
 
 template <typename T, int MB, int EPI, int OCC, bool PREF>
 __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
@@ -173,118 +298,178 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
       }
     }
 
-    // ---------------------------------------------------------- epilogue --
-    const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
-    if constexpr (EPI == EPI_LN_BWD) {
-      // acc = dL/da with a = ReLU(LN(z)); resid holds a, save_z holds z, save_stats (mean, rstd).
-      // dz = rstd (dzhat - mean(dzhat) - zhat mean(dzhat zhat)), dzhat = g * dn, dn = da [a > 0]
-      float gam[8];
+    conv_epilogue<T, MB, EPI>(a, tl, g, acc, wave, lr, lk, lnp);
+  }
+  conv_ln_reduce<EPI>(lnp, reinterpret_cast<float *>(&lds[0][0]), a.ln_part, tid, wave, lr, lk);
+}
+
+
+// Variant with both MFMA operands in LDS.  Tiles of 64*MB rows (MB m-blocks per
+// wave; MB = 6 is the largest without register spills), one wave per SIMD.  Per 64-byte K chunk the halo block is DMA'd once;
+// the weights of each group of three taps (one tap row di) are DMA'd into a
+// two-slot ring one group ahead, so the MFMA loop reads only LDS.  Every wave
+// issues a fixed number of halo DMA instructions, which lets the wait for the
+// next weight group (issued first) leave the halo loads in flight
+// (s_waitcnt vmcnt(APW)).  The next tile's first chunk is prefetched during the
+// last group of the current one.
+template <typename T, int EPI, int MB>
+__global__ __launch_bounds__(256, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
+  constexpr int TILE = 64 * MB;
+  constexpr int HMAX = halo_rows_max(TILE);
+  constexpr int NINS = HMAX / 16;                  // halo DMA instructions per chunk
+  constexpr int APW = (NINS + 3) / 4;              // per wave (fixed)
+  constexpr int AROWS = APW * 4 * 16;              // rows written per chunk (>= HMAX)
+  constexpr int ZROW = AROWS;                      // all-zero row
+  constexpr int KC = 64 / (int)sizeof(T);
+  constexpr int BROWS = 3 * 8 * 16;                // 64-byte weight rows per 3-tap group
+  constexpr int BPW = BROWS / 16 / 4;              // weight DMA instructions per wave per group
+  static_assert(APW < 16, "vmcnt immediate below");
+  __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
+  __shared__ __align__(16) unsigned char lds_b[2][BROWS * ROWB];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  if (tid < 8) {
+    v16 z = {{0, 0, 0, 0}};
+    st16(&lds_a[tid >> 2][ZROW * ROWB + (tid & 3) * 16], z);
+  }
+  const int cin = a.c0 + a.c1;
+  const int nch = cin / KC;
+  float lnp[EPI == EPI_LN_BWD ? 16 : 1];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) gam[nb] = a.ln_g[ch0 + nb];
+  for (int k = 0; k < (EPI == EPI_LN_BWD ? 16 : 1); ++k) lnp[k] = 0.f;
+
+  const int G = gridDim.x;
+  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+
+  // weight buffer resource (bounds unchecked: offsets are within the layer's block)
+  const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc((void *)a.w, 0, 0x7FFFFFFF, 0x00020000);
+  auto stage_b = [&](int c, int grp, int slot) {
+    const uint32_t base = (uint32_t)((c * 9 + 3 * grp) * 8 * 16) * ROWB;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
-          const bool valid = r < tl.nrows;
-          const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
-          float av[8], zv[8];
-          pack8<T>::load(a.resid + grow * NRX_D + ch0, av);
-          pack8<T>::load(a.save_z + grow * NRX_D + ch0, zv);
-          const float mean = a.save_stats[2 * grow], rstd = a.save_stats[2 * grow + 1];
-          float dn[8], zh[8], dzh[8], s1 = 0.f, s2 = 0.f;
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) {
-            dn[nb] = (valid && av[nb] > 0.f) ? acc[mb][nb][i] : 0.f;
-            zh[nb] = (zv[nb] - mean) * rstd;
-            dzh[nb] = dn[nb] * gam[nb];
-            s1 += dzh[nb];
-            s2 += dzh[nb] * zh[nb];
-            lnp[nb] += dn[nb] * zh[nb];
-            lnp[8 + nb] += dn[nb];
-          }
-          s1 = row_sum16(s1) * (1.0f / NRX_D);
-          s2 = row_sum16(s2) * (1.0f / NRX_D);
-          float dz[8];
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) dz[nb] = rstd * (dzh[nb] - s1 - zh[nb] * s2);
-          if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, dz);
-        }
-      }
-      continue;
+    for (int j = 0; j < BPW; ++j) {
+      const int ins = wave + 4 * j;
+      const int row = ins * 16 + (lane >> 2);
+      const int piece = (lane & 3) ^ swz(row);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (lds_void *)&lds_b[slot][ins * 16 * ROWB], 16,
+                                                base + row * ROWB + piece * 16, 0, 0, 0);
     }
-    float bias[8];
+  };
+  // halo of chunk c of a tile described by (row_base, rel0, halo, S, rps)
+  struct Geo {
+    int64_t row_base;
+    int rel0, halo, S, rps, U, s_first;
+  };
+  auto geo_of = [&](const Tile &tl, const SlotGeo &g) {
+    Geo q;
+    q.U = g.U;
+    q.S = g.S;
+    q.rps = 14 * g.U;
+    q.s_first = tl.row0 / q.rps;
+    const int s_last = (tl.row0 + tl.nrows - 1) / q.rps;
+    q.halo = (s_last - q.s_first + 3) * q.rps;
+    q.rel0 = (q.s_first - 1) * q.rps;
+    q.row_base = g.row_base;
+    return q;
+  };
+  auto stage_a = [&](const Geo &q, int c, int b) {
+    const T *src;
+    int cs, coff;
+    if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
+    else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
+    const T *base = src + q.row_base * cs + coff;
+    const int nrec = q.S * q.rps * cs * (int)sizeof(T);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, nrec, 0x00020000);
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
+    for (int j = 0; j < APW; ++j) {
+      const int ins = wave + 4 * j;
+      const int h = ins * 16 + (lane >> 2);
+      const int piece = (lane & 3) ^ swz(h);
+      // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
+      const uint32_t voff = h < q.halo ? (uint32_t)((q.rel0 + h) * cs * (int)sizeof(T) + piece * 16) : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)&lds_a[b][ins * 16 * ROWB], 16, voff, 0, 0, 0);
+    }
+  };
+  constexpr int WAIT_ALL = 0;
+  constexpr int WAIT_KEEP_A = (0xF << 8) | (7 << 4) | APW;   // vmcnt <= APW, no wait on lgkm/exp
+
+  int ka = 0, kb = 0;   // running halo-buffer and weight-slot counters
+  int tile = lb;
+  if (tile < a.n_tiles) {
+    const Tile t0 = a.tiles[tile];
+    const Geo q0 = geo_of(t0, a.geo[t0.slot]);
+    stage_b(0, 0, 0);
+    stage_a(q0, 0, 0);
+    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    __syncthreads();
+  }
+  for (; tile < a.n_tiles; tile += G) {
+    const Tile tl = a.tiles[tile];
+    const SlotGeo g = a.geo[tl.slot];
+    const Geo q = geo_of(tl, g);
+    int hc[MB], tt[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
+      const int r = wave * 16 * MB + mb * 16 + lr;
+      const int R = tl.row0 + r;
+      const int s = R / q.rps;
+      tt[mb] = r < tl.nrows ? (R - s * q.rps) / q.U : -1;
+      hc[mb] = R - q.rel0;
+    }
+    f32x4_t acc[MB][8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
-        const bool valid = r < tl.nrows;
-        const int R = tl.row0 + (valid ? r : 0);
-        const int s = R / rps;
-        const int rem = R - s * rps;
-        const int t = rem / U, u = rem - (rem / U) * U;
-        const int64_t grow = g.row_base + R;
-        float v[8];
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
-        if (a.pe) {
-          int par = (s - (u >> 1)) & 1;
-          int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
-          const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
-        }
-        if constexpr (EPI == EPI_LN_RELU) {
-          float sm = 0.f;
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) sm += v[nb];
-          const float mean = row_sum16(sm) * (1.0f / NRX_D);
-          float sq = 0.f;
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
-          const float var = row_sum16(sq) * (1.0f / NRX_D);
-          const float rstd = 1.0f / sqrtf(var + 1e-5f);
-          if (valid && a.save_z) {
-            pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
-            if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
-          }
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) {
-            float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
-            v[nb] = n > 0.f ? n : 0.f;
-          }
-        } else if constexpr (EPI == EPI_RESID) {
-          float rsd[8];
-          if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
-        }
-        if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
+      for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int ngrp = 3 * nch;
+    const int next_tile = tile + G;
+    for (int k = 0; k < ngrp; ++k) {
+      const int c = k / 3, grp = k - 3 * c;
+      bool a_issued = false;
+      if (k + 1 < ngrp) {
+        stage_b((k + 1) / 3, (k + 1) % 3, (kb + 1) & 1);
+        if (grp == 0 && c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); a_issued = true; }
+      } else if (next_tile < a.n_tiles) {
+        // prefetch the next tile's first chunk and weight group
+        const Tile tn = a.tiles[next_tile];
+        const Geo qn = geo_of(tn, a.geo[tn.slot]);
+        stage_b(0, 0, (kb + 1) & 1);
+        stage_a(qn, 0, (ka + 1) & 1);
+        a_issued = true;
       }
-    }
-  }
-  if constexpr (EPI == EPI_LN_BWD) {
-    // reduce over the 4 row groups of a wave, then over the 4 waves (fixed order)
+      const unsigned char *la = &lds_a[ka & 1][0];
+      const unsigned char *lbw = &lds_b[kb & 1][0];
+      const int di = grp - 1;
+#pragma unroll 1
+      for (int tj = 0; tj < 3; ++tj) {
+        const int dj = tj - 1;
+        const int off = di * q.rps + dj * q.U;
+        v16 af[MB];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      lnp[k] += __shfl_xor(lnp[k], 16, 64);
-      lnp[k] += __shfl_xor(lnp[k], 32, 64);
-    }
-    __syncthreads();
-    float *red = reinterpret_cast<float *>(&lds[0][0]);   // [4 waves][256]
-    if (lk == 0) {
+        for (int mb = 0; mb < MB; ++mb) {
+          const bool ok = tt[mb] >= 0 && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
+          const int row = ok ? hc[mb] + off : ZROW;
+          af[mb] = ld16(la + row * ROWB + ((lk ^ swz(row)) << 4));
+        }
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) {
-        red[wave * 256 + 8 * lr + nb] = lnp[nb];
-        red[wave * 256 + 128 + 8 * lr + nb] = lnp[8 + nb];
+        for (int nb = 0; nb < 8; ++nb) {
+          const int brow = (tj * 8 + nb) * 16 + lr;
+          const v16 bf = ld16(lbw + brow * ROWB + ((lk ^ swz(brow)) << 4));
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(af[mb], bf, acc[mb][nb]);
+        }
       }
+      // the next weight group must have landed; a halo load issued after it may stay in flight
+      if (a_issued && grp == 0 && k + 1 < ngrp) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
+      else __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+      __syncthreads();
+      kb += 1;
+      if (grp == 2) ka += 1;
     }
-    __syncthreads();
-    a.ln_part[(int64_t)blockIdx.x * 256 + tid] = red[tid] + red[256 + tid] + red[512 + tid] + red[768 + tid];
+    conv_epilogue<T, MB, EPI>(a, tl, g, acc, wave, lr, lk, lnp);
   }
+  conv_ln_reduce<EPI>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
 }
 
 }  // namespace
@@ -296,6 +481,7 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {4, 2, 0},   // 256-row tiles, 2 waves/SIMD, no prefetch
     {2, 2, 1},   // 128-row tiles, 2 waves/SIMD, prefetch
     {2, 2, 0},   // 128-row tiles, 2 waves/SIMD, no prefetch
+    {NRX_LDS_MB, 1, 2},   // 384-row tiles, 1 wave/SIMD, weights and halo both through LDS
 };
 
 template <typename T>
@@ -318,6 +504,13 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_CONV_CASE(2, 2, 2, true)
   NRX_CONV_CASE(3, 2, 2, false)
 #undef NRX_CONV_CASE
+  if (variant == 4) {
+    constexpr int M = NRX_LDS_MB;
+    if (epi == EPI_STORE) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_STORE, M>), dim3(grid), blk, 0, st, a);
+    else if (epi == EPI_LN_RELU) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_RELU, M>), dim3(grid), blk, 0, st, a);
+    else if (epi == EPI_RESID) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_RESID, M>), dim3(grid), blk, 0, st, a);
+    else hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_BWD, M>), dim3(grid), blk, 0, st, a);
+  }
 }
 
 template void launch_conv<float>(const ConvArgs<float> &, int, int, int, hipStream_t);

@@ -48,9 +48,9 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 namespace {
 
 constexpr int MLP_TILE = 128;
-constexpr int N_TILE_SIZES = 2;            // conv tiles of 128 and 256 rows (MB = 2, 4)
-inline int tile_size_index(int mb) { return mb == 2 ? 0 : 1; }
-inline int tile_rows_of_index(int i) { return i == 0 ? 128 : 256; }
+constexpr int N_TILE_SIZES = 3;            // conv tiles of 128, 256 and 384 rows (MB = 2, 4, 6)
+inline int tile_size_index(int mb) { return mb == 2 ? 0 : (mb == 4 ? 1 : 2); }
+inline int tile_rows_of_index(int i) { return 128 * (i + 1); }
 
 struct TensorInfo {
   std::string name;
@@ -89,7 +89,7 @@ struct Plan {
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
   // device table blob
-  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
+  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
   ~Plan() {

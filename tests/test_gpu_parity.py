@@ -135,7 +135,7 @@ def test_nrx_forward_single_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=(0, 1, 2, 3))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=(0, 1, 2, 3, 4))
 
 
 def test_bce_and_adam_match_oracle():
@@ -182,12 +182,12 @@ def test_bce_and_adam_match_oracle():
     assert np.allclose(tv.cpu().numpy(), ev, rtol=1e-6, atol=1e-7)
 
 
-def _grad_case(prec, tol, cos_min, seed=21):
+def _grad_case(prec, tol, cos_min, seed=21, variant=1):
     shapes = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
               dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 2], slot_number=2)]
     m_max = 4
     net = cgnn.NetConfig(4, 128, 3, 1, m_max)
-    log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R}")
+    log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R} conv variant {variant}")
     ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
     w = synth.he_weights(cgnn.layout(net), seed, perturb=True)
     W = cgnn.unflatten(w.astype(np.float64), net)
@@ -210,6 +210,7 @@ def _grad_case(prec, tol, cos_min, seed=21):
         ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
         dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
         wt = dev(w)
+        L.set_all_conv_variants(model, variant)
         L.nrx_forward(model, wt, descs, y, llr, ws, save_acts=True)
         L.nrx_backward(model, wt, descs, dev(dllr_np), dw, ws)
         torch.cuda.synchronize()
@@ -230,8 +231,9 @@ def _grad_case(prec, tol, cos_min, seed=21):
         L.nrx_model_destroy(model)
 
 
-def test_nrx_backward_fp32_matches_oracle():
-    _grad_case(0, 1e-4, 0.9999999)
+@pytest.mark.parametrize("variant", [1, 4])
+def test_nrx_backward_fp32_matches_oracle(variant):
+    _grad_case(0, 1e-4, 0.9999999, variant=variant)
 
 
 def test_nrx_backward_bf16_close_to_oracle():
