@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
+    ap.add_argument("--variant-sweep", action="store_true", help="time every conv variant per layer class")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -117,6 +118,22 @@ def main():
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         steps = args.steps if name == "bf16" else args.fp32_steps
         warm = args.warmup if name == "bf16" else 1
+        if args.variant_sweep:
+            sweep = {}
+            for v in range(L.nrx_conv_variant(model, L.NRX_K_CONV_B)[1]):
+                L.set_all_conv_variants(model, v)
+                L.nrx_forward(model, dw, descs, y, llr, ws)
+                torch.cuda.synchronize()
+                L.nrx_profile_enable(model, True)
+                for c in range(len(L.KERNEL_CLASSES)):
+                    L.nrx_profile_read(model, c, reset=True)
+                for _ in range(3):
+                    L.nrx_forward(model, dw, descs, y, llr, ws)
+                sweep[v] = {L.KERNEL_CLASSES[c]: round(L.nrx_profile_read(model, c)[0] / 3 /
+                                                       max(1, L.nrx_profile_read(model, c)[1] / 3), 4)
+                            for c in L.CONV_CLASSES}
+                L.nrx_profile_enable(model, False)
+            results.setdefault("sweep", {})[name] = sweep
         if not args.no_autotune:
             L.nrx_autotune(model, dw, descs, y, llr, ws)
         results.setdefault("variants", {})[name] = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0]
@@ -226,6 +243,7 @@ def main():
         "llr_rel_err_bf16_vs_fp32": rel_llr,
         "lmmse_ms": lmmse_ms,
         "conv_variants": results.get("variants"),
+        "conv_variant_sweep_ms": results.get("sweep"),
         "kernels_bf16": results["bf16"]["kernels"],
         "batch1_latency_ms": {k: results[k]["batch1_ms"] for k in llrs},
         "roofline": {"bound": "mfma", "kernel": "conv3x3_kernel (residual conv_b, bf16)", "achieved": achieved / 1e12,

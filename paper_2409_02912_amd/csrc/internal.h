@@ -27,11 +27,11 @@ struct ConvArgs {
 };
 
 struct ConvVariant {
-  int mb;     // MFMA m-blocks (16 rows) per wave: tile = 64 * mb rows
+  int mb;     // tile = 64 * mb rows (MFMA m-blocks per wave for 4-wave workgroups)
   int occ;    // waves per SIMD the kernel is built for
   int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS
 };
-#define NRX_CONV_VARIANTS 5
+#define NRX_CONV_VARIANTS 6
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
 
 template <typename T>

@@ -145,7 +145,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
 }
 
 // Final dgamma/dbeta reduction of the LayerNorm-backward epilogue (after the tile loop).
-template <int EPI>
+template <int EPI, int NW>
 __device__ __forceinline__ void conv_ln_reduce(float *lnp, float *red, float *out, int tid, int wave, int lr, int lk) {
   if constexpr (EPI == EPI_LN_BWD) {
 #pragma unroll
@@ -162,7 +162,12 @@ __device__ __forceinline__ void conv_ln_reduce(float *lnp, float *red, float *ou
       }
     }
     __syncthreads();
-    out[(int64_t)blockIdx.x * 256 + tid] = red[tid] + red[256 + tid] + red[512 + tid] + red[768 + tid];
+    if (tid < 256) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += red[w * 256 + tid];
+      out[(int64_t)blockIdx.x * 256 + tid] = v;
+    }
   }
 }
 
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
 
     conv_epilogue<T, MB, EPI>(a, tl, g, acc, wave, lr, lk, lnp);
   }
-  conv_ln_reduce<EPI>(lnp, reinterpret_cast<float *>(&lds[0][0]), a.ln_part, tid, wave, lr, lk);
+  conv_ln_reduce<EPI, 4>(lnp, reinterpret_cast<float *>(&lds[0][0]), a.ln_part, tid, wave, lr, lk);
 }
 
 
@@ -312,17 +317,17 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
 // next weight group (issued first) leave the halo loads in flight
 // (s_waitcnt vmcnt(APW)).  The next tile's first chunk is prefetched during the
 // last group of the current one.
-template <typename T, int EPI, int MB>
-__global__ __launch_bounds__(256, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
-  constexpr int TILE = 64 * MB;
+template <typename T, int EPI, int MB, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
+  constexpr int TILE = 16 * MB * NW;
   constexpr int HMAX = halo_rows_max(TILE);
   constexpr int NINS = HMAX / 16;                  // halo DMA instructions per chunk
-  constexpr int APW = (NINS + 3) / 4;              // per wave (fixed)
-  constexpr int AROWS = APW * 4 * 16;              // rows written per chunk (>= HMAX)
+  constexpr int APW = (NINS + NW - 1) / NW;       // per wave (fixed)
+  constexpr int AROWS = APW * NW * 16;             // rows written per chunk (>= HMAX)
   constexpr int ZROW = AROWS;                      // all-zero row
   constexpr int KC = 64 / (int)sizeof(T);
   constexpr int BROWS = 3 * 8 * 16;                // 64-byte weight rows per 3-tap group
-  constexpr int BPW = BROWS / 16 / 4;              // weight DMA instructions per wave per group
+  constexpr int BPW = BROWS / 16 / NW;             // weight DMA instructions per wave per group
   static_assert(APW < 16, "vmcnt immediate below");
   __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
   __shared__ __align__(16) unsigned char lds_b[2][BROWS * ROWB];
@@ -348,7 +353,7 @@ __global__ __launch_bounds__(256, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
     const uint32_t base = (uint32_t)((c * 9 + 3 * grp) * 8 * 16) * ROWB;
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
-      const int ins = wave + 4 * j;
+      const int ins = wave + NW * j;
       const int row = ins * 16 + (lane >> 2);
       const int piece = (lane & 3) ^ swz(row);
       __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (lds_void *)&lds_b[slot][ins * 16 * ROWB], 16,
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, nrec, 0x00020000);
 #pragma unroll
     for (int j = 0; j < APW; ++j) {
-      const int ins = wave + 4 * j;
+      const int ins = wave + NW * j;
       const int h = ins * 16 + (lane >> 2);
       const int piece = (lane & 3) ^ swz(h);
       // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(256, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
     }
     conv_epilogue<T, MB, EPI>(a, tl, g, acc, wave, lr, lk, lnp);
   }
-  conv_ln_reduce<EPI>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
+  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
 }
 
 }  // namespace
@@ -482,6 +487,7 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {2, 2, 1},   // 128-row tiles, 2 waves/SIMD, prefetch
     {2, 2, 0},   // 128-row tiles, 2 waves/SIMD, no prefetch
     {NRX_LDS_MB, 1, 2},   // 384-row tiles, 1 wave/SIMD, weights and halo both through LDS
+    {8, 2, 2},            // 512-row tiles of 8 waves (4 m-blocks each), 2 waves/SIMD, operands through LDS
 };
 
 template <typename T>
@@ -504,13 +510,20 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_CONV_CASE(2, 2, 2, true)
   NRX_CONV_CASE(3, 2, 2, false)
 #undef NRX_CONV_CASE
-  if (variant == 4) {
-    constexpr int M = NRX_LDS_MB;
-    if (epi == EPI_STORE) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_STORE, M>), dim3(grid), blk, 0, st, a);
-    else if (epi == EPI_LN_RELU) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_RELU, M>), dim3(grid), blk, 0, st, a);
-    else if (epi == EPI_RESID) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_RESID, M>), dim3(grid), blk, 0, st, a);
-    else hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_BWD, M>), dim3(grid), blk, 0, st, a);
+#define NRX_LDS_CASE(V, M, NWV)                                                                       \
+  if (variant == V) {                                                                                \
+    dim3 b2(64 * NWV);                                                                               \
+    if (epi == EPI_STORE) hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_STORE, M, NWV>), dim3(grid), b2, 0, st, a); \
+    else if (epi == EPI_LN_RELU)                                                                     \
+      hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_RELU, M, NWV>), dim3(grid), b2, 0, st, a);    \
+    else if (epi == EPI_RESID)                                                                       \
+      hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_RESID, M, NWV>), dim3(grid), b2, 0, st, a);      \
+    else hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_BWD, M, NWV>), dim3(grid), b2, 0, st, a);  \
+    return;                                                                                          \
   }
+  NRX_LDS_CASE(4, NRX_LDS_MB, 4)
+  NRX_LDS_CASE(5, 4, 8)
+#undef NRX_LDS_CASE
 }
 
 template void launch_conv<float>(const ConvArgs<float> &, int, int, int, hipStream_t);

@@ -48,8 +48,8 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 namespace {
 
 constexpr int MLP_TILE = 128;
-constexpr int N_TILE_SIZES = 3;            // conv tiles of 128, 256 and 384 rows (MB = 2, 4, 6)
-inline int tile_size_index(int mb) { return mb == 2 ? 0 : (mb == 4 ? 1 : 2); }
+constexpr int N_TILE_SIZES = 4;            // conv tiles of 128, 256, 384 and 512 rows (mb = 2, 4, 6, 8)
+inline int tile_size_index(int mb) { return mb / 2 - 1; }
 inline int tile_rows_of_index(int i) { return 128 * (i + 1); }
 
 struct TensorInfo {
@@ -89,7 +89,7 @@ struct Plan {
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
   // device table blob
-  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
+  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0, 0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
   ~Plan() {
@@ -877,7 +877,8 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.save_stats = const_cast<float *>(stats);
     a.ln_part = lpart;
     a.geo = D.geo;
-    const int v = m->conv_variant[cls];
+    // the LayerNorm-backward epilogue spills in the large-tile variants: keep it on variant 1
+    const int v = epi == EPI_LN_BWD ? 1 : m->conv_variant[cls];
     const ConvVariant &cv = kConvVariants[v];
     const int ti = tile_size_index(cv.mb);
     a.tiles = D.ct[ti];

@@ -135,7 +135,7 @@ def test_nrx_forward_single_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=(0, 1, 2, 3, 4))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=(0, 1, 2, 3, 4, 5))
 
 
 def test_bce_and_adam_match_oracle():
@@ -231,7 +231,7 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1):
         L.nrx_model_destroy(model)
 
 
-@pytest.mark.parametrize("variant", [1, 4])
+@pytest.mark.parametrize("variant", [1, 4, 5])
 def test_nrx_backward_fp32_matches_oracle(variant):
     _grad_case(0, 1e-4, 0.9999999, variant=variant)
 
