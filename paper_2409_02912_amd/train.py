@@ -61,6 +61,9 @@ class Trainer:
         self.bws = torch.empty(L.nrx_bce_workspace_bytes(self.descs, self.m_max), dtype=torch.uint8, device=dev)
         self.step = 0
         self.n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in self.shapes)
+        # pick the convolution tile shapes for this batch (forward timing only)
+        L.slot_sim(self.sim, self.seed, 0, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
+        L.nrx_autotune(self.model, self.params, self.descs, self.y, self.llr, self.ws)
 
     def load(self, path):
         z = np.load(path, allow_pickle=False)
