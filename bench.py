@@ -62,6 +62,60 @@ def cpu_baseline(w, weights, net_args, budget_s):
                       f"fp64 numpy LS + CGNN forward, {t_total:.1f} s"}
 
 
+def ragged_batch(steps, no_autotune):
+    """Uneven batch of 256 slots (PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM) in BF16,
+    replayed from a captured hipGraph; per-slot latency = start of the pass to the end of the
+    slot's last readout tile, from the device wall clock."""
+    import numpy as np
+    import torch
+    from paper_2409_02912_amd import libnrx as L
+    from paper_2409_02912_amd import synth
+    w = synth.WORKLOADS["c4"]
+    shapes = synth.uniform_shapes(w)
+    m_max = w["m"]
+    descs, sz = L.make_slots(shapes, m_max)
+    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, L.NRX_BF16, flags=1)
+    try:
+        layout = [(n, s) for n, _, s in L.weight_layout(model)]
+        dw = torch.from_numpy(synth.he_weights(layout, 0)).cuda()
+        cfg = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
+                           rho=w["rho"], snr_db_lo=w["snr"][0], snr_db_hi=w["snr"][1])
+        y = torch.empty(2 * sz["y"], dtype=torch.float32, device="cuda")
+        sws = torch.empty(L.slot_sim_workspace_bytes(cfg, descs), dtype=torch.uint8, device="cuda")
+        L.slot_sim(cfg, 0, 0, descs, m_max, y, sws)
+        del sws
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
+        if not no_autotune:
+            L.nrx_autotune(model, dw, descs, y, llr, ws)
+        lat = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            L.nrx_forward(model, dw, descs, y, llr, ws)      # first call captures the graph
+        torch.cuda.synchronize()
+        lats = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        total = 0.0
+        for _ in range(steps):
+            e0.record()
+            L.nrx_forward(model, dw, descs, y, llr, ws)
+            e1.record()
+            L.nrx_slot_latency(model, descs, ws, lat)
+            torch.cuda.synchronize()
+            total += e0.elapsed_time(e1)
+            lats.append(lat.cpu().numpy().copy())
+        ms = total / steps
+        v = np.concatenate(lats)
+        res = sum(12 * s["n_prb"] * 14 for s in shapes)
+        return {"workload": f"{len(shapes)} uneven slots: PRB 4-273, 1-4 UE, 4/8/16 ant, QPSK..256-QAM, bf16, "
+                            f"hipGraph replay",
+                "slots_per_s": len(shapes) / (ms * 1e-3), "res_per_s": res / (ms * 1e-3), "ms_per_step": ms,
+                "steps": steps, "latency_us_p50": float(np.percentile(v, 50)),
+                "latency_us_p99": float(np.percentile(v, 99)),
+                "conv_variants": {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}}
+    finally:
+        L.nrx_model_destroy(model)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +128,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
     ap.add_argument("--variant-sweep", action="store_true", help="time every conv variant per layer class")
+    ap.add_argument("--ragged-steps", type=int, default=5,
+                    help="timed replays of the uneven 256-slot batch under a hipGraph (0: skip)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -254,6 +310,8 @@ def main():
         out["fp32"] = {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
                        "ms_per_step": results["fp32"]["ms_per_step"], "kernels": results["fp32"]["kernels"]}
         out["speedup_bf16_vs_fp32"] = results["fp32"]["ms_per_step"] / ms
+    if args.ragged_steps > 0:
+        out["ragged"] = ragged_batch(args.ragged_steps, args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)

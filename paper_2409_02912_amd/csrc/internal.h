@@ -78,9 +78,16 @@ struct MlpArgs {
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;
+  unsigned int *slot_done;        // readout: finished tiles per slot (zeroed by launch_stamp_start)
+  unsigned long long *stamps;     // readout: wall-clock time at which each slot's last tile finished
 };
 template <typename T>
 void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st);
+// Zeroes the per-slot tile counters and records the start time in stamps[n_slots].
+void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, int n_slots, hipStream_t st);
+// latency_us[i] = (stamps[i] - stamps[n]) / rate
+void launch_stamp_latency(const unsigned long long *stamps, int n_slots, double ticks_per_us, float *latency_us,
+                          hipStream_t st);
 template <typename T>
 void launch_readout(const MlpArgs<T> &a, int grid, hipStream_t st);
 

@@ -209,10 +209,33 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
         }
     }
     __syncthreads();   // LDS reads done before the next tile overwrites it
+    if (a.slot_done && tid == 0) {
+      // the workgroup that finishes a slot's last readout tile stamps its completion time
+      __threadfence();
+      const int per_slot = (S * 14 * U + MLP_ROWS - 1) / MLP_ROWS;
+      if (atomicAdd(&a.slot_done[tl.slot], 1u) + 1u == (unsigned)per_slot) a.stamps[tl.slot] = wall_clock64();
+    }
   }
 }
 
+__global__ void stamp_start_kernel(unsigned int *slot_done, unsigned long long *stamps, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) slot_done[i] = 0u;
+  if (threadIdx.x == 0) stamps[n] = wall_clock64();
+}
+
+__global__ void stamp_latency_kernel(const unsigned long long *stamps, int n, double ticks_per_us, float *lat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lat[i] = (float)((double)(long long)(stamps[i] - stamps[n]) / ticks_per_us);
+}
+
 }  // namespace
+
+void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, int n, hipStream_t st) {
+  hipLaunchKernelGGL(stamp_start_kernel, dim3(1), dim3(256), 0, st, slot_done, stamps, n);
+}
+void launch_stamp_latency(const unsigned long long *stamps, int n, double ticks_per_us, float *lat, hipStream_t st) {
+  hipLaunchKernelGGL(stamp_latency_kernel, dim3((n + 255) / 256), dim3(256), 0, st, stamps, n, ticks_per_us, lat);
+}
 
 template <typename T>
 void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st) {

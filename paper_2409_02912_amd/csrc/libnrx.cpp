@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/libnrx.h"
@@ -254,6 +255,20 @@ int num_cu() {
   return g_num_cu;
 }
 
+// captured forward launch sequences, keyed by batch plan and buffer addresses
+struct GraphKey {
+  const void *plan, *w, *y, *h, *llr, *ws;
+  bool save;
+  bool operator<(const GraphKey &o) const {
+    return std::tie(plan, w, y, h, llr, ws, save) < std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save);
+  }
+};
+
+struct Graphs {
+  hipStream_t cap = nullptr;
+  std::map<GraphKey, hipGraphExec_t> execs;
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------- model --
@@ -274,6 +289,7 @@ struct nrx_model {
   int64_t bprep_elems = 0;
   void *pinned_bjobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
+  Graphs *graphs = nullptr;        // captured forward graphs (flags bit 0)
   // conv kernel variant per layer class (autotuned; indices into kConvVariants)
   int conv_variant[NRX_K_NCLASS] = {1, 1, 1, 1, 1, 1, 1};
   // per-class event timing (diagnostics)
@@ -430,6 +446,11 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
 
 extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
   if (!m) return fail(NRX_ERR_INVALID, "null model");
+  if (m->graphs) {
+    for (auto &kv : m->graphs->execs) (void)hipGraphExecDestroy(kv.second);
+    if (m->graphs->cap) (void)hipStreamDestroy(m->graphs->cap);
+    delete m->graphs;
+  }
   if (m->pinned_bjobs) (void)hipHostFree(m->pinned_bjobs);
   for (auto &e : m->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : m->pool) (void)hipEventDestroy(e);
@@ -457,7 +478,7 @@ extern "C" nrx_status nrx_weight_tensor(const nrx_model *m, int32_t idx, char *n
 namespace {
 
 struct FwdLayout {
-  size_t meta, jobs, wprep, fields, dmrs, pairs, X;
+  size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps;
   std::vector<size_t> h;      // h_0 .. h_C (inference: one buffer)
   std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
   std::vector<size_t> stats;  // per block (training)
@@ -484,6 +505,8 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   L.dmrs = o; o = align256(o + (size_t)P->dmrs_total * 8);
   L.pairs = o; o = align256(o + (size_t)P->pairs_total * 8);
   L.X = o; o = align256(o + (size_t)P->rows * m->cx * ts);
+  L.done = o; o = align256(o + (size_t)P->n * 4);
+  L.stamps = o; o = align256(o + (size_t)(P->n + 1) * 8);
   const int C = m->cfg.n_blocks, R = m->cfg.n_rounds;
   if (!save) {
     L.h.push_back(o); o += act;
@@ -563,6 +586,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   float2 *dmrs = (float2 *)(ws + L.dmrs);
   float2 *pairs = (float2 *)(ws + L.pairs);
   T *X = (T *)(ws + L.X);
+  launch_stamp_start((unsigned int *)(ws + L.done), (unsigned long long *)(ws + L.stamps), P->n, st);
   {
     ProfMark pm(m, NRX_K_FRONTEND, st);
     launch_prep<T>(w, (const PrepJob *)(ws + L.jobs), (int)m->jobs.size(), m->prep_total, wprep, fields, st);
@@ -653,6 +677,8 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   ra.geo = D.geo;
   ra.tiles = D.rt;
   ra.n_tiles = (int)P->rt.size();
+  ra.slot_done = (unsigned int *)(ws + L.done);
+  ra.stamps = (unsigned long long *)(ws + L.stamps);
   {
     ProfMark pm(m, NRX_K_READOUT, st);
     launch_readout<T>(ra, grid_mlp, st);
@@ -661,6 +687,11 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   return NRX_OK;
 }
 
+}  // namespace
+
+namespace {
+template <typename F>
+nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipStream_t st);
 }  // namespace
 
 extern "C" size_t nrx_workspace_bytes(nrx_model *m, const nrx_slot_desc *slots, int32_t n, int32_t save_acts) {
@@ -679,16 +710,78 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
   if (s != NRX_OK) return s;
   const FwdLayout L = fwd_layout(m, P, save_acts != 0);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
-  if (m->cfg.precision == NRX_FP32)
-    s = forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, st);
-  else
-    s = forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, st);
+  auto run = [&](hipStream_t s2) {
+    if (m->cfg.precision == NRX_FP32) return forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2);
+    return forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2);
+  };
+  if ((m->cfg.flags & 1) && !m->profile) {
+    // replay the whole launch sequence from a graph captured once per (batch, buffers)
+    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0}, run, st);
+  } else {
+    s = run(st);
+  }
   if (s == NRX_OK && save_acts) {
     std::lock_guard<std::mutex> lk(m->mu);
     m->saved_ws = ws;
     m->saved_plan = P;
   }
   return s;
+}
+
+namespace {
+template <typename F>
+nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipStream_t st) {
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(m->mu);
+    if (!m->graphs) m->graphs = new Graphs();
+    auto it = m->graphs->execs.find(key);
+    if (it != m->graphs->execs.end()) exec = it->second;
+  }
+  if (!exec) {
+    // host-side allocations happen before the capture
+    nrx_status ps = model_pinned(m);
+    if (ps != NRX_OK) return ps;
+    {
+      std::lock_guard<std::mutex> lk(g_plans.mu);
+      if (!P->pinned) {
+        if (hipHostMalloc(&P->pinned, P->meta_bytes, hipHostMallocDefault) != hipSuccess)
+          return fail(NRX_ERR_HIP, "hipHostMalloc failed");
+        memcpy(P->pinned, P->blob.data(), P->meta_bytes);
+      }
+    }
+    if (!m->graphs->cap) HIPCHK(hipStreamCreateWithFlags(&m->graphs->cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(m->graphs->cap, hipStreamCaptureModeThreadLocal));
+    nrx_status s = run(m->graphs->cap);
+    hipError_t e = hipStreamEndCapture(m->graphs->cap, &graph);
+    if (s != NRX_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+    if (e != hipSuccess) return fail(NRX_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(NRX_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lk(m->mu);
+    m->graphs->execs[key] = exec;
+  }
+  HIPCHK(hipGraphLaunch(exec, st));
+  return NRX_OK;
+}
+}  // namespace
+
+extern "C" nrx_status nrx_slot_latency(nrx_model *m, const nrx_slot_desc *slots, int32_t n, const void *ws,
+                                       float *latency_us, hipStream_t st) {
+  if (!m || !ws || !latency_us) return fail(NRX_ERR_INVALID, "null argument");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const FwdLayout L = fwd_layout(m, P, false);
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(NRX_ERR_HIP, "wall clock rate unavailable");
+  launch_stamp_latency((const unsigned long long *)((const char *)ws + L.stamps), P->n, khz / 1000.0, latency_us, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
 }
 
 extern "C" nrx_status nrx_profile_enable(nrx_model *m, int32_t enable) {

@@ -78,6 +78,7 @@ _SIGS = {
     "nrx_profile_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "nrx_autotune": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _sz, ctypes.c_char_p, _vp]),
     "nrx_conv_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "nrx_slot_latency": (_i32, [_vp, _DESC, _i32, _vp, _vp, _vp]),
     "nrx_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -284,3 +285,8 @@ CONV_CLASSES = (NRX_K_CONV_IN, NRX_K_CONV_A, NRX_K_CONV_A_MP, NRX_K_CONV_B)
 def set_all_conv_variants(model, variant):
     for c in CONV_CLASSES:
         nrx_conv_variant(model, c, variant)
+
+
+def nrx_slot_latency(model, slots, ws, latency_us, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_slot_latency(model, arr, n, _ptr(ws), _ptr(latency_us), _stream(stream)))

@@ -16,6 +16,9 @@ WORKLOADS = {
                snr=(5.0, 30.0), d=128, n_blocks=8, n_rounds=3),
     "c5": dict(n_slots=64, n_prb=106, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
                snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
+    # uneven batch: per slot PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM (ragged_shapes)
+    "c4": dict(n_slots=256, ragged=True, n_prb=273, n_ant=16, n_ue=4, m=8, n_taps=12, decay_ns=487.42,
+               doppler=0.0, rho=0.0, snr=(0.0, 30.0), d=128, n_blocks=6, n_rounds=2),
     # small training workload (learning test: trains in about a minute)
     "t": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
               snr=(0.0, 15.0), d=128, n_blocks=2, n_rounds=1),
@@ -56,5 +59,7 @@ def ragged_shapes(n_slots, seed, max_prb=273, ants=(4, 8, 16), mods=(2, 4, 6, 8)
 
 def uniform_shapes(w, n_slots=None, n_prb=None):
     n = n_slots or w["n_slots"]
+    if w.get("ragged"):
+        return ragged_shapes(n, 0, max_prb=n_prb or w["n_prb"])
     return [dict(n_prb=n_prb or w["n_prb"], n_ant=w["n_ant"], n_ue=w["n_ue"], bits=[w["m"]] * w["n_ue"],
                  slot_number=i % 20) for i in range(n)]

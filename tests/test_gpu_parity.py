@@ -274,3 +274,111 @@ def test_trained_nrx_beats_lmmse():
     sd = np.sqrt(b2 * (1 - b2) / n)
     log(f"  BER nrx {b1:.4f}  lmmse {b2:.4f}  bits {n}")
     assert b1 < b2 - 5 * sd
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_graph_replay_matches_eager(prec, tol):
+    """Model flag bit 0: the forward pass captured once and replayed on new inputs in the same
+    buffers gives the eager result on every replay, with unrelated eager work in between."""
+    shapes = [s for s in RAGGED if s["n_ant"] <= 8]
+    net, m_max = cgnn.NetConfig(8, 128, 3, 2, 6), 6
+    w = synth.he_weights(cgnn.layout(net), 5, perturb=True)
+    eager = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+    graph = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec, flags=1)
+    try:
+        descs, sz = L.make_slots(shapes, m_max)
+        wd = dev(w)
+        y = torch.zeros(2 * sz["y"], dtype=torch.float32, device="cuda")
+        llr_e = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        llr_g = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws_e = ws_tensor(L.nrx_workspace_bytes(eager, descs))
+        ws_g = ws_tensor(L.nrx_workspace_bytes(graph, descs))
+        for rep in range(4):
+            log(f"graph replay {rep}: prec={prec}")
+            ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 11, rep, m_max)
+            y.copy_(torch.from_numpy(pack_complex([r["y32"] for r in ref_slots])))
+            llr_g.fill_(float("nan"))
+            L.nrx_forward(graph, wd, descs, y, llr_g, ws_g)
+            junk = torch.randn(1 << 20, device="cuda")
+            junk = (junk * 2).sum()
+            torch.cuda.synchronize()
+            L.nrx_forward(eager, wd, descs, y, llr_e, ws_e)
+            torch.cuda.synchronize()
+            assert torch.equal(llr_g, llr_e), f"replay {rep} differs from the eager pass"
+            if rep in (0, 3):
+                exp = oracle_nrx(w, net, ref_slots)
+                got = split_llr(llr_g.cpu().numpy(), shapes, m_max)
+                for i in range(len(shapes)):
+                    check_llr(got[i], exp[i], tol)
+    finally:
+        L.nrx_model_destroy(eager)
+        L.nrx_model_destroy(graph)
+
+
+def test_slot_latency_stamps():
+    """Per-slot completion times from the readout kernel lie inside the forward pass."""
+    shapes = synth.ragged_shapes(24, 0, max_prb=64)
+    m_max = max(max(s["bits"]) for s in shapes)
+    n_ant = max(s["n_ant"] for s in shapes)
+    model = L.nrx_model_create(n_ant, 128, 2, 1, m_max, 1)
+    try:
+        descs, sz = L.make_slots(shapes, m_max)
+        w = synth.he_weights([(n, sh) for n, _, sh in L.weight_layout(model)], 1)
+        y = torch.randn(2 * sz["y"], dtype=torch.float32, device="cuda")
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        lat = torch.full((len(shapes),), -1.0, dtype=torch.float32, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        L.nrx_forward(model, dev(w), descs, y, llr, ws)
+        torch.cuda.synchronize()
+        e0.record()
+        L.nrx_forward(model, dev(w), descs, y, llr, ws)
+        e1.record()
+        L.nrx_slot_latency(model, descs, ws, lat)
+        torch.cuda.synchronize()
+        total_us = e0.elapsed_time(e1) * 1e3
+        v = lat.cpu().numpy()
+        log(f"slot latency us: min {v.min():.1f} max {v.max():.1f}, forward {total_us:.1f}")
+        assert np.all(np.isfinite(v)) and np.all(v > 0)
+        assert v.max() <= total_us * 1.05 + 20.0
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_autograd_function_gradient():
+    """NrxFunction: torch autograd through the hand-written backward equals nrx_backward, and a
+    central finite difference of the fp32 GPU forward along a random direction matches the
+    gradient's directional derivative."""
+    from paper_2409_02912_amd.autograd import Nrx
+    shapes = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 4], slot_number=s) for s in range(4)]
+    net, m_max = cgnn.NetConfig(4, 128, 2, 1, 4), 4
+    w = synth.he_weights(cgnn.layout(net), 7, perturb=True)
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 7, 0, m_max)
+    y = dev(pack_complex([r["y32"] for r in ref_slots]))
+    nrx = Nrx(net.B, net.d, net.C, net.R, m_max, 0, shapes)
+    try:
+        rng = np.random.default_rng(7)
+        r = dev(rng.standard_normal(nrx.sizes["llr"]).astype(np.float32))
+        wt = dev(w).requires_grad_(True)
+        llr = nrx(wt, y)
+        (llr * r).sum().backward()
+        g = wt.grad.detach().clone()
+        # direct call on the same saved activations
+        g2 = torch.empty_like(g)
+        L.nrx_backward(nrx.model, wt.detach(), nrx.slots, r, g2, nrx.ws)
+        torch.cuda.synchronize()
+        assert torch.equal(g, g2)
+        v = rng.standard_normal(w.size)
+        v /= np.linalg.norm(v)
+        eps = 1e-3 * float(np.linalg.norm(w))
+        rn = r.double().cpu().numpy()
+
+        def loss(wv):
+            with torch.no_grad():
+                return float(np.dot(nrx(dev(wv.astype(np.float32)), y).double().cpu().numpy(), rn))
+        fd = (loss(w + eps * v) - loss(w - eps * v)) / (2 * eps)
+        an = float(np.dot(g.double().cpu().numpy(), v))
+        log(f"directional derivative: analytic {an:.6e} finite difference {fd:.6e} (eps {eps:.2e})")
+        assert abs(fd - an) <= 2e-2 * abs(an) + 1e-6
+    finally:
+        nrx.close()
