@@ -62,7 +62,7 @@ def cpu_baseline(w, weights, net_args, budget_s):
                       f"fp64 numpy LS + CGNN forward, {t_total:.1f} s"}
 
 
-def ragged_batch(steps, no_autotune):
+def ragged_batch(steps, no_autotune, tune_cache=None):
     """Uneven batch of 256 slots (PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM) in BF16,
     replayed from a captured hipGraph; per-slot latency = start of the pass to the end of the
     slot's last readout tile, from the device wall clock."""
@@ -87,7 +87,7 @@ def ragged_batch(steps, no_autotune):
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         if not no_autotune:
-            L.nrx_autotune(model, dw, descs, y, llr, ws)
+            L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=tune_cache)
         lat = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
         for _ in range(2):
             L.nrx_forward(model, dw, descs, y, llr, ws)      # first call captures the graph
@@ -116,6 +116,10 @@ def ragged_batch(steps, no_autotune):
         L.nrx_model_destroy(model)
 
 
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,9 +131,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 pass")
     ap.add_argument("--variant-sweep", action="store_true", help="time every conv variant per layer class")
     ap.add_argument("--ragged-steps", type=int, default=5,
                     help="timed replays of the uneven 256-slot batch under a hipGraph (0: skip)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache (JSON lines): reuse its tile-shape choices, append new ones")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain elementwise copy kernel over this many MiB (HBM-counter calibration)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,6 +152,15 @@ def main():
     from paper_2409_02912_amd import libnrx as L
     from paper_2409_02912_amd import synth
     from oracle import cgnn  # layout names only (weights are drawn by synth)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes n floats
+        torch.cuda.synchronize()
+        del src, dst
 
     w = synth.WORKLOADS[args.workload]
     shapes = synth.uniform_shapes(w)
@@ -163,17 +181,29 @@ def main():
     n0 = torch.empty(n_slots, dtype=torch.float32, device="cuda")
     sws = torch.empty(L.slot_sim_workspace_bytes(cfg, descs), dtype=torch.uint8, device="cuda")
     L.slot_sim(cfg, 0, 0, descs, m_max, y, sws, bits=bits, n0=n0)
+    # FP8 activation scales are calibrated on a different batch of the same workload
+    y_cal = None
+    if not args.no_fp8:
+        y_cal = torch.empty_like(y)
+        L.slot_sim(cfg, 0, 1, descs, m_max, y_cal, sws)
     del sws
 
     results = {}
     llrs = {}
-    passes = ((L.NRX_BF16, "bf16"),) if args.bf16_only else ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32"))
+    passes = [(L.NRX_BF16, "bf16")]
+    if not args.no_fp8:
+        passes.append((L.NRX_FP8, "fp8"))
+    if not args.bf16_only:
+        passes.append((L.NRX_FP32, "fp32"))
     for prec, name in passes:
         model = L.nrx_model_create(*net_args, prec)
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
-        steps = args.steps if name == "bf16" else args.fp32_steps
-        warm = args.warmup if name == "bf16" else 1
+        if name == "fp8":
+            L.nrx_calibrate(model, dw, descs, y_cal, llr, ws)
+            results.setdefault("fp8_scales", L.nrx_act_scales(model).tolist())
+        steps = args.fp32_steps if name == "fp32" else args.steps
+        warm = 1 if name == "fp32" else args.warmup
         if args.variant_sweep:
             sweep = {}
             for v in range(L.nrx_conv_variant(model, L.NRX_K_CONV_B)[1]):
@@ -191,7 +221,7 @@ def main():
                 L.nrx_profile_enable(model, False)
             results.setdefault("sweep", {})[name] = sweep
         if not args.no_autotune:
-            L.nrx_autotune(model, dw, descs, y, llr, ws)
+            L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=args.tune_cache)
         results.setdefault("variants", {})[name] = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0]
                                                     for c in L.CONV_CLASSES}
         for _ in range(warm):
@@ -213,6 +243,7 @@ def main():
             kern[cname] = {"ms_per_launch": t / max(n, 1), "launches_per_step": n / steps}
         L.nrx_profile_enable(model, False)
         results[name] = {"ms_per_step": ms, "kernels": kern}
+        progress(f"{name}: {ms:.3f} ms/step")
         llrs[name] = llr
         if args.bf16_only:
             results[name]["batch1_ms"] = None
@@ -225,7 +256,7 @@ def main():
         for _ in range(3):
             L.nrx_forward(model, dw, d1, y, l1, ws1)
         torch.cuda.synchronize()
-        reps = 20 if name == "bf16" else 3
+        reps = 3 if name == "fp32" else 20
         e0.record()
         for _ in range(reps):
             L.nrx_forward(model, dw, d1, y, l1, ws1)
@@ -259,11 +290,15 @@ def main():
         b32 = ber["fp32"]
         tol = max(0.05 * b32, 3 * math.sqrt(max(b32 * (1 - b32), 1e-30) / n_bits))
         ber["matched"] = abs(ber["bf16"] - b32) <= tol
+        if "fp8" in ber:
+            ber["fp8_matched"] = abs(ber["fp8"] - b32) <= tol
         ber["tolerance"] = tol
         rel_llr = (torch.linalg.vector_norm(llrs["bf16"] - llrs["fp32"]) /
                    torch.linalg.vector_norm(llrs["fp32"])).item()
+        rel_llr8 = ((torch.linalg.vector_norm(llrs["fp8"] - llrs["fp32"]) /
+                     torch.linalg.vector_norm(llrs["fp32"])).item() if "fp8" in llrs else None)
     else:
-        rel_llr = None
+        rel_llr = rel_llr8 = None
     ber["n_bits"] = n_bits
 
     S = 12 * w["n_prb"]
@@ -297,6 +332,7 @@ def main():
         "tflops": fpr * rows / (ms * 1e-3) / 1e12,
         "ber": ber,
         "llr_rel_err_bf16_vs_fp32": rel_llr,
+        "llr_rel_err_fp8_vs_fp32": rel_llr8,
         "lmmse_ms": lmmse_ms,
         "conv_variants": results.get("variants"),
         "conv_variant_sweep_ms": results.get("sweep"),
@@ -306,12 +342,23 @@ def main():
                      "peak": PEAKS["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"],
                      "traffic": None},
     }
+    if "fp8" in results:
+        ms8 = results["fp8"]["ms_per_step"]
+        cb8 = results["fp8"]["kernels"]["conv_b"]["ms_per_launch"]
+        out["fp8"] = {"slots_per_s": n_slots / (ms8 * 1e-3), "ms_per_step": ms8, "res_per_s": n_slots * S * 14 / (ms8 * 1e-3),
+                      "speedup_vs_bf16": ms / ms8, "kernels": results["fp8"]["kernels"],
+                      "act_scales": results.get("fp8_scales"),
+                      "conv_b_roofline": {"bound": "mfma", "achieved": conv_flops / (cb8 * 1e-3) / 1e12,
+                                          "peak": PEAKS["fp8"] / 1e12, "unit": "TFLOP/s",
+                                          "frac": conv_flops / (cb8 * 1e-3) / PEAKS["fp8"]}}
     if "fp32" in results:
         out["fp32"] = {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
                        "ms_per_step": results["fp32"]["ms_per_step"], "kernels": results["fp32"]["kernels"]}
         out["speedup_bf16_vs_fp32"] = results["fp32"]["ms_per_step"] / ms
+    progress("ber done")
     if args.ragged_steps > 0:
-        out["ragged"] = ragged_batch(args.ragged_steps, args.no_autotune)
+        out["ragged"] = ragged_batch(args.ragged_steps, args.no_autotune, args.tune_cache)
+    progress("uneven batch done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)

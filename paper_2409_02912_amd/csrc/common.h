@@ -79,6 +79,27 @@ __host__ __device__ __forceinline__ int swz(int h) { return (h >> 1) & 3; }
 // channels of each of its rows.
 __host__ __device__ __forceinline__ int nperm(int nb, int j) { return 8 * j + nb; }
 
+// FP8 (OCP E4M3) MFMA, 16x16x128, unit block scales: lane l holds 32 bytes of
+// A row l%16 and of B column l%16 for k-group l/16; A and B use the same
+// k order, so any pairing of operand bytes with input channels that both sides
+// share gives the dot product.
+__device__ __forceinline__ f32x4_t mfma_fp8(const i32x8_t &a, const i32x8_t &b, f32x4_t c) {
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+
+// 8 floats -> 8 E4M3 bytes of x * inv (saturated to the finite range +-448)
+__device__ __forceinline__ uint2 fp8x8(const float *x, float inv) {
+  float q[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) q[k] = fminf(fmaxf(x[k] * inv, -448.f), 448.f);
+  int lo = 0, hi = 0;
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[0], q[1], lo, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(q[2], q[3], lo, true);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[4], q[5], hi, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(q[6], q[7], hi, true);
+  return make_uint2((unsigned)lo, (unsigned)hi);
+}
+
 __device__ __forceinline__ float shfl_xor16(float v, int m) { return __shfl_xor(v, m, 64); }
 
 // sum over the 16 lanes that share l/16 (the lanes owning one row's channels)
@@ -140,7 +161,7 @@ struct SlotGeo {
   int64_t dmrs_off;   // complex elements into the DMRS table ([2][S/2] per slot)
 };
 
-struct Tile {
+struct __align__(16) Tile {
   int32_t slot;
   int32_t row0;       // first row within the slot
   int32_t nrows;

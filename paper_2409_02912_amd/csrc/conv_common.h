@@ -1,0 +1,238 @@
+// Device pieces shared by the convolution kernels: halo sizing, the fused
+// epilogue (bias + positional-encoding field, LayerNorm + ReLU, residual add,
+// LayerNorm backward) and the LayerNorm-backward partial-sum reduction.
+#pragma once
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int ROWB = 64;   // bytes per LDS row (one 64-byte K chunk of one activation row)
+
+__host__ __device__ constexpr int halo_rows_max(int tile_rows) {
+  int best = 0;
+  for (int U = 1; U <= 4; ++U) {
+    int v = ((tile_rows - 1) / (14 * U) + 4) * 14 * U;
+    best = v > best ? v : best;
+  }
+  return (best + 15) / 16 * 16;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Load through the constant address space: with a uniform address this becomes a
+// scalar load, which is not ordered behind outstanding vector-memory (DMA) work.
+template <typename X>
+__device__ __forceinline__ X ldc(const X *p) {
+  return *(const __attribute__((address_space(4))) X *)p;
+}
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+
+// Buffer descriptor words of a wave-uniform base address and size (raw buffer,
+// no stride; reads past nbytes return zero).
+__device__ __forceinline__ i32x4_t rsrc_words(const void *base, int nbytes) {
+  const uint64_t b = (uint64_t)base;
+  i32x4_t r;
+  r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  r.y = __builtin_amdgcn_readfirstlane((int)((b >> 32) & 0xFFFF));
+  r.z = __builtin_amdgcn_readfirstlane(nbytes);
+  r.w = 0x00020000;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+  return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const lds_void *)p);
+}
+
+// Global -> LDS copy of 16 bytes per lane (lane i writes lds + 16 i) through the
+// buffer unit.  Written as inline assembly so that the compiler's wait-count pass
+// does not tie later LDS reads of other buffers to it; the kernels order it
+// explicitly (s_waitcnt vmcnt and a barrier before the data is read).  M0 holds
+// the LDS address; these kernels use M0 for nothing else, and the s_nop covers
+// the M0-write to LDS-DMA hazard.
+__device__ __forceinline__ void dma16(const i32x4_t &rsrc, uint32_t lds, uint32_t voff) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tbuffer_load_dwordx4 %1, %2, 0 offen lds"
+               :
+               : "s"(lds), "v"(voff), "s"(rsrc)
+               : "memory");
+}
+
+// Workgroup barrier for the DMA-pipelined kernels.  __syncthreads() carries a
+// workgroup release fence, which drains every outstanding vector-memory operation,
+// including the LDS DMA deliberately left in flight across the barrier.  Here each
+// wave first waits for exactly the DMA it needs (s_waitcnt issued by the caller),
+// all LDS reads before the barrier have been consumed by MFMAs, and the signal
+// fences stop the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void dma_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// the fields of a slot's geometry the convolutions use (S, U, row_base), by scalar loads
+__device__ __forceinline__ SlotGeo ldc_geo(const SlotGeo *p) {
+  SlotGeo g{};
+  g.S = ldc(&p->S);
+  g.U = ldc(&p->U);
+  g.row_base = ldc(&p->row_base);
+  return g;
+}
+// a tile descriptor as one 16-byte scalar load (three used fields would make a
+// 12-byte load, which has no scalar form)
+__device__ __forceinline__ Tile ldc(const Tile *p) {
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  const i32x4 v = *(const __attribute__((address_space(4))) i32x4 *)p;
+  return Tile{v.x, v.y, v.z, v.w};
+}
+
+// Buffer resource of a wave-uniform base address and size, built from scalar
+// registers (a descriptor the compiler cannot prove uniform is used through a
+// per-lane loop).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *base, int nbytes) {
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), 0,
+                                           __builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+}
+
+// Epilogue of one tile: bias (+ PE field) -> store | LayerNorm + ReLU | residual
+// add | LayerNorm backward.  Lane owns channels 8*lr .. +7 of rows 4*lk + i.
+template <typename T, int MB, int EPI>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &tl, const SlotGeo &g,
+                                              f32x4_t (&acc)[MB][8], int wave, int lr, int lk, float *lnp) {
+  const int U = g.U, S = g.S, rps = 14 * U;
+  const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
+  if constexpr (EPI == EPI_LN_BWD) {
+    // acc = dL/da with a = ReLU(LN(z)); resid holds a, save_z holds z, save_stats (mean, rstd).
+    // dz = rstd (dzhat - mean(dzhat) - zhat mean(dzhat zhat)), dzhat = g * dn, dn = da [a > 0]
+    float gam[8];
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) gam[nb] = a.ln_g[ch0 + nb];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+        const bool valid = r < tl.nrows;
+        const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
+        float av[8], zv[8];
+        pack8<T>::load(a.resid + grow * NRX_D + ch0, av);
+        pack8<T>::load(a.save_z + grow * NRX_D + ch0, zv);
+        const float mean = a.save_stats[2 * grow], rstd = a.save_stats[2 * grow + 1];
+        float dn[8], zh[8], dzh[8], s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          dn[nb] = (valid && av[nb] > 0.f) ? acc[mb][nb][i] : 0.f;
+          zh[nb] = (zv[nb] - mean) * rstd;
+          dzh[nb] = dn[nb] * gam[nb];
+          s1 += dzh[nb];
+          s2 += dzh[nb] * zh[nb];
+          lnp[nb] += dn[nb] * zh[nb];
+          lnp[8 + nb] += dn[nb];
+        }
+        s1 = row_sum16(s1) * (1.0f / NRX_D);
+        s2 = row_sum16(s2) * (1.0f / NRX_D);
+        float dz[8];
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) dz[nb] = rstd * (dzh[nb] - s1 - zh[nb] * s2);
+        if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, dz);
+      }
+    }
+    return;
+  }
+  float bias[8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
+  float vmax = 0.f;   // max |output| of this lane (calibration of FP8 scales)
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+      const bool valid = r < tl.nrows;
+      const int R = tl.row0 + (valid ? r : 0);
+      const int s = R / rps;
+      const int rem = R - s * rps;
+      const int t = rem / U, u = rem - (rem / U) * U;
+      const int64_t grow = g.row_base + R;
+      float v[8];
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
+      if (a.pe) {
+        int par = (s - (u >> 1)) & 1;
+        int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
+        const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
+      }
+      if constexpr (EPI == EPI_LN_RELU) {
+        float sm = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) sm += v[nb];
+        const float mean = row_sum16(sm) * (1.0f / NRX_D);
+        float sq = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
+        const float var = row_sum16(sq) * (1.0f / NRX_D);
+        const float rstd = 1.0f / sqrtf(var + 1e-5f);
+        if (valid && a.save_z) {
+          pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
+          if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
+        }
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
+          v[nb] = n > 0.f ? n : 0.f;
+        }
+      } else if constexpr (EPI == EPI_RESID) {
+        float rsd[8];
+        if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
+      }
+      if (valid) {
+        if (a.out) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
+        if (a.out8) *reinterpret_cast<uint2 *>(a.out8 + grow * NRX_D + ch0) = fp8x8(v, a.out8_inv);
+        if (a.amax) {
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) vmax = fmaxf(vmax, fabsf(v[nb]));
+        }
+      }
+    }
+  }
+  if (a.amax) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, m, 64));
+    if (lr == 0 && lk == 0) atomicMax(a.amax, __float_as_uint(vmax));
+  }
+}
+
+// Final dgamma/dbeta reduction of the LayerNorm-backward epilogue (after the tile loop).
+template <int EPI, int NW>
+__device__ __forceinline__ void conv_ln_reduce(float *lnp, float *red, float *out, int tid, int wave, int lr, int lk) {
+  if constexpr (EPI == EPI_LN_BWD) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lnp[k] += __shfl_xor(lnp[k], 16, 64);
+      lnp[k] += __shfl_xor(lnp[k], 32, 64);
+    }
+    __syncthreads();
+    if (lk == 0) {
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) {
+        red[wave * 256 + 8 * lr + nb] = lnp[nb];
+        red[wave * 256 + 128 + 8 * lr + nb] = lnp[8 + nb];
+      }
+    }
+    __syncthreads();
+    if (tid < 256) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v += red[w * 256 + tid];
+      out[(int64_t)blockIdx.x * 256 + tid] = v;
+    }
+  }
+}
+
+}  // namespace

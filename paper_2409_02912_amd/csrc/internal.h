@@ -24,6 +24,14 @@ struct ConvArgs {
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;
+  // FP8 operands (conv3x3_fp8 kernels): E4M3 activations [rows][c0] / [rows][c1],
+  // prepped weights [chunk][tap pair][nb][16][128 B] and per-output-channel scales
+  const uint8_t *src8_0, *src8_1;
+  const uint8_t *w8;
+  const float *wscale;
+  uint8_t *out8;            // E4M3 copy of the output, out * out8_inv, or null (out may then be null)
+  float out8_inv;
+  unsigned int *amax;       // max |output| over the launch (float bits, atomicMax), or null
 };
 
 struct ConvVariant {
@@ -33,6 +41,24 @@ struct ConvVariant {
 };
 #define NRX_CONV_VARIANTS 6
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
+#define NRX_CONV8_VARIANTS 3
+extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64
+
+// FP8 convolution (EPI_LN_RELU or EPI_RESID) on E4M3 operands a.src8_*, a.w8, a.wscale.
+void launch_conv8(const ConvArgs<bf16_t> &a, int epi, int variant, int grid, hipStream_t st);
+
+// Quantisation of one conv layer's weights to E4M3 with the input activation
+// scales folded in (s0 for input channels < c0, s1 above).
+struct Fp8Job {
+  int64_t src;         // element offset of the master conv tensor [3][3][cin_total][128]
+  int32_t cin_real;    // input channels quantised (multiple of 64; PE channels excluded)
+  int32_t cin_total;
+  int32_t c0;          // channels of the first input
+  float s0, s1;        // activation scales of the two inputs
+  int64_t dst;         // byte offset of the prepped operand
+  int64_t sdst;        // float offset of the 128 weight scales
+};
+void launch_prep_fp8(const float *w, const Fp8Job *jobs, int n_jobs, uint8_t *w8, float *wscale, hipStream_t st);
 
 template <typename T>
 void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream_t st);
@@ -78,6 +104,9 @@ struct MlpArgs {
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;
+  uint8_t *out8;                  // MP: E4M3 copy of the aggregated messages (out * out8_inv) or null
+  float out8_inv;
+  unsigned int *amax;             // MP: max |aggregate| (float bits, atomicMax) or null
   unsigned int *slot_done;        // readout: finished tiles per slot (zeroed by launch_stamp_start)
   unsigned long long *stamps;     // readout: wall-clock time at which each slot's last tile finished
 };

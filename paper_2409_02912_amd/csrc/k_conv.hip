@@ -23,153 +23,17 @@
 //               the 128 channels of a row (intra-wave shuffles) -> ReLU, or a
 //               residual add; each lane owns 8 consecutive channels of a row so
 //               stores are full 16/32-byte vectors.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
+#include "conv_common.h"
 
 #ifndef NRX_LDS_MB
 #define NRX_LDS_MB 6
 #endif
 
 namespace {
-
-constexpr int ROWB = 64;   // bytes per LDS row (one 64-byte K chunk of one activation row)
-
-__host__ __device__ constexpr int halo_rows_max(int tile_rows) {
-  int best = 0;
-  for (int U = 1; U <= 4; ++U) {
-    int v = ((tile_rows - 1) / (14 * U) + 4) * 14 * U;
-    best = v > best ? v : best;
-  }
-  return (best + 15) / 16 * 16;
-}
-
-typedef __attribute__((address_space(3))) void lds_void;
-
-// Epilogue of one tile: bias (+ PE field) -> store | LayerNorm + ReLU | residual
-// add | LayerNorm backward.  Lane owns channels 8*lr .. +7 of rows 4*lk + i.
-template <typename T, int MB, int EPI>
-__device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &tl, const SlotGeo &g,
-                                              f32x4_t (&acc)[MB][8], int wave, int lr, int lk, float *lnp) {
-  const int U = g.U, S = g.S, rps = 14 * U;
-  const int ch0 = 8 * lr;          // this lane's 8 consecutive output channels
-  if constexpr (EPI == EPI_LN_BWD) {
-    // acc = dL/da with a = ReLU(LN(z)); resid holds a, save_z holds z, save_stats (mean, rstd).
-    // dz = rstd (dzhat - mean(dzhat) - zhat mean(dzhat zhat)), dzhat = g * dn, dn = da [a > 0]
-    float gam[8];
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) gam[nb] = a.ln_g[ch0 + nb];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
-        const bool valid = r < tl.nrows;
-        const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
-        float av[8], zv[8];
-        pack8<T>::load(a.resid + grow * NRX_D + ch0, av);
-        pack8<T>::load(a.save_z + grow * NRX_D + ch0, zv);
-        const float mean = a.save_stats[2 * grow], rstd = a.save_stats[2 * grow + 1];
-        float dn[8], zh[8], dzh[8], s1 = 0.f, s2 = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          dn[nb] = (valid && av[nb] > 0.f) ? acc[mb][nb][i] : 0.f;
-          zh[nb] = (zv[nb] - mean) * rstd;
-          dzh[nb] = dn[nb] * gam[nb];
-          s1 += dzh[nb];
-          s2 += dzh[nb] * zh[nb];
-          lnp[nb] += dn[nb] * zh[nb];
-          lnp[8 + nb] += dn[nb];
-        }
-        s1 = row_sum16(s1) * (1.0f / NRX_D);
-        s2 = row_sum16(s2) * (1.0f / NRX_D);
-        float dz[8];
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) dz[nb] = rstd * (dzh[nb] - s1 - zh[nb] * s2);
-        if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, dz);
-      }
-    }
-    return;
-  }
-  float bias[8];
-#pragma unroll
-  for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
-      const bool valid = r < tl.nrows;
-      const int R = tl.row0 + (valid ? r : 0);
-      const int s = R / rps;
-      const int rem = R - s * rps;
-      const int t = rem / U, u = rem - (rem / U) * U;
-      const int64_t grow = g.row_base + R;
-      float v[8];
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
-      if (a.pe) {
-        int par = (s - (u >> 1)) & 1;
-        int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
-        const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
-      }
-      if constexpr (EPI == EPI_LN_RELU) {
-        float sm = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) sm += v[nb];
-        const float mean = row_sum16(sm) * (1.0f / NRX_D);
-        float sq = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
-        const float var = row_sum16(sq) * (1.0f / NRX_D);
-        const float rstd = 1.0f / sqrtf(var + 1e-5f);
-        if (valid && a.save_z) {
-          pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
-          if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
-        }
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
-          v[nb] = n > 0.f ? n : 0.f;
-        }
-      } else if constexpr (EPI == EPI_RESID) {
-        float rsd[8];
-        if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
-      }
-      if (valid) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
-    }
-  }
-}
-
-// Final dgamma/dbeta reduction of the LayerNorm-backward epilogue (after the tile loop).
-template <int EPI, int NW>
-__device__ __forceinline__ void conv_ln_reduce(float *lnp, float *red, float *out, int tid, int wave, int lr, int lk) {
-  if constexpr (EPI == EPI_LN_BWD) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      lnp[k] += __shfl_xor(lnp[k], 16, 64);
-      lnp[k] += __shfl_xor(lnp[k], 32, 64);
-    }
-    __syncthreads();
-    if (lk == 0) {
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb) {
-        red[wave * 256 + 8 * lr + nb] = lnp[nb];
-        red[wave * 256 + 128 + 8 * lr + nb] = lnp[8 + nb];
-      }
-    }
-    __syncthreads();
-    if (tid < 256) {
-      float v = 0.f;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) v += red[w * 256 + tid];
-      out[(int64_t)blockIdx.x * 256 + tid] = v;
-    }
-  }
-}
 
 template <typename T, int MB, int EPI, int OCC, bool PREF>
 __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
@@ -309,14 +173,21 @@ __global__ __launch_bounds__(256, OCC) void conv3x3_kernel(ConvArgs<T> a) {
 }
 
 
-// Variant with both MFMA operands in LDS.  Tiles of 64*MB rows (MB m-blocks per
-// wave; MB = 6 is the largest without register spills), one wave per SIMD.  Per 64-byte K chunk the halo block is DMA'd once;
-// the weights of each group of three taps (one tap row di) are DMA'd into a
-// two-slot ring one group ahead, so the MFMA loop reads only LDS.  Every wave
-// issues a fixed number of halo DMA instructions, which lets the wait for the
-// next weight group (issued first) leave the halo loads in flight
-// (s_waitcnt vmcnt(APW)).  The next tile's first chunk is prefetched during the
-// last group of the current one.
+// Variant with both MFMA operands in LDS.  Tiles of 16*MB*NW rows (MB m-blocks
+// per wave).  Per 64-byte K chunk the halo block is DMA'd once; the weights of
+// each group of three taps (one tap row di) are DMA'd into a two-slot ring one
+// group ahead, so the MFMA loop reads only LDS.  Every wave issues a fixed
+// number of halo DMA instructions, which lets the wait for the next weight group
+// (issued first) leave the halo loads in flight (s_waitcnt vmcnt(APW)).  The
+// next tile's first chunk is prefetched during the last group of the current one.
+//
+// The two halo buffers and the two weight slots are four distinct LDS arrays,
+// and the K loop is unrolled over its period (two chunks = six groups) so that
+// every access names its array statically: the compiler can then tell that a
+// DMA in flight writes a different array than the one being read, and does not
+// drain the DMA queue before each LDS read.  Tile metadata is read through the
+// constant address space (scalar loads), so it does not wait on the DMA queue
+// either.
 template <typename T, int EPI, int MB, int NW>
 __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) {
   constexpr int TILE = 16 * MB * NW;
@@ -329,17 +200,21 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
   constexpr int BROWS = 3 * 8 * 16;                // 64-byte weight rows per 3-tap group
   constexpr int BPW = BROWS / 16 / NW;             // weight DMA instructions per wave per group
   static_assert(APW < 16, "vmcnt immediate below");
-  __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
-  __shared__ __align__(16) unsigned char lds_b[2][BROWS * ROWB];
+  __shared__ __align__(16) unsigned char lds_a0[(AROWS + 1) * ROWB];
+  __shared__ __align__(16) unsigned char lds_a1[(AROWS + 1) * ROWB];
+  __shared__ __align__(16) unsigned char lds_b0[BROWS * ROWB];
+  __shared__ __align__(16) unsigned char lds_b1[BROWS * ROWB];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar LDS addresses)
   const int lr = lane & 15, lk = lane >> 4;
-  if (tid < 8) {
+  if (tid < 4) {
     v16 z = {{0, 0, 0, 0}};
-    st16(&lds_a[tid >> 2][ZROW * ROWB + (tid & 3) * 16], z);
+    st16(&lds_a0[ZROW * ROWB + tid * 16], z);
+    st16(&lds_a1[ZROW * ROWB + tid * 16], z);
   }
   const int cin = a.c0 + a.c1;
-  const int nch = cin / KC;
+  const int nch = cin / KC;   // even (checked by the host)
   float lnp[EPI == EPI_LN_BWD ? 16 : 1];
 #pragma unroll
   for (int k = 0; k < (EPI == EPI_LN_BWD ? 16 : 1); ++k) lnp[k] = 0.f;
@@ -349,42 +224,41 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
 
   // weight buffer resource (bounds unchecked: offsets are within the layer's block)
   const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc((void *)a.w, 0, 0x7FFFFFFF, 0x00020000);
-  auto stage_b = [&](int c, int grp, int slot) {
+  auto stage_b = [&](int c, int grp, unsigned char *dst) {
     const uint32_t base = (uint32_t)((c * 9 + 3 * grp) * 8 * 16) * ROWB;
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       const int ins = wave + NW * j;
       const int row = ins * 16 + (lane >> 2);
       const int piece = (lane & 3) ^ swz(row);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (lds_void *)&lds_b[slot][ins * 16 * ROWB], 16,
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (lds_void *)&dst[ins * 16 * ROWB], 16,
                                                 base + row * ROWB + piece * 16, 0, 0, 0);
     }
   };
-  // halo of chunk c of a tile described by (row_base, rel0, halo, S, rps)
   struct Geo {
     int64_t row_base;
-    int rel0, halo, S, rps, U, s_first;
+    int rel0, halo, S, rps, U;
   };
-  auto geo_of = [&](const Tile &tl, const SlotGeo &g) {
+  auto geo_of = [&](const Tile &tl) {
+    const SlotGeo g = ldc_geo(a.geo + tl.slot);
     Geo q;
     q.U = g.U;
     q.S = g.S;
     q.rps = 14 * g.U;
-    q.s_first = tl.row0 / q.rps;
+    const int s_first = tl.row0 / q.rps;
     const int s_last = (tl.row0 + tl.nrows - 1) / q.rps;
-    q.halo = (s_last - q.s_first + 3) * q.rps;
-    q.rel0 = (q.s_first - 1) * q.rps;
+    q.halo = (s_last - s_first + 3) * q.rps;
+    q.rel0 = (s_first - 1) * q.rps;
     q.row_base = g.row_base;
     return q;
   };
-  auto stage_a = [&](const Geo &q, int c, int b) {
+  auto stage_a = [&](const Geo &q, int c, unsigned char *dst) {
     const T *src;
     int cs, coff;
     if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
     else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
-    const T *base = src + q.row_base * cs + coff;
-    const int nrec = q.S * q.rps * cs * (int)sizeof(T);
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, nrec, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rs =
+        uniform_rsrc(src + q.row_base * cs + coff, q.S * q.rps * cs * (int)sizeof(T));
 #pragma unroll
     for (int j = 0; j < APW; ++j) {
       const int ins = wave + NW * j;
@@ -392,26 +266,23 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
       const int piece = (lane & 3) ^ swz(h);
       // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
       const uint32_t voff = h < q.halo ? (uint32_t)((q.rel0 + h) * cs * (int)sizeof(T) + piece * 16) : 0x80000000u;
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)&lds_a[b][ins * 16 * ROWB], 16, voff, 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)&dst[ins * 16 * ROWB], 16, voff, 0, 0, 0);
     }
   };
   constexpr int WAIT_ALL = 0;
   constexpr int WAIT_KEEP_A = (0xF << 8) | (7 << 4) | APW;   // vmcnt <= APW, no wait on lgkm/exp
 
-  int ka = 0, kb = 0;   // running halo-buffer and weight-slot counters
   int tile = lb;
   if (tile < a.n_tiles) {
-    const Tile t0 = a.tiles[tile];
-    const Geo q0 = geo_of(t0, a.geo[t0.slot]);
-    stage_b(0, 0, 0);
-    stage_a(q0, 0, 0);
+    const Tile t0 = ldc(a.tiles + tile);
+    stage_b(0, 0, lds_b0);
+    stage_a(geo_of(t0), 0, lds_a0);
     __builtin_amdgcn_s_waitcnt(WAIT_ALL);
     __syncthreads();
   }
   for (; tile < a.n_tiles; tile += G) {
-    const Tile tl = a.tiles[tile];
-    const SlotGeo g = a.geo[tl.slot];
-    const Geo q = geo_of(tl, g);
+    const Tile tl = ldc(a.tiles + tile);
+    const Geo q = geo_of(tl);
     int hc[MB], tt[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
@@ -427,24 +298,27 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    const int ngrp = 3 * nch;
     const int next_tile = tile + G;
-    for (int k = 0; k < ngrp; ++k) {
-      const int c = k / 3, grp = k - 3 * c;
+    // one group of three taps (tap row di = grp - 1) of chunk c; SI = position in the
+    // six-group period, which fixes the arrays read and written
+    auto group = [&](auto SI, int c) __attribute__((always_inline)) {
+      constexpr int si = decltype(SI)::value;
+      constexpr int grp = si % 3;
+      unsigned char *la = (si / 3) ? lds_a1 : lds_a0;     // halo of chunk c
+      unsigned char *la_next = (si / 3) ? lds_a0 : lds_a1;
+      unsigned char *lbr = (si & 1) ? lds_b1 : lds_b0;     // this group's weights
+      unsigned char *lb_next = (si & 1) ? lds_b0 : lds_b1;
+      const bool last = c + 1 == nch && grp == 2;
       bool a_issued = false;
-      if (k + 1 < ngrp) {
-        stage_b((k + 1) / 3, (k + 1) % 3, (kb + 1) & 1);
-        if (grp == 0 && c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); a_issued = true; }
+      if (!last) {
+        stage_b(grp == 2 ? c + 1 : c, grp == 2 ? 0 : grp + 1, lb_next);
+        if (grp == 0 && c + 1 < nch) { stage_a(q, c + 1, la_next); a_issued = true; }
       } else if (next_tile < a.n_tiles) {
-        // prefetch the next tile's first chunk and weight group
-        const Tile tn = a.tiles[next_tile];
-        const Geo qn = geo_of(tn, a.geo[tn.slot]);
-        stage_b(0, 0, (kb + 1) & 1);
-        stage_a(qn, 0, (ka + 1) & 1);
-        a_issued = true;
+        // prefetch the next tile's first chunk and weight group (period restarts at 0)
+        const Tile tn = ldc(a.tiles + next_tile);
+        stage_b(0, 0, lb_next);
+        stage_a(geo_of(tn), 0, la_next);
       }
-      const unsigned char *la = &lds_a[ka & 1][0];
-      const unsigned char *lbw = &lds_b[kb & 1][0];
       const int di = grp - 1;
 #pragma unroll 1
       for (int tj = 0; tj < 3; ++tj) {
@@ -457,24 +331,39 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
           const int row = ok ? hc[mb] + off : ZROW;
           af[mb] = ld16(la + row * ROWB + ((lk ^ swz(row)) << 4));
         }
+        auto load_bf = [&](int nb) {
+          const int brow = (tj * 8 + nb) * 16 + lr;
+          return ld16(lbr + brow * ROWB + ((lk ^ swz(brow)) << 4));
+        };
+        // weight fragments one n-block ahead of the MFMAs that use them; the
+        // scheduling barriers keep that order
+        v16 bcur = load_bf(0);
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
-          const int brow = (tj * 8 + nb) * 16 + lr;
-          const v16 bf = ld16(lbw + brow * ROWB + ((lk ^ swz(brow)) << 4));
+          const v16 bnext = nb < 7 ? load_bf(nb + 1) : bcur;
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(af[mb], bf, acc[mb][nb]);
+          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(af[mb], bcur, acc[mb][nb]);
+          bcur = bnext;
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       // the next weight group must have landed; a halo load issued after it may stay in flight
-      if (a_issued && grp == 0 && k + 1 < ngrp) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
+      if (a_issued) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
       else __builtin_amdgcn_s_waitcnt(WAIT_ALL);
-      __syncthreads();
-      kb += 1;
-      if (grp == 2) ka += 1;
+      dma_barrier();
+    };
+#pragma unroll 1
+    for (int c = 0; c < nch; c += 2) {
+      group(std::integral_constant<int, 0>{}, c);
+      group(std::integral_constant<int, 1>{}, c);
+      group(std::integral_constant<int, 2>{}, c);
+      group(std::integral_constant<int, 3>{}, c + 1);
+      group(std::integral_constant<int, 4>{}, c + 1);
+      group(std::integral_constant<int, 5>{}, c + 1);
     }
-    conv_epilogue<T, MB, EPI>(a, tl, g, acc, wave, lr, lk, lnp);
+    conv_epilogue<T, MB, EPI>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
   }
-  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
+  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(lds_b0), a.ln_part, tid, wave, lr, lk);
 }
 
 }  // namespace

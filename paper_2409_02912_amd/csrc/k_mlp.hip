@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void mp_kernel(MlpArgs<T> a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int ch0 = 8 * lr;
+  float vmax = 0.f;   // max |aggregate| written by this thread (FP8 calibration)
 
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const Tile tl = a.tiles[tile];
@@ -134,9 +135,13 @@ __global__ __launch_bounds__(256) void mp_kernel(MlpArgs<T> a) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] += m[k];
       }
-      pack8<T>::store(a.out + (gbase + r) * NRX_D + c8, v);
+      if (a.out) pack8<T>::store(a.out + (gbase + r) * NRX_D + c8, v);
+      if (a.out8) *reinterpret_cast<uint2 *>(a.out8 + (gbase + r) * NRX_D + c8) = fp8x8(v, a.out8_inv);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) vmax = fmaxf(vmax, fabsf(v[k]));
     }
   }
+  if (a.amax) atomicMax(a.amax, __float_as_uint(vmax));
 }
 
 template <typename T>

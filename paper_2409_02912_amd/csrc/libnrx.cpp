@@ -10,11 +10,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/libnrx.h"
@@ -65,6 +67,7 @@ struct ConvLayer {
   int cin_real = 0, cin_total = 0, n_chunks = 0;
   int64_t prep = 0;             // element offset in the prepped buffer
   int64_t field = -1;           // element offset in the field buffer (PE folded) or -1
+  int64_t w8 = -1, ws8 = -1;    // FP8 models: byte offset of the E4M3 operand, float offset of its scales
 };
 
 struct BlockLayer {
@@ -259,8 +262,11 @@ int num_cu() {
 struct GraphKey {
   const void *plan, *w, *y, *h, *llr, *ws;
   bool save;
+  uint64_t variants;   // conv kernel variant per layer class, 4 bits each
+  uint64_t epoch;      // FP8 activation-scale version (scales are kernel arguments)
   bool operator<(const GraphKey &o) const {
-    return std::tie(plan, w, y, h, llr, ws, save) < std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save);
+    return std::tie(plan, w, y, h, llr, ws, save, variants, epoch) <
+           std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save, o.variants, o.epoch);
   }
 };
 
@@ -290,6 +296,18 @@ struct nrx_model {
   void *pinned_bjobs = nullptr;
   size_t tsize = 4;                     // bytes per activation / operand element
   Graphs *graphs = nullptr;        // captured forward graphs (flags bit 0)
+  // FP8 models: E4M3 conv operands with per-layer activation scales
+  //   act_scale[i] (i < C): input h_i of block i; [C + i]: conv_a output of block i;
+  //   [2C + r]: aggregated messages of round r
+  bool fp8 = false;
+  bool calibrating = false;             // forward records max |activation| instead of using FP8
+  bool calibrated = false;
+  std::vector<float> act_scale;
+  uint64_t scale_epoch = 0;
+  int64_t w8_bytes = 0, n_wscale = 0;
+  std::vector<Fp8Job> fp8jobs;
+  void *pinned_fp8jobs = nullptr;
+  std::vector<void *> retired_pinned;   // job tables replaced while copies may be in flight
   // conv kernel variant per layer class (autotuned; indices into kConvVariants)
   int conv_variant[NRX_K_NCLASS] = {1, 1, 1, 1, 1, 1, 1};
   // per-class event timing (diagnostics)
@@ -331,11 +349,12 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   if (c.n_blocks < 1 || c.n_blocks > 16) return fail(NRX_ERR_SHAPE, "n_blocks %d outside 1..16", c.n_blocks);
   if (c.n_rounds < 0 || c.n_rounds > c.n_blocks) return fail(NRX_ERR_SHAPE, "n_rounds %d outside 0..n_blocks", c.n_rounds);
   if (c.m_max != 2 && c.m_max != 4 && c.m_max != 6 && c.m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", c.m_max);
-  if (c.precision != NRX_FP32 && c.precision != NRX_BF16)
+  if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
   auto m = std::make_unique<nrx_model>();
   m->cfg = c;
-  m->tsize = c.precision == NRX_FP32 ? 4 : 2;
+  m->tsize = c.precision == NRX_FP32 ? 4 : 2;   // FP8 models keep BF16 for everything but the block convs
+  m->fp8 = c.precision == NRX_FP8;
   const int d = c.d, B = c.n_ant;
   m->cx = std::max(32, 4 * B);
   std::vector<int> mpb;
@@ -400,8 +419,17 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     L.g = toff(m.get(), p + ".ln.g");
     L.beta = toff(m.get(), p + ".ln.b");
     conv_job(L.b, toff(m.get(), p + ".conv_b.w"), toff(m.get(), p + ".conv_b.b"), d, d, d, false);
+    if (m->fp8) {
+      for (ConvLayer *cl : {&L.a, &L.b}) {
+        cl->w8 = m->w8_bytes;
+        m->w8_bytes += (int64_t)(cl->cin_real / 64) * 5 * 8 * 16 * 128;
+        cl->ws8 = m->n_wscale;
+        m->n_wscale += NRX_D;
+      }
+    }
     m->blocks.push_back(L);
   }
+  if (m->fp8) m->act_scale.assign(2 * c.n_blocks + c.n_rounds, 1.0f);
   for (int r = 0; r < c.n_rounds; ++r) {
     const std::string p = "mp" + std::to_string(r);
     DenseLayer &L = m->mp[r];
@@ -455,6 +483,8 @@ extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
   for (auto &e : m->pending) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto e : m->pool) (void)hipEventDestroy(e);
   if (m->pinned_jobs) (void)hipHostFree(m->pinned_jobs);
+  if (m->pinned_fp8jobs) (void)hipHostFree(m->pinned_fp8jobs);
+  for (void *p : m->retired_pinned) (void)hipHostFree(p);
   delete m;
   return NRX_OK;
 }
@@ -479,6 +509,7 @@ namespace {
 
 struct FwdLayout {
   size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps;
+  size_t h8 = 0, a8 = 0, agg8 = 0, w8 = 0, wsc = 0, f8jobs = 0, amax = 0;   // FP8 models
   std::vector<size_t> h;      // h_0 .. h_C (inference: one buffer)
   std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
   std::vector<size_t> stats;  // per block (training)
@@ -508,6 +539,16 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   L.done = o; o = align256(o + (size_t)P->n * 4);
   L.stamps = o; o = align256(o + (size_t)(P->n + 1) * 8);
   const int C = m->cfg.n_blocks, R = m->cfg.n_rounds;
+  if (m->fp8) {
+    const size_t act8 = align256((size_t)P->rows * NRX_D);
+    L.h8 = o; o += act8;
+    L.a8 = o; o += act8;
+    L.agg8 = o; o += act8;
+    L.w8 = o; o = align256(o + (size_t)m->w8_bytes);
+    L.wsc = o; o = align256(o + (size_t)m->n_wscale * 4);
+    L.f8jobs = o; o = align256(o + sizeof(Fp8Job) * 2 * C);
+    L.amax = o; o = align256(o + m->act_scale.size() * 4);
+  }
   if (!save) {
     L.h.push_back(o); o += act;
     L.a.push_back(o); o += act;
@@ -595,18 +636,41 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     launch_features<T>(D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, m->cfg.n_ant, m->cx,
                        X, (float2 *)h_ls, st);
   }
+  // FP8 models: E4M3 block-conv operands (or, while calibrating, BF16 convs that record max |activation|)
+  const bool f8 = m->fp8 && !m->calibrating && !save;
+  uint8_t *h8 = m->fp8 ? (uint8_t *)(ws + L.h8) : nullptr;
+  uint8_t *a8 = m->fp8 ? (uint8_t *)(ws + L.a8) : nullptr;
+  uint8_t *agg8 = m->fp8 ? (uint8_t *)(ws + L.agg8) : nullptr;
+  unsigned int *amax = m->calibrating ? (unsigned int *)(ws + L.amax) : nullptr;
+  const int C = m->cfg.n_blocks;
+  auto inv_scale = [&](int idx) { return 1.0f / m->act_scale[idx]; };
+  if (f8) {
+    if (!m->calibrated) return fail(NRX_ERR_INVALID, "FP8 model has no activation scales (nrx_calibrate)");
+    ProfMark pm(m, NRX_K_FRONTEND, st);
+    HIPCHK(hipMemcpyAsync(ws + L.f8jobs, m->pinned_fp8jobs, sizeof(Fp8Job) * m->fp8jobs.size(),
+                          hipMemcpyHostToDevice, st));
+    launch_prep_fp8(w, (const Fp8Job *)(ws + L.f8jobs), (int)m->fp8jobs.size(), (uint8_t *)(ws + L.w8),
+                    (float *)(ws + L.wsc), st);
+  }
+  if (amax) HIPCHK(hipMemsetAsync(amax, 0, m->act_scale.size() * 4, st));
 
   const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), num_cu() * 4);
-  // launch one conv of layer class cls with its selected variant
-  auto conv = [&](ConvArgs<T> ca, int epi, int cls) {
-    const int v = m->conv_variant[cls];
-    const ConvVariant &cv = kConvVariants[v];
+  // launch one conv of layer class cls with its selected variant (E4M3 kernels when fp8op)
+  auto conv = [&](ConvArgs<T> ca, int epi, int cls, bool fp8op) {
+    int v = m->conv_variant[cls];
+    if (fp8op) v = std::min(v, NRX_CONV8_VARIANTS - 1);
+    else if (kConvVariants[v].pref == 2 && ((ca.c0 + ca.c1) / (64 / (int)sizeof(T))) % 2)
+      v = 1;   // the LDS-operand kernels walk the input channels two chunks at a time
+    const ConvVariant &cv = fp8op ? kConv8Variants[v] : kConvVariants[v];
     const int ti = tile_size_index(cv.mb);
     ca.tiles = D.ct[ti];
     ca.n_tiles = (int)P->ct[ti].size();
     int grid = std::min<int>(ca.n_tiles, num_cu() * cv.occ);
     grid = (grid + 7) / 8 * 8;    // the kernel's XCD-aware order needs a multiple of 8
     ProfMark pm(m, cls, st);
+    if constexpr (std::is_same<T, bf16_t>::value) {
+      if (fp8op) { launch_conv8(ca, epi, v, grid, st); return; }
+    }
     launch_conv<T>(ca, epi, v, grid, st);
   };
   auto buf = [&](size_t off) { return (T *)(ws + off); };
@@ -619,8 +683,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   a.bias = w + m->conv_in.b;
   a.pe = fields + m->conv_in.field;
   a.out = buf(L.h[0]);
-  conv(a, EPI_STORE, NRX_K_CONV_IN);
-  const int C = m->cfg.n_blocks;
+  ConvArgs<T> a0 = a;
+  if (f8) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
+  if (amax) a0.amax = amax + 0;
+  conv(a0, EPI_STORE, NRX_K_CONV_IN, false);
   for (int i = 0; i < C; ++i) {
     const BlockLayer &B = m->blocks[i];
     T *h_in = buf(L.h[save ? i : 0]);
@@ -637,6 +703,8 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ma.b1 = w + m->mp[r].b1;
       ma.b2 = w + m->mp[r].b2;
       ma.out = agg;
+      if (f8) { ma.out = nullptr; ma.out8 = agg8; ma.out8_inv = inv_scale(2 * C + r); }
+      if (amax) ma.amax = amax + 2 * C + r;
       ma.save_m1 = save ? buf(L.m1[r]) : nullptr;
       ma.geo = D.geo;
       ma.tiles = D.mt;
@@ -655,7 +723,17 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ca.out = abuf;
     ca.save_z = save ? buf(L.z[i]) : nullptr;
     ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
-    conv(ca, EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A);
+    if (f8) {
+      ca.src8_0 = h8;
+      ca.src8_1 = agg ? agg8 : nullptr;
+      ca.w8 = (const uint8_t *)(ws + L.w8) + B.a.w8;
+      ca.wscale = (const float *)(ws + L.wsc) + B.a.ws8;
+      ca.out = nullptr;
+      ca.out8 = a8;
+      ca.out8_inv = inv_scale(C + i);
+    }
+    if (amax) ca.amax = amax + C + i;
+    conv(ca, EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, f8);
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
@@ -663,7 +741,14 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     cb.pe = nullptr;
     cb.resid = h_in;
     cb.out = h_out;
-    conv(cb, EPI_RESID, NRX_K_CONV_B);
+    if (f8) {
+      cb.src8_0 = a8;
+      cb.w8 = (const uint8_t *)(ws + L.w8) + B.b.w8;
+      cb.wscale = (const float *)(ws + L.wsc) + B.b.ws8;
+      if (i + 1 < C) { cb.out8 = h8; cb.out8_inv = inv_scale(i + 1); }
+    }
+    if (amax && i + 1 < C) cb.amax = amax + i + 1;
+    conv(cb, EPI_RESID, NRX_K_CONV_B, f8);
   }
   MlpArgs<T> ra{};
   ra.h = buf(L.h[save ? C : 0]);
@@ -708,6 +793,7 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
   Plan *P;
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
   if (s != NRX_OK) return s;
+  if (m->fp8 && save_acts) return fail(NRX_ERR_UNSUPPORTED, "FP8 models are inference-only (train in BF16)");
   const FwdLayout L = fwd_layout(m, P, save_acts != 0);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
   auto run = [&](hipStream_t s2) {
@@ -716,7 +802,9 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
   };
   if ((m->cfg.flags & 1) && !m->profile) {
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
-    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0}, run, st);
+    uint64_t vs = 0;
+    for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (4 * c);
+    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch}, run, st);
   } else {
     s = run(st);
   }
@@ -811,13 +899,21 @@ extern "C" nrx_status nrx_profile_read(nrx_model *m, int32_t cls, double *ms_tot
   return NRX_OK;
 }
 
+namespace {
+// block convs of FP8 models run the E4M3 kernel family
+int n_conv_variants(const nrx_model *m, int cls) {
+  return m->fp8 && cls != NRX_K_CONV_IN ? NRX_CONV8_VARIANTS : NRX_CONV_VARIANTS;
+}
+}  // namespace
+
 extern "C" nrx_status nrx_conv_variant(nrx_model *m, int32_t cls, int32_t variant, int32_t *current,
                                        int32_t *n_variants) {
   if (!m || cls < NRX_K_CONV_IN || cls > NRX_K_CONV_B) return fail(NRX_ERR_INVALID, "bad model or class");
-  if (variant >= NRX_CONV_VARIANTS) return fail(NRX_ERR_INVALID, "variant %d out of range", variant);
+  const int nv = n_conv_variants(m, cls);
+  if (variant >= nv) return fail(NRX_ERR_INVALID, "variant %d out of range", variant);
   if (variant >= 0) m->conv_variant[cls] = variant;
   if (current) *current = m->conv_variant[cls];
-  if (n_variants) *n_variants = NRX_CONV_VARIANTS;
+  if (n_variants) *n_variants = nv;
   return NRX_OK;
 }
 
@@ -828,7 +924,8 @@ std::string tune_key(const nrx_model *m, const Plan *P, int cls) {
   int maxu = 0;
   for (auto &g : P->geo) maxu = std::max(maxu, g.U);
   char b[256];
-  snprintf(b, sizeof b, "gfx950|%s|%s|rows=%lld|slots=%d|maxU=%d|B=%d", m->cfg.precision == NRX_FP32 ? "fp32" : "bf16",
+  snprintf(b, sizeof b, "gfx950|%s|%s|rows=%lld|slots=%d|maxU=%d|B=%d",
+           m->cfg.precision == NRX_FP32 ? "fp32" : (m->cfg.precision == NRX_FP8 ? "fp8" : "bf16"),
            kClassName[cls], (long long)P->rows, P->n, maxu, m->cfg.n_ant);
   return b;
 }
@@ -855,7 +952,7 @@ extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_
           const char *vq = strstr(line, "\"variant\": ");
           if (q && vq) {
             int v = atoi(vq + 11);
-            if (v >= 0 && v < NRX_CONV_VARIANTS) { pick[c] = v; found |= 1 << c; }
+            if (v >= 0 && v < n_conv_variants(m, c)) { pick[c] = v; found |= 1 << c; }
           }
         }
       }
@@ -869,11 +966,18 @@ extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_
     }
   }
   const bool prof_was = m->profile;
+  const int flags_was = m->cfg.flags;
+  m->cfg.flags &= ~1;   // trials run eagerly (no graph per trial)
+  struct Restore {
+    nrx_model *m;
+    int f;
+    ~Restore() { m->cfg.flags = f; }
+  } restore{m, flags_was};
   double best[NRX_K_NCLASS];
   int bestv[NRX_K_NCLASS];
   for (int c = 0; c < NRX_K_NCLASS; ++c) { best[c] = 1e30; bestv[c] = m->conv_variant[c]; }
   for (int v = 0; v < NRX_CONV_VARIANTS; ++v) {
-    for (int c : classes) m->conv_variant[c] = v;
+    for (int c : classes) m->conv_variant[c] = std::min(v, n_conv_variants(m, c) - 1);
     m->profile = false;
     s = nrx_forward(m, w, slots, n, y, nullptr, llr, 0, ws, ws_bytes, st);   // warm-up
     if (s != NRX_OK) { m->profile = prof_was; return s; }
@@ -888,7 +992,7 @@ extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_
       int64_t cnt;
       s = nrx_profile_read(m, c, &ms, &cnt, 0);
       if (s != NRX_OK) { m->profile = prof_was; return s; }
-      if (cnt > 0 && ms / cnt < best[c]) { best[c] = ms / cnt; bestv[c] = v; }
+      if (cnt > 0 && ms / cnt < best[c]) { best[c] = ms / cnt; bestv[c] = std::min(v, n_conv_variants(m, c) - 1); }
     }
     nrx_profile_read(m, 0, nullptr, nullptr, 1);
   }
@@ -971,7 +1075,8 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.ln_part = lpart;
     a.geo = D.geo;
     // the LayerNorm-backward epilogue spills in the large-tile variants: keep it on variant 1
-    const int v = epi == EPI_LN_BWD ? 1 : m->conv_variant[cls];
+    int v = epi == EPI_LN_BWD ? 1 : m->conv_variant[cls];
+    if (kConvVariants[v].pref == 2 && ((a.c0 + a.c1) / (64 / (int)sizeof(T))) % 2) v = 1;
     const ConvVariant &cv = kConvVariants[v];
     const int ti = tile_size_index(cv.mb);
     a.tiles = D.ct[ti];
@@ -1284,4 +1389,73 @@ extern "C" nrx_status slot_sim(const nrx_sim_config *cfg, uint64_t seed, uint32_
              P->max_bits, st);
   HIPCHK(hipGetLastError());
   return NRX_OK;
+}
+
+// ------------------------------------------------------------------- FP8 scales --
+
+namespace {
+// quantisation jobs of the block convs from the current activation scales, in a
+// fresh pinned table (the previous one may still be the source of a queued copy)
+nrx_status build_fp8_jobs(nrx_model *m) {
+  const int C = m->cfg.n_blocks;
+  std::vector<Fp8Job> jobs;
+  for (int i = 0; i < C; ++i) {
+    const BlockLayer &B = m->blocks[i];
+    const float s_agg = B.mp_round >= 0 ? m->act_scale[2 * C + B.mp_round] : 1.0f;
+    jobs.push_back(Fp8Job{B.a.w, B.a.cin_real, B.a.cin_total, NRX_D, m->act_scale[i], s_agg, B.a.w8, B.a.ws8});
+    jobs.push_back(Fp8Job{B.b.w, B.b.cin_real, B.b.cin_total, NRX_D, m->act_scale[C + i], 1.0f, B.b.w8, B.b.ws8});
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, sizeof(Fp8Job) * jobs.size(), hipHostMallocDefault) != hipSuccess)
+    return fail(NRX_ERR_HIP, "hipHostMalloc failed");
+  memcpy(p, jobs.data(), sizeof(Fp8Job) * jobs.size());
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (m->pinned_fp8jobs) m->retired_pinned.push_back(m->pinned_fp8jobs);
+  m->pinned_fp8jobs = p;
+  m->fp8jobs = jobs;
+  m->calibrated = true;
+  m->scale_epoch += 1;
+  return NRX_OK;
+}
+}  // namespace
+
+extern "C" int32_t nrx_act_scale_count(const nrx_model *m) {
+  return m && m->fp8 ? (int32_t)m->act_scale.size() : 0;
+}
+
+extern "C" nrx_status nrx_act_scales(nrx_model *m, const float *set, float *get, int32_t n) {
+  if (!m || !m->fp8) return fail(NRX_ERR_INVALID, "not an FP8 model");
+  if (n != (int32_t)m->act_scale.size()) return fail(NRX_ERR_SHAPE, "expected %zu scales, got %d", m->act_scale.size(), n);
+  if (set) {
+    for (int i = 0; i < n; ++i)
+      if (!(set[i] > 0.f) || !std::isfinite(set[i])) return fail(NRX_ERR_INVALID, "scale %d is not a positive number", i);
+    std::copy(set, set + n, m->act_scale.begin());
+    nrx_status s = build_fp8_jobs(m);
+    if (s != NRX_OK) return s;
+  }
+  if (get) std::copy(m->act_scale.begin(), m->act_scale.end(), get);
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_calibrate(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                    const float *y, float *llr, void *ws, size_t ws_bytes, float headroom,
+                                    hipStream_t st) {
+  if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  if (!m->fp8) return fail(NRX_ERR_INVALID, "not an FP8 model");
+  if (!(headroom >= 1.0f)) return fail(NRX_ERR_INVALID, "headroom %g < 1", headroom);
+  Plan *P;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  if (s != NRX_OK) return s;
+  const FwdLayout L = fwd_layout(m, P, false);
+  if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  m->calibrating = true;
+  s = forward_impl<bf16_t>(m, P, L, w, y, nullptr, llr, false, (char *)ws, st);
+  m->calibrating = false;
+  if (s != NRX_OK) return s;
+  std::vector<float> amax(m->act_scale.size());
+  HIPCHK(hipMemcpyAsync(amax.data(), (char *)ws + L.amax, amax.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t i = 0; i < amax.size(); ++i)
+    m->act_scale[i] = amax[i] > 0.f && std::isfinite(amax[i]) ? amax[i] * headroom / 448.0f : 1.0f;
+  return build_fp8_jobs(m);
 }

@@ -79,6 +79,9 @@ _SIGS = {
     "nrx_autotune": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _sz, ctypes.c_char_p, _vp]),
     "nrx_conv_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "nrx_slot_latency": (_i32, [_vp, _DESC, _i32, _vp, _vp, _vp]),
+    "nrx_act_scale_count": (_i32, [_vp]),
+    "nrx_act_scales": (_i32, [_vp, _vp, _vp, _i32]),
+    "nrx_calibrate": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp]),
     "nrx_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -290,3 +293,21 @@ def set_all_conv_variants(model, variant):
 def nrx_slot_latency(model, slots, ws, latency_us, stream=None):
     arr, n = _descs(slots)
     _check(_lib.nrx_slot_latency(model, arr, n, _ptr(ws), _ptr(latency_us), _stream(stream)))
+
+
+def nrx_act_scales(model, scales=None):
+    """Returns the FP8 activation scales (numpy float32); sets them first when given."""
+    import numpy as np
+    n = int(_lib.nrx_act_scale_count(model))
+    out = np.zeros(n, dtype=np.float32)
+    src = None
+    if scales is not None:
+        src = np.ascontiguousarray(scales, dtype=np.float32)
+    _check(_lib.nrx_act_scales(model, src.ctypes.data if src is not None else None, out.ctypes.data, n))
+    return out
+
+
+def nrx_calibrate(model, w, slots, y, llr, ws, headroom=1.25, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_calibrate(model, _ptr(w), arr, n, _ptr(y), _ptr(llr), _ptr(ws), ws.numel() * ws.element_size(),
+                              float(headroom), _stream(stream)))

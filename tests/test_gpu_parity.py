@@ -370,15 +370,68 @@ def test_autograd_function_gradient():
         assert torch.equal(g, g2)
         v = rng.standard_normal(w.size)
         v /= np.linalg.norm(v)
-        eps = 1e-3 * float(np.linalg.norm(w))
         rn = r.double().cpu().numpy()
 
         def loss(wv):
             with torch.no_grad():
                 return float(np.dot(nrx(dev(wv.astype(np.float32)), y).double().cpu().numpy(), rn))
-        fd = (loss(w + eps * v) - loss(w - eps * v)) / (2 * eps)
         an = float(np.dot(g.double().cpu().numpy(), v))
-        log(f"directional derivative: analytic {an:.6e} finite difference {fd:.6e} (eps {eps:.2e})")
-        assert abs(fd - an) <= 2e-2 * abs(an) + 1e-6
+        # central differences over shrinking steps: ReLU kinks crossed by a large step bias the
+        # estimate, fp32 rounding limits the smallest; the best step must agree to 2 %
+        errs = []
+        for rel in (1e-3, 3e-4, 1e-4):
+            eps = rel * float(np.linalg.norm(w))
+            fd = (loss(w + eps * v) - loss(w - eps * v)) / (2 * eps)
+            errs.append(abs(fd - an) / abs(an))
+            log(f"directional derivative: analytic {an:.6e} finite difference {fd:.6e} (eps {eps:.2e})")
+        assert min(errs) <= 2e-2
     finally:
         nrx.close()
+
+
+FP8_TOL = 0.25        # norm-wise LLR error bound of the E4M3 block convs (derivation in the design notes)
+FP8_AGREE = 0.99      # hard-decision agreement where |LLR_oracle| > 2
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_nrx_forward_fp8(variant):
+    """FP8 model: calibrated per-layer activation scales, E4M3 block convs, LLRs against the
+    FP64 oracle (norm-wise error and hard decisions), for each FP8 conv tile shape."""
+    shapes = [dict(n_prb=6, n_ant=8, n_ue=4, bits=[4, 4, 4, 4], slot_number=s) for s in range(3)] + \
+             [dict(n_prb=5, n_ant=4, n_ue=2, bits=[4, 2], slot_number=7)]
+    net, m_max = cgnn.NetConfig(8, 128, 4, 2, 4), 4
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 21, 0, m_max)
+    w = synth.he_weights(cgnn.layout(net), 21, perturb=True)
+    exp = oracle_nrx(w, net, ref_slots)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, L.NRX_FP8)
+    try:
+        descs, sz = L.make_slots(shapes, m_max)
+        y = _upload_batch(shapes, ref_slots)
+        wd = dev(w)
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        with pytest.raises(L.NrxError):
+            L.nrx_forward(model, wd, descs, y, llr, ws)        # no scales yet
+        L.nrx_calibrate(model, wd, descs, y, llr, ws)
+        scales = L.nrx_act_scales(model)
+        log(f"fp8 scales: {np.array2string(scales, precision=4)}")
+        assert scales.size == 2 * net.C + net.R and np.all(scales > 0)
+        for c in (L.NRX_K_CONV_A, L.NRX_K_CONV_A_MP, L.NRX_K_CONV_B):
+            L.nrx_conv_variant(model, c, variant)
+        llr.zero_()
+        L.nrx_forward(model, wd, descs, y, llr, ws)
+        torch.cuda.synchronize()
+        got = split_llr(llr.cpu().numpy(), shapes, m_max)
+        worst, agree_n, agree_d = 0.0, 0, 0
+        for i in range(len(shapes)):
+            for u in range(shapes[i]["n_ue"]):
+                worst = max(worst, rel_err(got[i][u], exp[i][u]))
+                big = np.abs(exp[i][u]) > 2.0
+                agree_n += int(np.sum((got[i][u][big] > 0) == (exp[i][u][big] > 0)))
+                agree_d += int(np.sum(big))
+        log(f"fp8 variant {variant}: worst relative error {worst:.3e}, decision agreement "
+            f"{agree_n / max(agree_d, 1):.5f} over {agree_d}")
+        assert worst <= FP8_TOL
+        assert agree_n >= FP8_AGREE * agree_d
+    finally:
+        L.nrx_model_destroy(model)
