@@ -298,12 +298,12 @@ def nrx_slot_latency(model, slots, ws, latency_us, stream=None):
 def nrx_act_scales(model, scales=None):
     """Returns the FP8 activation scales (numpy float32); sets them first when given."""
     import numpy as np
+    if scales is not None:
+        src = np.ascontiguousarray(scales, dtype=np.float32).reshape(-1)
+        _check(_lib.nrx_act_scales(model, src.ctypes.data, None, src.size))
     n = int(_lib.nrx_act_scale_count(model))
     out = np.zeros(n, dtype=np.float32)
-    src = None
-    if scales is not None:
-        src = np.ascontiguousarray(scales, dtype=np.float32)
-    _check(_lib.nrx_act_scales(model, src.ctypes.data if src is not None else None, out.ctypes.data, n))
+    _check(_lib.nrx_act_scales(model, None, out.ctypes.data, n))
     return out
 
 

@@ -95,3 +95,34 @@ def test_entry_points_reject_before_enqueueing():
         assert e.value.status == L.NRX_ERR_SHAPE
     finally:
         L.nrx_model_destroy(model)
+
+
+def test_fp8_model_host_checks():
+    # FP8 models: one activation scale per scaled tensor, inference only, scales validated
+    model = L.nrx_model_create(8, 128, 6, 2, 4, L.NRX_FP8)
+    plain = L.nrx_model_create(8, 128, 6, 2, 4, L.NRX_BF16)
+    try:
+        import torch
+        t = torch.zeros(16)
+        st = type("S", (), {"cuda_stream": 0})()
+        assert L._lib.nrx_act_scale_count(model) == 2 * 6 + 2
+        assert L._lib.nrx_act_scale_count(plain) == 0
+        sl, _ = L.make_slots([dict(n_prb=4, n_ant=8, n_ue=4, bits=[4] * 4)], 4)
+        assert L.nrx_workspace_bytes(model, sl) > L.nrx_workspace_bytes(plain, sl)   # E4M3 copies and operands
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_forward(model, t, sl, t, t, t, save_acts=True, stream=st)
+        assert e.value.status == L.NRX_ERR_UNSUPPORTED
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_act_scales(model, np.r_[np.ones(13), 0.0])
+        assert e.value.status == L.NRX_ERR_INVALID
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_act_scales(model, np.ones(5))
+        assert e.value.status == L.NRX_ERR_SHAPE
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_calibrate(plain, t, sl, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_INVALID
+        lay8 = L.weight_layout(model)
+        assert lay8 == L.weight_layout(plain)      # same master weights as the BF16 model
+    finally:
+        L.nrx_model_destroy(model)
+        L.nrx_model_destroy(plain)

