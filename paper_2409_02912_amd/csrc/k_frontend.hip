@@ -84,10 +84,14 @@ __global__ void ls_pairs_kernel(const SlotGeo *geo, const float2 *y, const float
 template <typename T>
 __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float2 *pairs, const int64_t *pair_off,
                                 int model_B, int cx, T *X, float2 *h_out) {
+  // one thread per (row, group of 8 input channels): the threads of a row write
+  // its cx channels as adjacent 16/32-byte vectors, a wave a contiguous block
   const int slot = blockIdx.y;
   const SlotGeo g = geo[slot];
   const int S = g.S, U = g.U, B = g.B;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;   // row within the slot
+  const int ngrp = X ? cx / 8 : 1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = (int)(e / ngrp), grp = (int)(e - (int64_t)r * ngrp);   // row within the slot, channel group
   if (r >= S * 14 * U) return;
   const int s = r / (14 * U);
   const int rem = r - s * 14 * U;
@@ -116,26 +120,23 @@ __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float
     return make_float2(wt0 * hl[0].x + wt1 * hl[1].x, wt0 * hl[0].y + wt1 * hl[1].y);
   };
   const float2 *yr = y + g.y_off + ((int64_t)s * 14 + t) * B;
-  if (h_out) {
+  if (h_out && grp == 0) {
     for (int b = 0; b < B; ++b) h_out[g.h_off + (((int64_t)s * 14 + t) * U + u) * B + b] = hval(b);
   }
   if (X) {
     // channel order [Re y | Im y | Re h | Im h], each block model_B wide, zero padded to cx
-    T *dst = X + (g.row_base + r) * cx;
-    for (int c0 = 0; c0 < cx; c0 += 8) {
-      float f[8];
+    float f[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int c = c0 + e, part = c / model_B, b = c - part * model_B;
-        float v = 0.f;
-        if (part < 4 && b < B) {
-          if (part < 2) { float2 q = yr[b]; v = part == 0 ? q.x : q.y; }
-          else { float2 q = hval(b); v = part == 2 ? q.x : q.y; }
-        }
-        f[e] = v;
+    for (int k = 0; k < 8; ++k) {
+      const int c = 8 * grp + k, part = c / model_B, b = c - part * model_B;
+      float v = 0.f;
+      if (part < 4 && b < B) {
+        if (part < 2) { const float2 q = yr[b]; v = part == 0 ? q.x : q.y; }
+        else { const float2 q = hval(b); v = part == 2 ? q.x : q.y; }
       }
-      pack8<T>::store(dst + c0, f);
+      f[k] = v;
     }
+    pack8<T>::store(X + (g.row_base + r) * cx + 8 * grp, f);
   }
 }
 
@@ -155,7 +156,8 @@ template <typename T>
 void launch_features(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_rows, const float2 *y,
                      const float2 *pairs, const int64_t *pair_off, int model_B, int cx, T *X, float2 *h_out,
                      hipStream_t st) {
-  dim3 grid((unsigned)((max_rows + 255) / 256), n_slots);
+  const int64_t threads = max_rows * (X ? cx / 8 : 1);   // one per (row, 8-channel group)
+  dim3 grid((unsigned)((threads + 255) / 256), n_slots);
   hipLaunchKernelGGL(features_kernel<T>, grid, dim3(256), 0, st, geo, y, pairs, pair_off, model_B, cx, X, h_out);
 }
 template void launch_features<float>(const SlotGeo *, const int64_t *, int, int64_t, const float2 *, const float2 *,

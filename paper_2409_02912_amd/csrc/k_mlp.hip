@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
     }
     __syncthreads();   // LDS reads done before the next tile overwrites it
     if (a.slot_done && tid == 0) {
-      // the workgroup that finishes a slot's last readout tile stamps its completion time
-      __threadfence();
+      // the workgroup that finishes a slot's last readout tile stamps the time (its LLR
+      // stores are issued; no fence: a device-scope release would write back the L2 per tile)
       const int per_slot = (S * 14 * U + MLP_ROWS - 1) / MLP_ROWS;
       if (atomicAdd(&a.slot_done[tl.slot], 1u) + 1u == (unsigned)per_slot) a.stamps[tl.slot] = wall_clock64();
     }
