@@ -116,6 +116,22 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
         L.nrx_model_destroy(model)
 
 
+def stored_traffic(conv_b_variant):
+    """HBM bytes per conv_b launch from the committed FETCH_SIZE / WRITE_SIZE passes, or None when the
+    kernel sources or the tile variant differ from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "conv_b_bf16_m273_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for src in d["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != d["sources_sha256"] or conv_b_variant != d["conv_variant"]:
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -340,7 +356,10 @@ def main():
         "batch1_latency_ms": {k: results[k]["batch1_ms"] for k in llrs},
         "roofline": {"bound": "mfma", "kernel": "conv3x3_kernel (residual conv_b, bf16)", "achieved": achieved / 1e12,
                      "peak": PEAKS["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"],
-                     "traffic": None},
+                     "traffic": (stored_traffic(results["variants"]["bf16"]["conv_b"])
+                                 if args.workload == "m" else None),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE, WRITE_SIZE; profiles/)",
+                     "algorithmic_bytes": rows * 768},
     }
     if "fp8" in results:
         ms8 = results["fp8"]["ms_per_step"]
