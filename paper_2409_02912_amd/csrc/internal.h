@@ -37,9 +37,10 @@ struct ConvArgs {
 struct ConvVariant {
   int mb;     // tile = 64 * mb rows (MFMA m-blocks per wave for 4-wave workgroups)
   int occ;    // waves per SIMD the kernel is built for
-  int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS
+  int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS (K loop unrolled
+              // over two chunks: even chunk counts only); 3: the same, rolled (ring kernel)
 };
-#define NRX_CONV_VARIANTS 6
+#define NRX_CONV_VARIANTS 8
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
 #define NRX_CONV8_VARIANTS 3
 extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64

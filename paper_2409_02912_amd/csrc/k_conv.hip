@@ -366,6 +366,173 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
   conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(lds_b0), a.ln_part, tid, wave, lr, lk);
 }
 
+// Ring variant: the same operands-in-LDS scheme with the K loop rolled and the
+// global -> LDS copies issued as inline assembly (dma16), so buffer slots are
+// chosen at run time without the compiler draining the DMA queue before LDS
+// reads.  G taps of weights per ring slot (G = 1: 8 KB slots, small enough for
+// two 256-row workgroups per CU, so one workgroup's epilogue overlaps the other's
+// MFMAs; G = 3: the 3-tap groups of conv3x3_lds_kernel).
+template <typename T, int EPI, int MB, int NW, int G, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> a) {
+  constexpr int TILE = 16 * MB * NW;
+  constexpr int HMAX = halo_rows_max(TILE);
+  constexpr int NINS = HMAX / 16;
+  constexpr int APW = (NINS + NW - 1) / NW;
+  constexpr int AROWS = APW * NW * 16;
+  constexpr int ZROW = AROWS;
+  constexpr int KC = 64 / (int)sizeof(T);
+  constexpr int NG = 9 / G;                        // weight groups per chunk
+  constexpr int BROWS = G * 8 * 16;                // 64-byte weight rows per group
+  constexpr int BINS = BROWS / 16;                 // weight DMA instructions per group
+  constexpr int BPW = (BINS + NW - 1) / NW;
+  static_assert(9 % G == 0 && APW < 16, "shape");
+  __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
+  __shared__ __align__(16) unsigned char lds_b[2][BROWS * ROWB];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  if (tid < 4) {
+    v16 z = {{0, 0, 0, 0}};
+    st16(&lds_a[0][ZROW * ROWB + tid * 16], z);
+    st16(&lds_a[1][ZROW * ROWB + tid * 16], z);
+  }
+  const int nch = (a.c0 + a.c1) / KC;
+  float lnp[EPI == EPI_LN_BWD ? 16 : 1];
+#pragma unroll
+  for (int k = 0; k < (EPI == EPI_LN_BWD ? 16 : 1); ++k) lnp[k] = 0.f;
+
+  const int Gd = gridDim.x;
+  const int lb = (blockIdx.x & 7) * (Gd >> 3) + (blockIdx.x >> 3);
+  const i32x4_t wrs = rsrc_words(a.w, 0x7FFFFFFF);
+  // weights of group k (chunk k / NG, taps G * (k % NG) ..) into ring slot b
+  auto stage_b = [&](int k, int b) {
+    const int c = k / NG, grp = k - NG * c;
+    const uint32_t base = (uint32_t)((c * 9 + G * grp) * 8 * 16) * ROWB;
+#pragma unroll
+    for (int j = 0; j < BPW; ++j) {
+      const int ins = wave + NW * j;
+      if (BINS % NW == 0 || ins < BINS) {
+        const int row = ins * 16 + (lane >> 2);
+        const int piece = (lane & 3) ^ swz(row);
+        dma16(wrs, lds_addr(&lds_b[b][ins * 16 * ROWB]), base + row * ROWB + piece * 16);
+      }
+    }
+  };
+  struct Geo {
+    int64_t row_base;
+    int rel0, halo, S, rps, U;
+  };
+  auto geo_of = [&](const Tile &tl) {
+    const SlotGeo g = ldc_geo(a.geo + tl.slot);
+    Geo q;
+    q.U = g.U;
+    q.S = g.S;
+    q.rps = 14 * g.U;
+    const int s_first = tl.row0 / q.rps;
+    const int s_last = (tl.row0 + tl.nrows - 1) / q.rps;
+    q.halo = (s_last - s_first + 3) * q.rps;
+    q.rel0 = (s_first - 1) * q.rps;
+    q.row_base = g.row_base;
+    return q;
+  };
+  auto stage_a = [&](const Geo &q, int c, int b) {
+    const T *src;
+    int cs, coff;
+    if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
+    else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
+    const i32x4_t rs = rsrc_words(src + q.row_base * cs + coff, q.S * q.rps * cs * (int)sizeof(T));
+#pragma unroll
+    for (int j = 0; j < APW; ++j) {
+      const int ins = wave + NW * j;
+      const int h = ins * 16 + (lane >> 2);
+      const int piece = (lane & 3) ^ swz(h);
+      // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
+      const uint32_t voff = h < q.halo ? (uint32_t)((q.rel0 + h) * cs * (int)sizeof(T) + piece * 16) : 0x80000000u;
+      dma16(rs, lds_addr(&lds_a[b][ins * 16 * ROWB]), voff);
+    }
+  };
+  constexpr int WAIT_ALL = 0;
+  constexpr int WAIT_KEEP_A = (0xF << 8) | (7 << 4) | APW;   // vmcnt <= APW, no wait on lgkm/exp
+
+  int ka = 0, kb = 0;
+  int tile = lb;
+  if (tile < a.n_tiles) {
+    stage_b(0, 0);
+    stage_a(geo_of(ldc(a.tiles + tile)), 0, 0);
+    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    dma_barrier();
+  }
+  for (; tile < a.n_tiles; tile += Gd) {
+    const Tile tl = ldc(a.tiles + tile);
+    const Geo q = geo_of(tl);
+    int hc[MB], tt[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int r = wave * 16 * MB + mb * 16 + lr;
+      const int R = tl.row0 + r;
+      const int s = R / q.rps;
+      tt[mb] = r < tl.nrows ? (R - s * q.rps) / q.U : -1;
+      hc[mb] = R - q.rel0;
+    }
+    f32x4_t acc[MB][8];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int ngrp = NG * nch;
+    const int next_tile = tile + Gd;
+#pragma unroll 1
+    for (int k = 0; k < ngrp; ++k) {
+      const int c = k / NG, grp = k - NG * c;
+      bool a_issued = false;
+      if (k + 1 < ngrp) {
+        stage_b(k + 1, (kb + 1) & 1);
+        if (grp == 0 && c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); a_issued = true; }
+      } else if (next_tile < a.n_tiles) {
+        stage_b(0, (kb + 1) & 1);
+        stage_a(geo_of(ldc(a.tiles + next_tile)), 0, (ka + 1) & 1);
+      }
+      const unsigned char *la = &lds_a[ka & 1][0];
+      const unsigned char *lbr = &lds_b[kb & 1][0];
+#pragma unroll 1
+      for (int tg = 0; tg < G; ++tg) {
+        const int tap = G * grp + tg;
+        const int di = tap / 3 - 1, dj = tap % 3 - 1;
+        const int off = di * q.rps + dj * q.U;
+        v16 af[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+          const bool ok = tt[mb] >= 0 && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
+          const int row = ok ? hc[mb] + off : ZROW;
+          af[mb] = ld16(la + row * ROWB + ((lk ^ swz(row)) << 4));
+        }
+        auto load_bf = [&](int nb) {
+          const int brow = (tg * 8 + nb) * 16 + lr;
+          return ld16(lbr + brow * ROWB + ((lk ^ swz(brow)) << 4));
+        };
+        v16 bcur = load_bf(0);
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) {
+          const v16 bnext = nb < 7 ? load_bf(nb + 1) : bcur;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(af[mb], bcur, acc[mb][nb]);
+          bcur = bnext;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if (a_issued) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
+      else __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+      dma_barrier();
+      kb += 1;
+      if (grp == NG - 1) ka += 1;
+    }
+    conv_epilogue<T, MB, EPI>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
+  }
+  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
+}
+
 }  // namespace
 
 // Compiled shapes: rows per wave (16*MB), waves per SIMD, B-operand prefetch.
@@ -377,6 +544,8 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {2, 2, 0},   // 128-row tiles, 2 waves/SIMD, no prefetch
     {NRX_LDS_MB, 1, 2},   // 384-row tiles, 1 wave/SIMD, weights and halo both through LDS
     {8, 2, 2},            // 512-row tiles of 8 waves (4 m-blocks each), 2 waves/SIMD, operands through LDS
+    {4, 2, 3},            // ring kernel: 256-row tiles of 4 waves, 1-tap weight slots, 2 workgroups/CU
+    {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, 3-tap slots, 1 workgroup/CU
 };
 
 template <typename T>
@@ -413,6 +582,22 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_LDS_CASE(4, NRX_LDS_MB, 4)
   NRX_LDS_CASE(5, 4, 8)
 #undef NRX_LDS_CASE
+#define NRX_RING_CASE(V, M, NWV, GV, OCCV)                                                              \
+  if (variant == V) {                                                                                   \
+    dim3 b2(64 * NWV);                                                                                  \
+    if (epi == EPI_STORE)                                                                               \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+    else if (epi == EPI_LN_RELU)                                                                        \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+    else if (epi == EPI_RESID)                                                                          \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+    else                                                                                                \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+    return;                                                                                             \
+  }
+  NRX_RING_CASE(6, 4, 4, 1, 2)
+  NRX_RING_CASE(7, 4, 8, 3, 1)
+#undef NRX_RING_CASE
 }
 
 template void launch_conv<float>(const ConvArgs<float> &, int, int, int, hipStream_t);
