@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (oracle).  Plain fp64 / integer code, no blocking.
 
-Paper basis: pilots are DMRS "type A with one additional position" (Sec. IV-C,
-simulation setup) known to the BS (Sec. II); constellations are Gray-labelled
+Paper basis: the pilots are mapping-type-A DMRS with one additional DMRS symbol
+(Sec. III-B, simulation setup), known to the BS (Sec. II); constellations are Gray-labelled
 QAM per the 5G NR MCS table (Sec. II), whose recursive labelling is what LLR
 masking relies on (Sec. III).  The sequence, mapping and modulation formulas are
 those of 3GPP TS 38.211 (Sec. 5.2.1 Gold sequence, 5.1 modulation, 6.4.1.1 PUSCH

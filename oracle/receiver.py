@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (oracle).
 The paper's NRX takes, per UE stream, an initial LS channel estimate from the
 DMRS (Sec. II-A, architecture description), and its classical baseline is LS
 channel estimation with interpolation followed by LMMSE equalisation and
-demapping (Sec. IV-C comparison).  LLRs are logits, positive meaning bit 1,
+demapping (Sec. III-B comparison).  LLRs are logits, positive meaning bit 1,
 Eq. (2).  Readings: despreading assumes equal channel on the two REs of an OCC
 pair; interpolation is linear with flat extrapolation, in frequency between pair
 centres and in time between the two DMRS symbols.

@@ -1,7 +1,7 @@
 // Classical judge / fallback: LMMSE equalisation and max-log Gray-QAM demapping.
 //
 // The paper's baseline receiver is LS channel estimation with interpolation,
-// LMMSE equalisation and demapping (Sec. IV-C).  Per data RE, with the channel
+// LMMSE equalisation and demapping (Sec. III-B).  Per data RE, with the channel
 // estimate taken as exact and unit-energy symbols:
 //   G = H^H H + N0 I (U x U), solved by an fp64 Cholesky factorisation,
 //   z~ = G^-1 H^H y, d_u = 1 - N0 [G^-1]_uu, z_u = z~_u / d_u,
