@@ -496,31 +496,40 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
       }
       const unsigned char *la = &lds_a[ka & 1][0];
       const unsigned char *lbr = &lds_b[kb & 1][0];
-#pragma unroll 1
-      for (int tg = 0; tg < G; ++tg) {
+      // the G taps x 8 n-blocks of the group as one software pipeline: weight
+      // fragments two steps ahead, the next tap's activation fragments half a tap ahead
+      auto load_a = [&](int tg, v16 *af) {
         const int tap = G * grp + tg;
         const int di = tap / 3 - 1, dj = tap % 3 - 1;
         const int off = di * q.rps + dj * q.U;
-        v16 af[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
           const bool ok = tt[mb] >= 0 && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
           const int row = ok ? hc[mb] + off : ZROW;
           af[mb] = ld16(la + row * ROWB + ((lk ^ swz(row)) << 4));
         }
-        auto load_bf = [&](int nb) {
-          const int brow = (tg * 8 + nb) * 16 + lr;
-          return ld16(lbr + brow * ROWB + ((lk ^ swz(brow)) << 4));
-        };
-        v16 bcur = load_bf(0);
+      };
+      auto load_bf = [&](int i) {
+        const int brow = i * 16 + lr;   // step i = tg * 8 + nb
+        return ld16(lbr + brow * ROWB + ((lk ^ swz(brow)) << 4));
+      };
+      v16 afc[MB], afn[MB];
+      load_a(0, afc);
+      v16 b0 = load_bf(0), b1 = load_bf(1);
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          const v16 bnext = nb < 7 ? load_bf(nb + 1) : bcur;
+      for (int i = 0; i < 8 * G; ++i) {
+        const int nb = i & 7;
+        const v16 b2 = i + 2 < 8 * G ? load_bf(i + 2) : b1;
+        if (nb == 4 && i / 8 + 1 < G) load_a(i / 8 + 1, afn);
 #pragma unroll
-          for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(af[mb], bcur, acc[mb][nb]);
-          bcur = bnext;
-          __builtin_amdgcn_sched_barrier(0);
+        for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(afc[mb], b0, acc[mb][nb]);
+        if (nb == 7 && i / 8 + 1 < G) {
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) afc[mb] = afn[mb];
         }
+        b0 = b1;
+        b1 = b2;
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (a_issued) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
       else __builtin_amdgcn_s_waitcnt(WAIT_ALL);
