@@ -170,11 +170,15 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
         float sm = 0.f;
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) sm += v[nb];
-        const float mean = row_sum16(sm) * (1.0f / NRX_D);
+        // channels at or beyond the state depth carry exact zeros (zero weights and bias)
+        const float mean = row_sum16(sm) * a.ln_inv;
         float sq = 0.f;
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) { float dv = v[nb] - mean; sq += dv * dv; }
-        const float var = row_sum16(sq) * (1.0f / NRX_D);
+        for (int nb = 0; nb < 8; ++nb) {
+          const float dv = v[nb] - mean;
+          sq += ch0 + nb < a.ln_d ? dv * dv : 0.f;
+        }
+        const float var = row_sum16(sq) * a.ln_inv;
         const float rstd = 1.0f / sqrtf(var + 1e-5f);
         if (valid && a.save_z) {
           pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);

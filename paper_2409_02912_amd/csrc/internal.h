@@ -15,7 +15,9 @@ struct ConvArgs {
   const T *w;               // prepped [chunk][tap][nb][16][KC]
   const float *bias;        // [128]
   const float *pe;          // positional-encoding field [2][3][14][128] or null
-  const float *ln_g, *ln_b; // [128] (EPI_LN_RELU)
+  const float *ln_g, *ln_b; // [128] (EPI_LN_RELU; zero beyond the state depth d)
+  float ln_inv;             // 1 / d: LayerNorm statistics over the first d channels (the rest are zero)
+  int ln_d;
   const T *resid;           // [rows][128] (EPI_RESID)
   T *out;                   // [rows][128]
   T *save_z;                // pre-LN output (EPI_LN_RELU, training; input of EPI_LN_BWD) or null
@@ -67,7 +69,7 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
 // Weight preparation: fp32 master -> MFMA operand layouts and PE fields.
 struct PrepJob {
   int32_t kind;        // 0 conv, 1 dense, 2 PE field, 3 conv transposed+flipped (dgrad), 4 narrow dense,
-                       // 5 dense transposed
+                       // 5 dense transposed, 6 vector zero-padded to 128 (into the field buffer)
   int32_t cin_real;    // input channels present in the master tensor (conv: without PE)
   int32_t cin_total;   // input channels of the master tensor (incl. PE channels)
   int32_t n_chunks;    // K chunks of the prepped operand
@@ -76,6 +78,8 @@ struct PrepJob {
   int64_t src;         // element offset into the master weights
   int64_t dst;         // element offset into the prepped (T) or field (fp32) buffer
   int64_t count;       // prepped elements of this job
+  int32_t d_out;       // output columns of the master conv/dense tensor (the state depth d <= 128)
+  int32_t seg;         // master input channels per 128-wide activation segment (0: identity map)
 };
 
 template <typename T>

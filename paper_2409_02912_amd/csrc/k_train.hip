@@ -56,11 +56,17 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
       for (int j = 0; j < 3; ++j) {
         const int tt = t + j - 1;
         if (tt < 0 || tt >= 14) continue;
-        const int64_t wt = J.src + ((int64_t)(i * 3 + j) * J.cin_total + J.cin_real) * NRX_D + o;
-        acc += w[wt] * pe_t_value(tt) + w[wt + NRX_D] * pf;
+        if (o >= J.d_out) continue;
+        const int64_t wt = J.src + ((int64_t)(i * 3 + j) * J.cin_total + J.cin_real) * J.d_out + o;
+        acc += w[wt] * pe_t_value(tt) + w[wt + J.d_out] * pf;
       }
     }
     fields[J.dst + k] = acc;
+    return;
+  }
+  if (J.kind == 6) {
+    // bias / LayerNorm vector padded with zeros to 128 channels
+    fields[J.dst + k] = k < J.cin_real ? w[J.src + k] : 0.f;
     return;
   }
   const int kl = k % KC;   // channel within the K chunk (natural order)
@@ -68,7 +74,7 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
     // narrow dense [chunk][16][KC]: column j = output j (zero beyond n_out)
     const int j = (k / KC) % 16, chunk = k / (16 * KC);
     const int c = chunk * KC + kl;
-    wprep[J.dst + k] = elem<T>::from_f(j < J.n_out ? w[J.src + (int64_t)c * J.n_out + j] : 0.f);
+    wprep[J.dst + k] = elem<T>::from_f(j < J.n_out && c < J.cin_real ? w[J.src + (int64_t)c * J.n_out + j] : 0.f);
     return;
   }
   const int j = (k / KC) % 16, nb = (k / (16 * KC)) % 8;
@@ -77,7 +83,7 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
   if (J.kind == 1) {
     const int chunk = k / (128 * KC);
     const int c = chunk * KC + kl;
-    if (c < J.cin_real) v = w[J.src + (int64_t)c * NRX_D + n];
+    if (c < J.cin_real && n < J.d_out) v = w[J.src + (int64_t)c * J.d_out + n];
   } else if (J.kind == 5) {
     // transposed dense: B[k = c][n] = W[n][c]
     const int chunk = k / (128 * KC);
@@ -87,7 +93,10 @@ __global__ void prep_kernel(const float *w, const PrepJob *jobs, int n_jobs, int
     const int tap = (k / (128 * KC)) % 9, chunk = k / (1152 * KC);
     const int c = chunk * KC + kl;
     if (J.kind == 0) {
-      if (c < J.cin_real) v = w[J.src + ((int64_t)tap * J.cin_total + c) * NRX_D + n];
+      // activation channel c -> master input channel (block convs: 128-wide segments of d channels)
+      const int cm = J.seg ? (c / NRX_D) * J.seg + (c % NRX_D) : c;
+      const bool in = J.seg ? (c % NRX_D) < J.seg : true;
+      if (in && cm < J.cin_real && n < J.d_out) v = w[J.src + ((int64_t)tap * J.cin_total + cm) * J.d_out + n];
     } else {
       // transposed, flipped: K = original output channel c, N = original input channel cin_first + n
       v = w[J.src + ((int64_t)(8 - tap) * J.cin_total + J.cin_first + n) * NRX_D + c];

@@ -68,11 +68,13 @@ struct ConvLayer {
   int64_t prep = 0;             // element offset in the prepped buffer
   int64_t field = -1;           // element offset in the field buffer (PE folded) or -1
   int64_t w8 = -1, ws8 = -1;    // FP8 models: byte offset of the E4M3 operand, float offset of its scales
+  int64_t bpad = -1;            // d < 128: bias padded to 128 channels (field buffer offset)
 };
 
 struct BlockLayer {
   ConvLayer a, b;
   int64_t g = 0, beta = 0;
+  int64_t gpad = -1, betapad = -1;   // d < 128: LayerNorm parameters padded with zeros
   int mp_round = -1;            // message-passing round before this block, or -1
   // backward: prepped data-gradient weights (offsets in the backward prepped buffer)
   int64_t bg_b = 0, bg_a_h = 0, bg_a_agg = -1;
@@ -80,6 +82,7 @@ struct BlockLayer {
 
 struct DenseLayer {
   int64_t w1 = 0, b1 = 0, w2 = 0, b2 = 0;
+  int64_t b1pad = -1, b2pad = -1;   // d < 128: biases padded with zeros
   int64_t p1 = 0, p2 = -1;      // prepped offsets
   int64_t t1 = -1, t2 = -1;     // backward: prepped transposed weights
 };
@@ -344,13 +347,14 @@ static int64_t toff(nrx_model *m, const std::string &name) {
 extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **out) {
   if (!cfg || !out) return fail(NRX_ERR_INVALID, "null argument");
   const nrx_model_config &c = *cfg;
-  if (c.d != NRX_D) return fail(NRX_ERR_SHAPE, "d = %d: this build supports d = 128", c.d);
+  if (c.d < 8 || c.d > NRX_D || c.d % 8) return fail(NRX_ERR_SHAPE, "d = %d: state depth must be a multiple of 8 in 8..128", c.d);
   if (c.n_ant != 4 && c.n_ant != 8 && c.n_ant != 16) return fail(NRX_ERR_SHAPE, "n_ant %d not in {4, 8, 16}", c.n_ant);
   if (c.n_blocks < 1 || c.n_blocks > 16) return fail(NRX_ERR_SHAPE, "n_blocks %d outside 1..16", c.n_blocks);
   if (c.n_rounds < 0 || c.n_rounds > c.n_blocks) return fail(NRX_ERR_SHAPE, "n_rounds %d outside 0..n_blocks", c.n_rounds);
   if (c.m_max != 2 && c.m_max != 4 && c.m_max != 6 && c.m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", c.m_max);
   if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
+  if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
   auto m = std::make_unique<nrx_model>();
   m->cfg = c;
   m->tsize = c.precision == NRX_FP32 ? 4 : 2;   // FP8 models keep BF16 for everything but the block convs
@@ -387,26 +391,30 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
 
   // weight preparation jobs
   const int KC = 64 / (int)m->tsize;
-  auto conv_job = [&](ConvLayer &L, int64_t w, int64_t b, int cin_real, int cin_total, int cin_pad, bool pe) {
+  // seg: master input channels per 128-wide activation segment (block convs: d; StateInit: identity)
+  auto conv_job = [&](ConvLayer &L, int64_t w, int64_t b, int cin_real, int cin_total, int cin_pad, bool pe, int seg) {
     L.w = w; L.b = b; L.cin_real = cin_real; L.cin_total = cin_total; L.n_chunks = cin_pad / KC;
     L.prep = m->prep_elems;
-    PrepJob j{0, cin_real, cin_total, L.n_chunks, 0, 0, w, L.prep, (int64_t)cin_pad * 9 * 128};
+    PrepJob j{0, cin_real, cin_total, L.n_chunks, 0, 0, w, L.prep, (int64_t)cin_pad * 9 * 128, d, seg};
     m->jobs.push_back(j);
     m->prep_elems += j.count;
     if (pe) {
       L.field = m->field_elems;
-      PrepJob f{2, cin_real, cin_total, 0, 0, 0, w, L.field, 2 * 3 * 14 * 128};
+      PrepJob f{2, cin_real, cin_total, 0, 0, 0, w, L.field, 2 * 3 * 14 * 128, d, 0};
       m->jobs.push_back(f);
       m->field_elems += f.count;
     }
   };
   auto dense_job = [&](int64_t w, int64_t &p) {
     p = m->prep_elems;
-    PrepJob j{1, d, d, d / KC, 0, 0, w, p, (int64_t)d * 128};
+    PrepJob j{1, d, d, NRX_D / KC, 0, 0, w, p, (int64_t)NRX_D * 128, d, 0};
     m->jobs.push_back(j);
     m->prep_elems += j.count;
   };
-  conv_job(m->conv_in, toff(m.get(), "conv_in.w"), toff(m.get(), "conv_in.b"), 4 * B, 4 * B + 2, m->cx, true);
+  // d < 128: vectors padded with zeros, placed in the field buffer after the PE fields
+  std::vector<std::pair<int64_t, int64_t *>> pads;
+  auto pad_vec = [&](int64_t src, int64_t *dst) { if (d < NRX_D) pads.push_back({src, dst}); };
+  conv_job(m->conv_in, toff(m.get(), "conv_in.w"), toff(m.get(), "conv_in.b"), 4 * B, 4 * B + 2, m->cx, true, 0);
   m->mp.resize(c.n_rounds);
   for (int i = 0; i < c.n_blocks; ++i) {
     const std::string p = "blk" + std::to_string(i);
@@ -415,10 +423,10 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
       if (mpb[r] == i) L.mp_round = r;
     const bool isb = L.mp_round >= 0;
     conv_job(L.a, toff(m.get(), p + ".conv_a.w"), toff(m.get(), p + ".conv_a.b"), isb ? 2 * d : d,
-             isb ? 2 * d + 2 : d, isb ? 2 * d : d, isb);
+             isb ? 2 * d + 2 : d, isb ? 2 * NRX_D : NRX_D, isb, d);
     L.g = toff(m.get(), p + ".ln.g");
     L.beta = toff(m.get(), p + ".ln.b");
-    conv_job(L.b, toff(m.get(), p + ".conv_b.w"), toff(m.get(), p + ".conv_b.b"), d, d, d, false);
+    conv_job(L.b, toff(m.get(), p + ".conv_b.w"), toff(m.get(), p + ".conv_b.b"), d, d, NRX_D, false, d);
     if (m->fp8) {
       for (ConvLayer *cl : {&L.a, &L.b}) {
         cl->w8 = m->w8_bytes;
@@ -443,14 +451,14 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   dense_job(m->ro.w1, m->ro.p1);
   {
     m->ro.p2 = m->prep_elems;
-    PrepJob j{4, d, d, d / KC, 0, c.m_max, m->ro.w2, m->ro.p2, (int64_t)d * 16};
+    PrepJob j{4, d, d, NRX_D / KC, 0, c.m_max, m->ro.w2, m->ro.p2, (int64_t)NRX_D * 16, d, 0};
     m->jobs.push_back(j);
     m->prep_elems += j.count;
   }
   // backward jobs: flipped/transposed conv weights and transposed dense weights
   auto bjob = [&](int kind, int64_t src, int cin_total, int cin_first, int64_t count) {
     const int64_t off = m->bprep_elems;
-    m->bjobs.push_back(PrepJob{kind, d, cin_total, d / KC, cin_first, 0, src, off, count});
+    m->bjobs.push_back(PrepJob{kind, d, cin_total, d / KC, cin_first, 0, src, off, count, d, 0});
     m->bprep_elems += count;
     return off;
   };
@@ -465,6 +473,22 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     m->mp[r].t2 = bjob(5, m->mp[r].w2, d, 0, (int64_t)d * 128);
   }
   m->ro.t1 = bjob(5, m->ro.w1, d, 0, (int64_t)d * 128);
+  if (d < NRX_D) {
+    pad_vec(m->conv_in.b, &m->conv_in.bpad);
+    for (auto &L : m->blocks) {
+      pad_vec(L.a.b, &L.a.bpad);
+      pad_vec(L.b.b, &L.b.bpad);
+      pad_vec(L.g, &L.gpad);
+      pad_vec(L.beta, &L.betapad);
+    }
+    for (auto &L : m->mp) { pad_vec(L.b1, &L.b1pad); pad_vec(L.b2, &L.b2pad); }
+    pad_vec(m->ro.b1, &m->ro.b1pad);
+    for (auto &pv : pads) {
+      *pv.second = m->field_elems;
+      m->jobs.push_back(PrepJob{6, d, d, 0, 0, 0, pv.first, m->field_elems, NRX_D, d, 0});
+      m->field_elems += NRX_D;
+    }
+  }
   // field jobs index a separate buffer; the prep kernel walks jobs in order over one index space
   m->prep_total = 0;
   for (auto &j : m->jobs) m->prep_total += j.count;
@@ -674,13 +698,17 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     launch_conv<T>(ca, epi, v, grid, st);
   };
   auto buf = [&](size_t off) { return (T *)(ws + off); };
+  // a bias / LayerNorm vector: the master weights, or its zero-padded copy when d < 128
+  auto vec = [&](int64_t master, int64_t pad) { return pad >= 0 ? fields + pad : w + master; };
 
   ConvArgs<T> a{};
   a.geo = D.geo;
+  a.ln_inv = 1.0f / (float)m->cfg.d;
+  a.ln_d = m->cfg.d;
   // StateInit
   a.src0 = X; a.c0 = m->cx; a.src1 = nullptr; a.c1 = 0;
   a.w = wprep + m->conv_in.prep;
-  a.bias = w + m->conv_in.b;
+  a.bias = vec(m->conv_in.b, m->conv_in.bpad);
   a.pe = fields + m->conv_in.field;
   a.out = buf(L.h[0]);
   ConvArgs<T> a0 = a;
@@ -700,8 +728,8 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ma.h = h_in;
       ma.w1 = wprep + m->mp[r].p1;
       ma.w2 = wprep + m->mp[r].p2;
-      ma.b1 = w + m->mp[r].b1;
-      ma.b2 = w + m->mp[r].b2;
+      ma.b1 = vec(m->mp[r].b1, m->mp[r].b1pad);
+      ma.b2 = vec(m->mp[r].b2, m->mp[r].b2pad);
       ma.out = agg;
       if (f8) { ma.out = nullptr; ma.out8 = agg8; ma.out8_inv = inv_scale(2 * C + r); }
       if (amax) ma.amax = amax + 2 * C + r;
@@ -716,10 +744,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ca.src0 = h_in; ca.c0 = NRX_D;
     ca.src1 = agg; ca.c1 = agg ? NRX_D : 0;
     ca.w = wprep + B.a.prep;
-    ca.bias = w + B.a.b;
+    ca.bias = vec(B.a.b, B.a.bpad);
     ca.pe = B.a.field >= 0 ? fields + B.a.field : nullptr;
-    ca.ln_g = w + B.g;
-    ca.ln_b = w + B.beta;
+    ca.ln_g = vec(B.g, B.gpad);
+    ca.ln_b = vec(B.beta, B.betapad);
     ca.out = abuf;
     ca.save_z = save ? buf(L.z[i]) : nullptr;
     ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
@@ -737,7 +765,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
-    cb.bias = w + B.b.b;
+    cb.bias = vec(B.b.b, B.b.bpad);
     cb.pe = nullptr;
     cb.resid = h_in;
     cb.out = h_out;
@@ -753,7 +781,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   MlpArgs<T> ra{};
   ra.h = buf(L.h[save ? C : 0]);
   ra.w1 = wprep + m->ro.p1;
-  ra.b1 = w + m->ro.b1;
+  ra.b1 = vec(m->ro.b1, m->ro.b1pad);
   ra.b2 = w + m->ro.b2;
   ra.w2 = wprep + m->ro.p2;
   ra.save_m1 = save ? buf(L.q) : nullptr;
@@ -794,6 +822,7 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
   if (s != NRX_OK) return s;
   if (m->fp8 && save_acts) return fail(NRX_ERR_UNSUPPORTED, "FP8 models are inference-only (train in BF16)");
+  if (m->cfg.d != NRX_D && save_acts) return fail(NRX_ERR_UNSUPPORTED, "training needs d = 128 in this build");
   const FwdLayout L = fwd_layout(m, P, save_acts != 0);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
   auto run = [&](hipStream_t s2) {

@@ -9,7 +9,7 @@ import numpy as np
 WORKLOADS = {
     # small single-UE case the oracle finishes in seconds
     "c1": dict(n_slots=16, n_prb=4, n_ant=4, n_ue=1, m=2, n_taps=3, decay_ns=100.0, doppler=0.0, rho=0.0,
-               snr=(10.0, 10.0), d=128, n_blocks=2, n_rounds=0),
+               snr=(10.0, 10.0), d=32, n_blocks=2, n_rounds=0),
     "c2": dict(n_slots=32, n_prb=273, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=100.0, rho=0.0,
                snr=(0.0, 20.0), d=128, n_blocks=6, n_rounds=2),
     "c3": dict(n_slots=64, n_prb=106, n_ant=16, n_ue=4, m=6, n_taps=24, decay_ns=305.02, doppler=0.0, rho=0.5,

@@ -27,26 +27,33 @@ def test_library_exports_every_declared_symbol():
     assert decl == set(L.EXPORTED)
 
 
-@pytest.mark.parametrize("B,C,R,m", [(8, 6, 2, 4), (16, 8, 3, 6), (4, 2, 0, 2), (4, 6, 2, 8)])
-def test_weight_layout_matches_oracle(B, C, R, m):
-    model = L.nrx_model_create(B, 128, C, R, m)
+@pytest.mark.parametrize("B,d,C,R,m", [(8, 128, 6, 2, 4), (16, 128, 8, 3, 6), (4, 128, 2, 0, 2), (4, 128, 6, 2, 8),
+                                       (4, 32, 2, 0, 2), (8, 64, 3, 2, 6)])
+def test_weight_layout_matches_oracle(B, d, C, R, m):
+    model = L.nrx_model_create(B, d, C, R, m)
     try:
         lay = L.weight_layout(model)
-        ref = cgnn.layout(cgnn.NetConfig(B, 128, C, R, m))
+        ref = cgnn.layout(cgnn.NetConfig(B, d, C, R, m))
         off = 0
         assert len(lay) == len(ref)
         for (n1, o1, s1), (n2, s2) in zip(lay, ref):
             assert (n1, o1, s1) == (n2, off, tuple(s2))
             off += int(np.prod(s2))
-        assert L.nrx_weight_count(model) == off == cgnn.n_params(cgnn.NetConfig(B, 128, C, R, m))
+        assert L.nrx_weight_count(model) == off == cgnn.n_params(cgnn.NetConfig(B, d, C, R, m))
     finally:
         L.nrx_model_destroy(model)
 
 
 def test_model_config_errors():
     with pytest.raises(L.NrxError) as e:
-        L.nrx_model_create(8, 96, 6, 2, 4)
+        L.nrx_model_create(8, 100, 6, 2, 4)          # state depth not a multiple of 8
     assert e.value.status == L.NRX_ERR_SHAPE
+    with pytest.raises(L.NrxError) as e:
+        L.nrx_model_create(8, 256, 6, 2, 4)          # deeper than the 128-channel kernels
+    assert e.value.status == L.NRX_ERR_SHAPE
+    with pytest.raises(L.NrxError) as e:
+        L.nrx_model_create(8, 32, 6, 2, 4, L.NRX_FP8)
+    assert e.value.status == L.NRX_ERR_UNSUPPORTED
     with pytest.raises(L.NrxError) as e:
         L.nrx_model_create(8, 128, 6, 7, 4)
     assert e.value.status == L.NRX_ERR_SHAPE
