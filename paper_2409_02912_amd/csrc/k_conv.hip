@@ -369,10 +369,22 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
 // Ring variant: the same operands-in-LDS scheme with the K loop rolled and the
 // global -> LDS copies issued as inline assembly (dma16), so buffer slots are
 // chosen at run time without the compiler draining the DMA queue before LDS
-// reads.  G taps of weights per ring slot (G = 1: 8 KB slots, small enough for
-// two 256-row workgroups per CU, so one workgroup's epilogue overlaps the other's
-// MFMAs; G = 3: the 3-tap groups of conv3x3_lds_kernel).
-template <typename T, int EPI, int MB, int NW, int G, int OCC>
+// reads.  G taps of weights per ring slot and NBUF slots: the weights of group
+// k + NBUF - 1 are requested while group k computes (weights are the same for
+// every tile, so the ring runs on across tiles), which hides NBUF - 1 groups of
+// DMA latency.  The next chunk's halo (or the next tile's first chunk) is
+// requested at the first group of a chunk.  G = 1 with small slots also lets two
+// 256-row workgroups share a CU, so one workgroup's epilogue overlaps the other's
+// MFMAs.
+//
+// DMA accounting (per wave, in issue order): every group issues BPW weight
+// copies, and a chunk's first group APW halo copies after them.  At the end of
+// group k the weights of group k + 1 must have landed; they were requested NBUF - 2
+// groups earlier, and at least (NBUF - 2) BPW weight copies (plus APW halo copies
+// if a halo was requested since) were issued after them, so s_waitcnt vmcnt of that
+// count suffices.  A halo requested at a chunk's first group is covered by the
+// wait at the chunk's last group (NG - 1 > NBUF - 2 groups later).
+template <typename T, int EPI, int MB, int NW, int G, int OCC, int NBUF>
 __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> a) {
   constexpr int TILE = 16 * MB * NW;
   constexpr int HMAX = halo_rows_max(TILE);
@@ -384,10 +396,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
   constexpr int NG = 9 / G;                        // weight groups per chunk
   constexpr int BROWS = G * 8 * 16;                // 64-byte weight rows per group
   constexpr int BINS = BROWS / 16;                 // weight DMA instructions per group
-  constexpr int BPW = (BINS + NW - 1) / NW;
-  static_assert(9 % G == 0 && APW < 16, "shape");
+  constexpr int BPW = BINS / NW;
+  static_assert(9 % G == 0 && BINS % NW == 0, "shape");
+  static_assert(NBUF >= 2 && NG - 1 > NBUF - 2, "ring depth");
+  constexpr int NB_ = (NBUF - 2) * BPW;
+  static_assert(NB_ + APW < 16, "vmcnt immediate below");
+  constexpr int WAIT_B = (0xF << 8) | (7 << 4) | NB_;            // weights of the next group landed
+  constexpr int WAIT_BA = (0xF << 8) | (7 << 4) | (NB_ + APW);   // the same with a halo issued since
   __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
-  __shared__ __align__(16) unsigned char lds_b[2][BROWS * ROWB];
+  __shared__ __align__(16) unsigned char lds_b[NBUF][BROWS * ROWB];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -412,11 +429,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       const int ins = wave + NW * j;
-      if (BINS % NW == 0 || ins < BINS) {
-        const int row = ins * 16 + (lane >> 2);
-        const int piece = (lane & 3) ^ swz(row);
-        dma16(wrs, lds_addr(&lds_b[b][ins * 16 * ROWB]), base + row * ROWB + piece * 16);
-      }
+      const int row = ins * 16 + (lane >> 2);
+      const int piece = (lane & 3) ^ swz(row);
+      dma16(wrs, lds_addr(&lds_b[b][ins * 16 * ROWB]), base + row * ROWB + piece * 16);
     }
   };
   struct Geo {
@@ -452,15 +467,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
       dma16(rs, lds_addr(&lds_a[b][ins * 16 * ROWB]), voff);
     }
   };
-  constexpr int WAIT_ALL = 0;
-  constexpr int WAIT_KEEP_A = (0xF << 8) | (7 << 4) | APW;   // vmcnt <= APW, no wait on lgkm/exp
 
-  int ka = 0, kb = 0;
+  int ka = 0, kb = 0, gsa = 1 << 20;   // halo buffer, weight-slot counter, groups since a halo request
   int tile = lb;
   if (tile < a.n_tiles) {
-    stage_b(0, 0);
+    const int ngrp0 = NG * nch;
+#pragma unroll 1
+    for (int j = 0; j < NBUF - 1; ++j) stage_b(j % ngrp0, j);
     stage_a(geo_of(ldc(a.tiles + tile)), 0, 0);
-    __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+    __builtin_amdgcn_s_waitcnt(0);
     dma_barrier();
   }
   for (; tile < a.n_tiles; tile += Gd) {
@@ -486,16 +501,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
 #pragma unroll 1
     for (int k = 0; k < ngrp; ++k) {
       const int c = k / NG, grp = k - NG * c;
-      bool a_issued = false;
-      if (k + 1 < ngrp) {
-        stage_b(k + 1, (kb + 1) & 1);
-        if (grp == 0 && c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); a_issued = true; }
-      } else if (next_tile < a.n_tiles) {
-        stage_b(0, (kb + 1) & 1);
-        stage_a(geo_of(ldc(a.tiles + next_tile)), 0, (ka + 1) & 1);
+      // weights NBUF - 1 groups ahead (wrapping into the next tile's groups), then the next halo
+      stage_b((k + NBUF - 1) % ngrp, (kb + NBUF - 1) % NBUF);
+      ++gsa;
+      if (grp == 0) {
+        if (c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); gsa = 0; }
+        else if (next_tile < a.n_tiles) { stage_a(geo_of(ldc(a.tiles + next_tile)), 0, (ka + 1) & 1); gsa = 0; }
       }
       const unsigned char *la = &lds_a[ka & 1][0];
-      const unsigned char *lbr = &lds_b[kb & 1][0];
+      const unsigned char *lbr = &lds_b[kb % NBUF][0];
       // the G taps x 8 n-blocks of the group as one software pipeline: weight
       // fragments two steps ahead, the next tap's activation fragments half a tap ahead
       auto load_a = [&](int tg, v16 *af) {
@@ -531,14 +545,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
         b1 = b2;
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (a_issued) __builtin_amdgcn_s_waitcnt(WAIT_KEEP_A);
-      else __builtin_amdgcn_s_waitcnt(WAIT_ALL);
+      if (gsa <= NBUF - 2) __builtin_amdgcn_s_waitcnt(WAIT_BA);
+      else __builtin_amdgcn_s_waitcnt(WAIT_B);
       dma_barrier();
       kb += 1;
       if (grp == NG - 1) ka += 1;
     }
     conv_epilogue<T, MB, EPI>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
   }
+  __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS outlives the workgroup
   conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
 }
 
@@ -555,6 +570,7 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {8, 2, 2},            // 512-row tiles of 8 waves (4 m-blocks each), 2 waves/SIMD, operands through LDS
     {4, 2, 3},            // ring kernel: 256-row tiles of 4 waves, 1-tap weight slots, 2 workgroups/CU
     {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, 3-tap slots, 1 workgroup/CU
+    {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, six 1-tap slots (weights 5 taps ahead)
 };
 
 template <typename T>
@@ -591,21 +607,22 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_LDS_CASE(4, NRX_LDS_MB, 4)
   NRX_LDS_CASE(5, 4, 8)
 #undef NRX_LDS_CASE
-#define NRX_RING_CASE(V, M, NWV, GV, OCCV)                                                              \
+#define NRX_RING_CASE(V, M, NWV, GV, OCCV, NBV)                                                              \
   if (variant == V) {                                                                                   \
     dim3 b2(64 * NWV);                                                                                  \
     if (epi == EPI_STORE)                                                                               \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_LN_RELU)                                                                        \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_RESID)                                                                          \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
     else                                                                                                \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
     return;                                                                                             \
   }
-  NRX_RING_CASE(6, 4, 4, 1, 2)
-  NRX_RING_CASE(7, 4, 8, 3, 1)
+  NRX_RING_CASE(6, 4, 4, 1, 2, 2)
+  NRX_RING_CASE(7, 4, 8, 3, 1, 2)
+  NRX_RING_CASE(8, 4, 8, 1, 1, 6)
 #undef NRX_RING_CASE
 }
 

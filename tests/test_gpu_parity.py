@@ -132,20 +132,20 @@ C1 = [dict(n_prb=4, n_ant=4, n_ue=1, bits=[2], slot_number=i) for i in range(16)
 def test_nrx_forward_single_ue(prec, tol, d):
     # the single-UE workload at its own width (32) and at 128; the StateInit input has 32 channels,
     # one bf16 K chunk (odd count) for the LDS-operand variants
-    _nrx_case(C1, cgnn.NetConfig(4, d, 2, 0, 2), prec, 0, tol, 2, variants=(0, 5, 6, 7))
+    _nrx_case(C1, cgnn.NetConfig(4, d, 2, 0, 2), prec, 0, tol, 2, variants=(0, 5, 6, 7, 8))
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_reduced_width_multi_ue(prec, tol):
     # d = 64 with message passing: [h, agg] inputs map to two 128-wide segments of 64 live channels
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 64, 3, 2, 6), prec, 4, tol, 6, variants=(1, 5, 7))
+    _nrx_case(shapes, cgnn.NetConfig(8, 64, 3, 2, 6), prec, 4, tol, 6, variants=(1, 5, 7, 8))
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(8)))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(9)))
 
 
 def test_bce_and_adam_match_oracle():
@@ -241,7 +241,7 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1):
         L.nrx_model_destroy(model)
 
 
-@pytest.mark.parametrize("variant", [1, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [1, 4, 5, 6, 7, 8])
 def test_nrx_backward_fp32_matches_oracle(variant):
     _grad_case(0, 1e-4, 0.9999999, variant=variant)
 
