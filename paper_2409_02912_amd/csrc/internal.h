@@ -42,7 +42,7 @@ struct ConvVariant {
   int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS (K loop unrolled
               // over two chunks: even chunk counts only); 3: the same, rolled (ring kernel)
 };
-#define NRX_CONV_VARIANTS 9
+#define NRX_CONV_VARIANTS 11
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
 #define NRX_CONV8_VARIANTS 3
 extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64

@@ -384,7 +384,9 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
 // if a halo was requested since) were issued after them, so s_waitcnt vmcnt of that
 // count suffices.  A halo requested at a chunk's first group is covered by the
 // wait at the chunk's last group (NG - 1 > NBUF - 2 groups later).
-template <typename T, int EPI, int MB, int NW, int G, int OCC, int NBUF>
+// SCHED: 0 scheduling barriers between pipeline steps, 1 none (compiler interleaves),
+// 2 scheduling barriers and raised wave priority around the MFMA steps
+template <typename T, int EPI, int MB, int NW, int G, int OCC, int NBUF, int SCHED>
 __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> a) {
   constexpr int TILE = 16 * MB * NW;
   constexpr int HMAX = halo_rows_max(TILE);
@@ -530,6 +532,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
       v16 afc[MB], afn[MB];
       load_a(0, afc);
       v16 b0 = load_bf(0), b1 = load_bf(1);
+      if constexpr (SCHED == 2) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int i = 0; i < 8 * G; ++i) {
         const int nb = i & 7;
@@ -543,8 +546,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> 
         }
         b0 = b1;
         b1 = b2;
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (SCHED != 1) __builtin_amdgcn_sched_barrier(0);
       }
+      if constexpr (SCHED == 2) __builtin_amdgcn_s_setprio(0);
       if (gsa <= NBUF - 2) __builtin_amdgcn_s_waitcnt(WAIT_BA);
       else __builtin_amdgcn_s_waitcnt(WAIT_B);
       dma_barrier();
@@ -571,6 +575,8 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {4, 2, 3},            // ring kernel: 256-row tiles of 4 waves, 1-tap weight slots, 2 workgroups/CU
     {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, 3-tap slots, 1 workgroup/CU
     {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, six 1-tap slots (weights 5 taps ahead)
+    {8, 1, 3},            // as 7, scheduling left to the compiler
+    {8, 1, 3},            // as 7, raised wave priority over the MFMA steps
 };
 
 template <typename T>
@@ -607,22 +613,24 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_LDS_CASE(4, NRX_LDS_MB, 4)
   NRX_LDS_CASE(5, 4, 8)
 #undef NRX_LDS_CASE
-#define NRX_RING_CASE(V, M, NWV, GV, OCCV, NBV)                                                              \
+#define NRX_RING_CASE(V, M, NWV, GV, OCCV, NBV, SCH)                                                              \
   if (variant == V) {                                                                                   \
     dim3 b2(64 * NWV);                                                                                  \
     if (epi == EPI_STORE)                                                                               \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_LN_RELU)                                                                        \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_RESID)                                                                          \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     else                                                                                                \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     return;                                                                                             \
   }
-  NRX_RING_CASE(6, 4, 4, 1, 2, 2)
-  NRX_RING_CASE(7, 4, 8, 3, 1, 2)
-  NRX_RING_CASE(8, 4, 8, 1, 1, 6)
+  NRX_RING_CASE(6, 4, 4, 1, 2, 2, 0)
+  NRX_RING_CASE(7, 4, 8, 3, 1, 2, 0)
+  NRX_RING_CASE(8, 4, 8, 1, 1, 6, 0)
+  NRX_RING_CASE(9, 4, 8, 3, 1, 2, 1)
+  NRX_RING_CASE(10, 4, 8, 3, 1, 2, 2)
 #undef NRX_RING_CASE
 }
 

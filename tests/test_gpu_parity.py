@@ -145,7 +145,7 @@ def test_nrx_forward_reduced_width_multi_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(9)))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(11)))
 
 
 def test_bce_and_adam_match_oracle():
