@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void mp_kernel(MlpArgs<T> a) {
 // reads them again, so the tile needs no barrier between the two GEMMs.  The
 // cross-UE sum is taken in registers: a lane holds four consecutive rows of one
 // column, which for U = 1, 2, 4 are whole REs (tiles start on RE boundaries);
-// U = 3 goes through LDS.
+// U = 3 goes through LDS.  NW waves share a 128-row tile (8 waves: 16 rows each,
+// two waves per SIMD to cover LDS latency).
 namespace mp2 {
 constexpr int AROWB = NRX_D * 2;         // bytes per activation row (bf16)
 constexpr int TILEB = MLP_ROWS * AROWB;  // 32 KB
@@ -168,8 +169,10 @@ __device__ __forceinline__ int wpos(int c, int nb, int j, int lk) {
 }
 }  // namespace mp2
 
-__global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
   using namespace mp2;
+  constexpr int MBW = MLP_ROWS / 16 / NW;   // m-blocks per wave
   __shared__ __align__(16) unsigned char lw1[WB];
   __shared__ __align__(16) unsigned char lw2[WB];
   __shared__ __align__(16) unsigned char lt[2][TILEB];
@@ -183,8 +186,8 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
   {
     const i32x4_t r1 = rsrc_words(a.w1, WB), r2 = rsrc_words(a.w2, WB);
 #pragma unroll
-    for (int j = 0; j < WB / 1024 / 4; ++j) {
-      const int ins = wave + 4 * j;
+    for (int j = 0; j < WB / 1024 / NW; ++j) {
+      const int ins = wave + NW * j;
       const int row = ins * 16 + (lane >> 2);
       const uint32_t src = row * 64 + (((lane & 3) ^ swz(row)) << 4);
       dma16(r1, lds_addr(&lw1[ins * 1024]), src);
@@ -197,8 +200,8 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
     const SlotGeo g = ldc_geo(a.geo + tl.slot);
     const i32x4_t rs = rsrc_words(a.h + (g.row_base + tl.row0) * NRX_D, tl.nrows * AROWB);
 #pragma unroll
-    for (int j = 0; j < TILEB / 1024 / 4; ++j) {
-      const int ins = wave + 4 * j;
+    for (int j = 0; j < TILEB / 1024 / NW; ++j) {
+      const int ins = wave + NW * j;
       const int row = ins * 4 + (lane >> 4);
       const int piece = (lane & 15) ^ (row & 15);
       dma16(rs, lds_addr(&lt[b][ins * 1024]), (uint32_t)(row * AROWB + piece * 16));
@@ -214,30 +217,30 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
     const SlotGeo g = ldc_geo(a.geo + tl.slot);
     const int U = ldc(&a.geo[tl.slot].U);
     unsigned char *t = lt[b];
-    const int rbase = wave * 16 * MLP_MB;
-    f32x4_t acc[MLP_MB][8];
+    const int rbase = wave * 16 * MBW;
+    f32x4_t acc[MBW][8];
     auto gemm = [&](const unsigned char *w) {
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb)
+      for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        v16 af[MLP_MB];
+        v16 af[MBW];
 #pragma unroll
-        for (int mb = 0; mb < MLP_MB; ++mb) af[mb] = ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk));
+        for (int mb = 0; mb < MBW; ++mb) af[mb] = ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk));
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
           const v16 bf = ld16(w + wpos(c, nb, lr, lk));
 #pragma unroll
-          for (int mb = 0; mb < MLP_MB; ++mb) acc[mb][nb] = mfma_bf16(af[mb], bf, acc[mb][nb]);
+          for (int mb = 0; mb < MBW; ++mb) acc[mb][nb] = mfma_bf16(af[mb], bf, acc[mb][nb]);
         }
       }
     };
     gemm(lw1);
     // hidden = ReLU(acc + b1), bf16, over this wave's own rows (LDS operations of a wave stay in order)
 #pragma unroll
-    for (int mb = 0; mb < MLP_MB; ++mb)
+    for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = rbase + mb * 16 + 4 * lk + i;
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
     if (U != 3) {
       // lane rows 4 lk .. 4 lk + 3 of a 16-row block: whole REs for U = 1, 2, 4
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb) {
+      for (int mb = 0; mb < MBW; ++mb) {
         float m[4][8];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
       // U = 3: messages (bf16) over this wave's rows, then sums across lanes and waves
       dma_barrier();   // every wave has finished GEMM 2 on the tile
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb)
+      for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           float v[8];
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
         }
       __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS stores are done
       dma_barrier();
-      for (int e = tid; e < tl.nrows * 16; e += 256) {
+      for (int e = tid; e < tl.nrows * 16; e += 64 * NW) {
         const int r = e >> 4, p = e & 15, re0 = r - r % 3;
         float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int o = 0; o < 3; ++o) {
@@ -330,8 +333,10 @@ __global__ __launch_bounds__(256, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
 // 128x128 first layer and the 128x16 second layer (outputs j >= m_max zero) are
 // copied to LDS once, 128-row tiles are DMA'd one ahead, and the hidden layer is
 // written back over the wave's own rows.
-__global__ __launch_bounds__(256, 1) void readout_lds_kernel(MlpArgs<bf16_t> a) {
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t> a) {
   using namespace mp2;
+  constexpr int MBW = MLP_ROWS / 16 / NW;   // m-blocks per wave
   constexpr int W2B = 4 * 16 * 64;       // prepped [chunk][16][32] bf16
   __shared__ __align__(16) unsigned char lw1[WB];
   __shared__ __align__(16) unsigned char lw2[W2B];
@@ -345,21 +350,23 @@ __global__ __launch_bounds__(256, 1) void readout_lds_kernel(MlpArgs<bf16_t> a) 
   {
     const i32x4_t r1 = rsrc_words(a.w1, WB), r2 = rsrc_words(a.w2, W2B);
 #pragma unroll
-    for (int j = 0; j < WB / 1024 / 4; ++j) {
-      const int ins = wave + 4 * j;
+    for (int j = 0; j < WB / 1024 / NW; ++j) {
+      const int ins = wave + NW * j;
       const int row = ins * 16 + (lane >> 2);
       dma16(r1, lds_addr(&lw1[ins * 1024]), row * 64 + (((lane & 3) ^ swz(row)) << 4));
     }
-    const int row = wave * 16 + (lane >> 2);   // 64 rows of 64 bytes: one instruction per wave
-    dma16(r2, lds_addr(&lw2[wave * 1024]), row * 64 + (((lane & 3) ^ swz(row)) << 4));
+    if (wave < 4) {   // 64 rows of 64 bytes: one instruction per wave of the first four
+      const int row = wave * 16 + (lane >> 2);
+      dma16(r2, lds_addr(&lw2[wave * 1024]), row * 64 + (((lane & 3) ^ swz(row)) << 4));
+    }
   }
   auto stage = [&](int tile, int b) {
     const Tile tl = ldc(a.tiles + tile);
     const SlotGeo g = ldc_geo(a.geo + tl.slot);
     const i32x4_t rs = rsrc_words(a.h + (g.row_base + tl.row0) * NRX_D, tl.nrows * AROWB);
 #pragma unroll
-    for (int j = 0; j < TILEB / 1024 / 4; ++j) {
-      const int ins = wave + 4 * j;
+    for (int j = 0; j < TILEB / 1024 / NW; ++j) {
+      const int ins = wave + NW * j;
       const int row = ins * 4 + (lane >> 4);
       const int piece = (lane & 15) ^ (row & 15);
       dma16(rs, lds_addr(&lt[b][ins * 1024]), (uint32_t)(row * AROWB + piece * 16));
@@ -376,26 +383,26 @@ __global__ __launch_bounds__(256, 1) void readout_lds_kernel(MlpArgs<bf16_t> a) 
     const int U = ldc(&a.geo[tl.slot].U);
     const int64_t llr_off = ldc(&a.geo[tl.slot].llr_off);
     unsigned char *t = lt[b];
-    const int rbase = wave * 16 * MLP_MB;
-    f32x4_t acc[MLP_MB][8];
+    const int rbase = wave * 16 * MBW;
+    f32x4_t acc[MBW][8];
 #pragma unroll
-    for (int mb = 0; mb < MLP_MB; ++mb)
+    for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      v16 af[MLP_MB];
+      v16 af[MBW];
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb) af[mb] = ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk));
+      for (int mb = 0; mb < MBW; ++mb) af[mb] = ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk));
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
         const v16 bf = ld16(lw1 + wpos(c, nb, lr, lk));
 #pragma unroll
-        for (int mb = 0; mb < MLP_MB; ++mb) acc[mb][nb] = mfma_bf16(af[mb], bf, acc[mb][nb]);
+        for (int mb = 0; mb < MBW; ++mb) acc[mb][nb] = mfma_bf16(af[mb], bf, acc[mb][nb]);
       }
     }
 #pragma unroll
-    for (int mb = 0; mb < MLP_MB; ++mb)
+    for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float v[8];
@@ -410,21 +417,21 @@ __global__ __launch_bounds__(256, 1) void readout_lds_kernel(MlpArgs<bf16_t> a) 
         st16(t + apos(rbase + mb * 16 + 4 * lk + i, lr), q);
       }
     // second layer: one 16-column block
-    f32x4_t o[MLP_MB];
+    f32x4_t o[MBW];
 #pragma unroll
-    for (int mb = 0; mb < MLP_MB; ++mb) o[mb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < MBW; ++mb) o[mb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int row = c * 16 + lr;
       const v16 bf = ld16(lw2 + row * 64 + ((lk ^ swz(row)) << 4));
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb)
+      for (int mb = 0; mb < MBW; ++mb)
         o[mb] = mfma_bf16(ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk)), bf, o[mb]);
     }
     if (lr < M) {
       const int S = g.S;
 #pragma unroll
-      for (int mb = 0; mb < MLP_MB; ++mb)
+      for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = rbase + mb * 16 + 4 * lk + i;
@@ -551,7 +558,7 @@ void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st) {
   if constexpr (std::is_same<T, bf16_t>::value) {
     // inference: LDS-staged kernel (the training forward keeps the hidden activations: generic kernel)
     if (!a.save_m1) {
-      hipLaunchKernelGGL(mp_lds_kernel, dim3(grid), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(mp_lds_kernel<8>, dim3(grid), dim3(512), 0, st, a);
       return;
     }
   }
@@ -561,7 +568,7 @@ template <typename T>
 void launch_readout(const MlpArgs<T> &a, int grid, hipStream_t st) {
   if constexpr (std::is_same<T, bf16_t>::value) {
     if (!a.save_m1) {
-      hipLaunchKernelGGL(readout_lds_kernel, dim3(grid), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(readout_lds_kernel<8>, dim3(grid), dim3(512), 0, st, a);
       return;
     }
   }
