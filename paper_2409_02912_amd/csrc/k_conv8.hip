@@ -177,14 +177,15 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
         return i32x8_t{(int)y1.w[0], (int)y1.w[1], (int)y1.w[2], (int)y1.w[3],
                        (int)y2.w[0], (int)y2.w[1], (int)y2.w[2], (int)y2.w[3]};
       };
-      // weight fragments one n-block ahead of the MFMAs that use them
-      i32x8_t bcur = load_bf(0);
+      // weight fragments two n-blocks ahead of the MFMAs that use them
+      i32x8_t b0 = load_bf(0), b1 = load_bf(1);
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
-        const i32x8_t bnext = nb < 7 ? load_bf(nb + 1) : bcur;
+        const i32x8_t b2 = nb < 6 ? load_bf(nb + 2) : b1;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma_fp8(af[mb], bcur, acc[mb][nb]);
-        bcur = bnext;
+        for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma_fp8(af[mb], b0, acc[mb][nb]);
+        b0 = b1;
+        b1 = b2;
         __builtin_amdgcn_sched_barrier(0);
       }
       // the next weight pair must have landed; a halo load issued after it may stay in flight
