@@ -132,6 +132,46 @@ def stored_traffic(conv_b_variant):
     return d["hbm_bytes_per_launch"].get(str(conv_b_variant))
 
 
+def paper_rt_latency(reps=50):
+    """Batch-1 latency of the real-time-sized network of Sec. IV-B (d_S = 56, two CGNN iterations;
+    here 2 conv blocks with 2 message-passing rounds) on the setup the paper times there: one slot of
+    132 PRB, 2 UEs, 4 BS antennas, 16-QAM.  The paper's A100 TensorRT figure is context only."""
+    import torch
+    from paper_2409_02912_amd import libnrx as L
+    from paper_2409_02912_amd import synth
+    shapes = [dict(n_prb=132, n_ant=4, n_ue=2, bits=[4, 4], slot_number=0)]
+    descs, sz = L.make_slots(shapes, 4)
+    cfg = L.sim_config(n_taps=12, tap_decay_ns=487.42, snr_db_lo=10.0, snr_db_hi=10.0)
+    y = torch.empty(2 * sz["y"], dtype=torch.float32, device="cuda")
+    sws = torch.empty(L.slot_sim_workspace_bytes(cfg, descs), dtype=torch.uint8, device="cuda")
+    L.slot_sim(cfg, 0, 0, descs, 4, y, sws)
+    out = {"setup": "1 slot, 132 PRB x 14 sym, 2 UE, 4 ant, 16-QAM; CGNN d=56, 2 blocks, 2 MP rounds",
+           "paper_a100_tensorrt_ms": 0.97,
+           "paper_note": "Sec. IV-B: about 270 us + 350 us per CGNN iteration on an A100 (float16, TensorRT)"}
+    for prec, name in ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32")):
+        for flags, mode in ((0, "eager"), (1, "graph")):
+            model = L.nrx_model_create(4, 56, 2, 2, 4, prec, flags=flags)
+            try:
+                layout = [(n, sh) for n, _, sh in L.weight_layout(model)]
+                dw = torch.from_numpy(synth.he_weights(layout, 0)).cuda()
+                llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+                ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
+                L.nrx_autotune(model, dw, descs, y, llr, ws)
+                for _ in range(5):
+                    L.nrx_forward(model, dw, descs, y, llr, ws)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    L.nrx_forward(model, dw, descs, y, llr, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                out[f"{name}_{mode}_ms"] = e0.elapsed_time(e1) / reps
+            finally:
+                L.nrx_model_destroy(model)
+    return out
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -381,6 +421,8 @@ def main():
     if args.ragged_steps > 0:
         out["ragged"] = ragged_batch(args.ragged_steps, args.no_autotune, args.tune_cache)
     progress("uneven batch done")
+    if not args.bf16_only:
+        out["paper_rt_batch1"] = paper_rt_latency()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)
