@@ -458,3 +458,82 @@ def test_nrx_forward_fp8(variant):
         assert agree_n >= FP8_AGREE * agree_d
     finally:
         L.nrx_model_destroy(model)
+
+
+def test_full_size_sampled_parity():
+    """The benchmark workload at full size and in the benchmark's launch configuration (32 slots x
+    273 PRB x 14 symbols, 4 UEs, 8 antennas, 16-QAM; d = 128, 6 blocks, 2 rounds; autotuned conv
+    variants; trained weights): LLRs at sampled subcarriers (both band edges and inside the band)
+    against the oracle run on a window of +-16 subcarriers around each.  The 13 stacked 3x3
+    convolutions see 13 subcarriers either way, message passing and the readout act per RE, and the
+    window starts on an even subcarrier (the PE comb parity), so the window reproduces the full grid
+    at its centre."""
+    import os
+    w = synth.WORKLOADS["m"]
+    shapes = synth.uniform_shapes(w)
+    m_max, S = w["m"], 12 * w["n_prb"]
+    net = cgnn.NetConfig(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max)
+    path = os.path.join(os.path.dirname(L.__file__), "weights", "nrx_c5.npy")
+    wts = np.load(path) if os.path.exists(path) else synth.he_weights(cgnn.layout(net), 0)
+    W = cgnn.unflatten(wts.astype(np.float64), net)
+    log("full-size parity: oracle slots")
+    ref = oracle_batch(shapes, sim_cfg_oracle(w), 0, 0, m_max)
+    samples = [(0, 0), (0, 1638), (17, S - 1), (31, 911)]
+    expected = {}
+    for slot, s0 in samples:
+        lo, hi = max(0, s0 - 16) & ~1, min(S, s0 + 17)
+        r = ref[slot]
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        expected[(slot, s0)] = cgnn.forward(W, net, r["y32"][lo:hi], h[lo:hi], r["desc"].bits_per_sym)[:, :, s0 - lo, :]
+    descs, sz = L.make_slots(shapes, m_max)
+    y = _upload_batch(shapes, ref)
+    wd = dev(wts)
+    for prec, tol in ((L.NRX_FP32, 1e-4), (L.NRX_BF16, 2e-2)):
+        model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+        try:
+            llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+            ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+            L.nrx_autotune(model, wd, descs, y, llr, ws)
+            llr.fill_(float("nan"))
+            L.nrx_forward(model, wd, descs, y, llr, ws)
+            torch.cuda.synchronize()
+            got = split_llr(llr.cpu().numpy(), shapes, m_max)
+            worst = 0.0
+            for (slot, s0), e in expected.items():
+                g = got[slot][:, :, s0, :]
+                err = rel_err(g, e)
+                worst = max(worst, err)
+                big = np.abs(e) > 0.5
+                assert np.all((g[big] > 0) == (e[big] > 0)), f"slot {slot} subcarrier {s0}: hard decisions differ"
+                assert err <= tol, f"slot {slot} subcarrier {s0}: relative error {err:.3e} > {tol}"
+            log(f"  prec {prec}: worst relative error {worst:.2e} over {len(expected)} sampled subcarriers")
+        finally:
+            L.nrx_model_destroy(model)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_forward_mu_mimo_16_antennas(prec, tol):
+    # the MU-MIMO workload's network and channel (16 antennas, 4 UEs, 64-QAM, 24-tap spatially
+    # correlated Rayleigh; d = 128, 8 blocks, 3 message-passing rounds) on a few 6-PRB slots
+    w = synth.WORKLOADS["c3"]
+    shapes = [dict(n_prb=6, n_ant=16, n_ue=4, bits=[6] * 4, slot_number=s) for s in range(3)]
+    net, m_max = cgnn.NetConfig(16, 128, 8, 3, 6), 6
+    log(f"nrx_forward 16 antennas: prec={prec}")
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(w), 9, 0, m_max)
+    wts = synth.he_weights(cgnn.layout(net), 9, perturb=True)
+    exp = oracle_nrx(wts, net, ref_slots)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+    try:
+        descs, sz = L.make_slots(shapes, m_max)
+        y = _upload_batch(shapes, ref_slots)
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        for v in (1, 5, 7):
+            L.set_all_conv_variants(model, v)
+            L.nrx_forward(model, dev(wts), descs, y, llr, ws)
+            torch.cuda.synchronize()
+            got = split_llr(llr.cpu().numpy(), shapes, m_max)
+            for i in range(len(shapes)):
+                check_llr(got[i], exp[i], tol)
+    finally:
+        L.nrx_model_destroy(model)

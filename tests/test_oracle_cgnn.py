@@ -199,3 +199,24 @@ def test_bce_and_adam():
     g = np.array([3.0, -0.01, 1e-3, -40.0])
     w1, m, v = cgnn.adam_step(w, g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
     assert np.allclose(w1, -1e-3 * np.sign(g), rtol=1e-4)
+
+
+def test_window_reproduces_full_grid():
+    """The 1 + 2C stacked 3x3 convolutions see C' = 1 + 2C subcarriers either way; with message
+    passing and the readout acting per RE, a window of +-16 subcarriers starting on an even
+    subcarrier (the PE comb parity) gives the full-grid LLRs at its centre, bit for bit.  The GPU
+    test at the benchmark's full size relies on this."""
+    from oracle import receiver, slot_sim
+    from paper_2409_02912_amd import synth
+    net = cgnn.NetConfig(8, 32, 6, 2, 4)
+    W = cgnn.unflatten(synth.he_weights(cgnn.layout(net), 3, perturb=True).astype(np.float64), net)
+    cfg = slot_sim.SimConfig(n_taps=12, tap_decay_ns=487.42, snr_db_lo=10, snr_db_hi=10)
+    d = slot_sim.SlotDesc(6, 8, 4, [4] * 4, slot_number=3)
+    r = slot_sim.simulate_slot(0, 0, 0, cfg, d, 4)
+    y, S = r["y"], 72
+    h = receiver.ls_estimate(y, d)
+    full = cgnn.forward(W, net, y, h, d.bits_per_sym)
+    for s0 in (0, 35, 71, 20):
+        lo, hi = max(0, s0 - 16) & ~1, min(S, s0 + 17)
+        win = cgnn.forward(W, net, y[lo:hi], h[lo:hi], d.bits_per_sym)[:, :, s0 - lo, :]
+        assert np.array_equal(win, full[:, :, s0, :])
