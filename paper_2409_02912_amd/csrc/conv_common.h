@@ -141,31 +141,65 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
     }
     return;
   }
-  float bias[8];
+  float bias[8], lng[8], lnb[8];
 #pragma unroll
   for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
+  if constexpr (EPI == EPI_LN_RELU) {
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) { lng[nb] = a.ln_g[ch0 + nb]; lnb[nb] = a.ln_b[ch0 + nb]; }
+  }
   float vmax = 0.f;   // max |output| of this lane (calibration of FP8 scales)
+  // residual rows of this lane, requested two m-blocks at a time before any of them is used
+  // (a memory round trip per two m-blocks instead of one per row); rows past the tile read
+  // row 0 and are not stored
+  constexpr int RB = MB < 2 ? MB : 2;
+  v16 rraw[EPI == EPI_RESID ? RB : 1][4];
+  auto fetch_resid = [&](int mb0) {
+    if constexpr (EPI == EPI_RESID && sizeof(T) == 2) {
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = wave * 16 * MB + (mb0 + q) * 16 + 4 * lk + i;
+          const int64_t grow = g.row_base + tl.row0 + (r < tl.nrows ? r : 0);
+          rraw[q][i] = ld16(a.resid + grow * NRX_D + ch0);
+        }
+    }
+  };
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
+    if (mb % RB == 0) fetch_resid(mb);
+    if (a.pe) {
+      // PE field of the m-block's four rows, all requested before the first is used
+      float pev[4][8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
+        const int R = tl.row0 + (r < tl.nrows ? r : 0);
+        const int s = R / rps;
+        const int rem = R - s * rps;
+        const int t = rem / U, u = rem - t * U;
+        const int par = (s - (u >> 1)) & 1;
+        const int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
+        const float4 *pf = reinterpret_cast<const float4 *>(a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0);
+        const float4 x0 = pf[0], x1 = pf[1];
+        pev[i][0] = x0.x; pev[i][1] = x0.y; pev[i][2] = x0.z; pev[i][3] = x0.w;
+        pev[i][4] = x1.x; pev[i][5] = x1.y; pev[i][6] = x1.z; pev[i][7] = x1.w;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int nb = 0; nb < 8; ++nb) acc[mb][nb][i] += pev[i][nb];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
       const bool valid = r < tl.nrows;
       const int R = tl.row0 + (valid ? r : 0);
-      const int s = R / rps;
-      const int rem = R - s * rps;
-      const int t = rem / U, u = rem - (rem / U) * U;
       const int64_t grow = g.row_base + R;
       float v[8];
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
-      if (a.pe) {
-        int par = (s - (u >> 1)) & 1;
-        int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
-        const float *pf = a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] += pf[nb];
-      }
       if constexpr (EPI == EPI_LN_RELU) {
         float sm = 0.f;
 #pragma unroll
@@ -186,12 +220,20 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
         }
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
-          float n = (v[nb] - mean) * rstd * a.ln_g[ch0 + nb] + a.ln_b[ch0 + nb];
+          float n = (v[nb] - mean) * rstd * lng[nb] + lnb[nb];
           v[nb] = n > 0.f ? n : 0.f;
         }
       } else if constexpr (EPI == EPI_RESID) {
         float rsd[8];
-        if (valid) pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
+        if constexpr (sizeof(T) == 2) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            rsd[2 * k] = __uint_as_float(rraw[mb % RB][i].w[k] << 16);
+            rsd[2 * k + 1] = __uint_as_float(rraw[mb % RB][i].w[k] & 0xFFFF0000u);
+          }
+        } else {
+          pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
+        }
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
       }
