@@ -192,6 +192,44 @@ def test_bce_and_adam_match_oracle():
     assert np.allclose(tv.cpu().numpy(), ev, rtol=1e-6, atol=1e-7)
 
 
+def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4):
+    """Weights whose ReLU units all lie far from their kink on this batch.
+
+    The gradient of a ReLU network jumps where a pre-activation crosses zero.  The fp32 path sums in another
+    order than the fp64 oracle, which moves pre-activations by about 1e-6 of their scale, so a unit that close
+    to zero can take the other branch; one such unit moves the whole gradient by about 1e-3.  Here the bias in
+    front of every ReLU (LayerNorm beta, the first bias of the message and readout MLPs) is set per channel so
+    that the channel's pre-activations over the batch sit at +-`sigmas` standard deviations (signs alternate
+    over channels, so both branches are taken), iterated because each layer's inputs depend on the earlier
+    biases.  Returns the weights and the smallest |pre-activation| relative to its layer's RMS."""
+    w = w.astype(np.float64).copy()
+    offs, off = {}, 0
+    for name, shape in cgnn.layout(net):
+        offs[name] = off
+        off += int(np.prod(shape))
+    sign = np.where(np.arange(net.d) % 2 == 0, 1.0, -1.0)
+    units = [(f"blk{i}", f"blk{i}.ln.b", 1) for i in range(net.C)] + \
+            [(f"mp{r}", f"mp{r}.b1", 1) for r in range(net.R)] + [("readout", "readout.b1", 1)]
+    margin = 0.0
+    for it in range(iters + 1):
+        W = cgnn.unflatten(w, net)
+        pre = {k: [] for k, _, _ in units}
+        for r in ref_slots:
+            h = receiver.ls_estimate(r["y32"], r["desc"])
+            _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True)
+            for k, _, j in units:
+                pre[k].append(cache[k][j].reshape(-1, net.d))
+        margin = np.inf
+        for k, bname, _ in units:
+            x = np.concatenate(pre[k])
+            b = w[offs[bname]:offs[bname] + net.d]
+            x0 = x - b                                   # the pre-activation without its bias
+            margin = min(margin, float(np.min(np.abs(x)) / np.sqrt(np.mean(x0 * x0))))
+            if it < iters:
+                w[offs[bname]:offs[bname] + net.d] = -x0.mean(axis=0) + sign * sigmas * x0.std(axis=0)
+    return w.astype(np.float32), margin
+
+
 def _grad_case(prec, tol, cos_min, seed=21, variant=1):
     shapes = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
               dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 2], slot_number=2)]
@@ -199,7 +237,9 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1):
     net = cgnn.NetConfig(4, 128, 3, 1, m_max)
     log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R} conv variant {variant}")
     ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
-    w = synth.he_weights(cgnn.layout(net), seed, perturb=True)
+    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), seed, perturb=True), net, ref_slots)
+    log(f"  smallest |ReLU input| / layer RMS {margin:.2e}")
+    assert margin > 5e-4
     W = cgnn.unflatten(w.astype(np.float64), net)
     rng = np.random.default_rng(seed)
     descs, sz = L.make_slots(shapes, m_max)
