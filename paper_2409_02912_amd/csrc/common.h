@@ -102,12 +102,20 @@ __device__ __forceinline__ uint2 fp8x8(const float *x, float inv) {
 
 __device__ __forceinline__ float shfl_xor16(float v, int m) { return __shfl_xor(v, m, 64); }
 
-// sum over the 16 lanes that share l/16 (the lanes owning one row's channels)
+// v plus the value of the lane that the DPP control CTRL selects within each row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes that share l/16 (the lanes owning one row's channels), all
+// lanes receiving it: a butterfly over the 16-lane DPP row (swap neighbours, swap
+// pairs, mirror each half, mirror the row) in four VALU adds, no LDS traffic.
 __device__ __forceinline__ float row_sum16(float v) {
-  v += shfl_xor16(v, 1);
-  v += shfl_xor16(v, 2);
-  v += shfl_xor16(v, 4);
-  v += shfl_xor16(v, 8);
+  v = dpp_add<0xB1>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);   // row_half_mirror
+  v = dpp_add<0x140>(v);   // row_mirror
   return v;
 }
 
