@@ -15,12 +15,13 @@ typedef __attribute__((__vector_size__(8 * sizeof(int)))) int i32x8_t;
 
 typedef uint16_t bf16_t;  // storage type of bfloat16 activations and weights
 
-// float -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ bf16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
+// float -> bfloat16, round to nearest even (the hardware conversion of gfx950)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
 }
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // Scalar element traits for the two activation storage types.
@@ -133,7 +134,7 @@ template <> struct pack8<bf16_t> {
   __device__ static __forceinline__ void store(bf16_t *p, const float *x) {
     v16 v;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v.w[i] = (uint32_t)f2bf(x[2 * i]) | ((uint32_t)f2bf(x[2 * i + 1]) << 16);
+    for (int i = 0; i < 4; ++i) v.w[i] = pack_bf2(x[2 * i], x[2 * i + 1]);
     st16(p, v);
   }
 };

@@ -204,16 +204,17 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
         float sm = 0.f;
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) sm += v[nb];
-        // channels at or beyond the state depth carry exact zeros (zero weights and bias)
+        // channels at or beyond the state depth carry exact zeros (zero weights and bias):
+        // each adds mean^2 to the sum of squared deviations, removed in one step
         const float mean = row_sum16(sm) * a.ln_inv;
         float sq = 0.f;
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
           const float dv = v[nb] - mean;
-          sq += ch0 + nb < a.ln_d ? dv * dv : 0.f;
+          sq += dv * dv;
         }
-        const float var = row_sum16(sq) * a.ln_inv;
-        const float rstd = 1.0f / sqrtf(var + 1e-5f);
+        const float var = fmaxf(row_sum16(sq) - a.ln_pad * mean * mean, 0.f) * a.ln_inv;
+        const float rstd = rsqrtf(var + 1e-5f);
         if (valid && a.save_z) {
           pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
           if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
@@ -235,7 +236,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
           pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
         }
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] += valid ? rsd[nb] : 0.f;
+        for (int nb = 0; nb < 8; ++nb) v[nb] += rsd[nb];   // rows past the tile are not stored
       }
       if (valid) {
         if (a.out) pack8<T>::store(a.out + grow * NRX_D + ch0, v);

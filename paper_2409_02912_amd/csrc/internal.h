@@ -17,7 +17,7 @@ struct ConvArgs {
   const float *pe;          // positional-encoding field [2][3][14][128] or null
   const float *ln_g, *ln_b; // [128] (EPI_LN_RELU; zero beyond the state depth d)
   float ln_inv;             // 1 / d: LayerNorm statistics over the first d channels (the rest are zero)
-  int ln_d;
+  float ln_pad;             // 128 - d, the number of zero channels
   const T *resid;           // [rows][128] (EPI_RESID)
   T *out;                   // [rows][128]
   T *save_z;                // pre-LN output (EPI_LN_RELU, training; input of EPI_LN_BWD) or null

@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
         }
         v16 q;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q.w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+        for (int k = 0; k < 4; ++k) q.w[k] = pack_bf2(v[2 * k], v[2 * k + 1]);
         st16(t + apos(r, lr), q);
       }
     gemm(lw2);
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
           for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias2[nb];
           v16 q;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) q.w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+          for (int k = 0; k < 4; ++k) q.w[k] = pack_bf2(v[2 * k], v[2 * k + 1]);
           st16(t + apos(rbase + mb * 16 + 4 * lk + i, lr), q);
         }
       __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): this wave's LDS stores are done
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
         }
         v16 q;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) q.w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+        for (int k = 0; k < 4; ++k) q.w[k] = pack_bf2(v[2 * k], v[2 * k + 1]);
         st16(t + apos(rbase + mb * 16 + 4 * lk + i, lr), q);
       }
     // second layer: one 16-column block

@@ -704,7 +704,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   ConvArgs<T> a{};
   a.geo = D.geo;
   a.ln_inv = 1.0f / (float)m->cfg.d;
-  a.ln_d = m->cfg.d;
+  a.ln_pad = (float)(NRX_D - m->cfg.d);
   // StateInit
   a.src0 = X; a.c0 = m->cx; a.src1 = nullptr; a.c1 = 0;
   a.w = wprep + m->conv_in.prep;
