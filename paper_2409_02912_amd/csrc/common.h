@@ -120,6 +120,19 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
+// row_sum16 of N independent values, each butterfly step applied to all of them in turn
+template <int N>
+__device__ __forceinline__ void row_sum16_n(float (&v)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = dpp_add<0xB1>(v[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = dpp_add<0x4E>(v[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = dpp_add<0x141>(v[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = dpp_add<0x140>(v[k]);
+}
+
 // 8 consecutive channels <-> 16/32 bytes
 template <typename T> struct pack8;
 template <> struct pack8<bf16_t> {

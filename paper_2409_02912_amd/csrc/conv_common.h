@@ -98,7 +98,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void *base,
 
 // Epilogue of one tile: bias (+ PE field) -> store | LayerNorm + ReLU | residual
 // add | LayerNorm backward.  Lane owns channels 8*lr .. +7 of rows 4*lk + i.
-template <typename T, int MB, int EPI>
+template <typename T, int MB, int EPI, int LB = (MB % 2 == 0 ? 2 : 1)>
 __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &tl, const SlotGeo &g,
                                               f32x4_t (&acc)[MB][8], int wave, int lr, int lk, float *lnp) {
   const int U = g.U, S = g.S, rps = 14 * U;
@@ -141,102 +141,162 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
     }
     return;
   }
-  float bias[8], lng[8], lnb[8];
+  constexpr bool LN = EPI == EPI_LN_RELU || EPI == EPI_LN_RELU_SAVE;
+  float bias[8];
 #pragma unroll
   for (int nb = 0; nb < 8; ++nb) bias[nb] = a.bias[ch0 + nb];
-  if constexpr (EPI == EPI_LN_RELU) {
+
+  // PE field: its row is fixed by (subcarrier class, symbol), found with float
+  // reciprocals (quotients below 2^12 with at least 0.5/rps to the next integer, far
+  // above the rounding error); rows past the tile use row 0.  Loads go out two
+  // m-blocks at a time before any is used.
+  if (EPI != EPI_RESID && a.pe) {   // (the residual convolutions carry no PE field)
+    const float inv_rps = 1.0f / (float)rps, inv_u = 1.0f / (float)U;
+    constexpr int PB = 1;
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb) { lng[nb] = a.ln_g[ch0 + nb]; lnb[nb] = a.ln_b[ch0 + nb]; }
-  }
-  float vmax = 0.f;   // max |output| of this lane (calibration of FP8 scales)
-  // residual rows of this lane, requested two m-blocks at a time before any of them is used
-  // (a memory round trip per two m-blocks instead of one per row); rows past the tile read
-  // row 0 and are not stored
-  constexpr int RB = MB < 2 ? MB : 2;
-  v16 rraw[EPI == EPI_RESID ? RB : 1][4];
-  auto fetch_resid = [&](int mb0) {
-    if constexpr (EPI == EPI_RESID && sizeof(T) == 2) {
+    for (int mb0 = 0; mb0 < MB; mb0 += PB) {
+      float pev[PB][4][8];
 #pragma unroll
-      for (int q = 0; q < RB; ++q)
+      for (int q = 0; q < PB; ++q)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = wave * 16 * MB + (mb0 + q) * 16 + 4 * lk + i;
-          const int64_t grow = g.row_base + tl.row0 + (r < tl.nrows ? r : 0);
-          rraw[q][i] = ld16(a.resid + grow * NRX_D + ch0);
+          const int R = tl.row0 + (r < tl.nrows ? r : 0);
+          const int s = (int)(((float)R + 0.5f) * inv_rps);
+          const int rem = R - s * rps;
+          const int t = (int)(((float)rem + 0.5f) * inv_u);
+          const int u = rem - t * U;
+          const int par = (s - (u >> 1)) & 1;
+          const int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
+          const float4 *pf = reinterpret_cast<const float4 *>(a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0);
+          const float4 x0 = pf[0], x1 = pf[1];
+          pev[q][i][0] = x0.x; pev[q][i][1] = x0.y; pev[q][i][2] = x0.z; pev[q][i][3] = x0.w;
+          pev[q][i][4] = x1.x; pev[q][i][5] = x1.y; pev[q][i][6] = x1.z; pev[q][i][7] = x1.w;
         }
+#pragma unroll
+      for (int q = 0; q < PB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) acc[mb0 + q][nb][i] += pev[q][i][nb];
     }
-  };
+  }
+
+  if constexpr (LN) {
+    float lng[8], lnb[8];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    if (mb % RB == 0) fetch_resid(mb);
-    if (a.pe) {
-      // PE field of the m-block's four rows, all requested before the first is used
-      float pev[4][8];
+    for (int nb = 0; nb < 8; ++nb) { lng[nb] = a.ln_g[ch0 + nb]; lnb[nb] = a.ln_b[ch0 + nb]; }
+    // statistics of LB m-blocks (4 LB rows) together: every butterfly step of the row
+    // sums runs over all of them before the next, so the steps do not wait on each other
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
-        const int R = tl.row0 + (r < tl.nrows ? r : 0);
-        const int s = R / rps;
-        const int rem = R - s * rps;
-        const int t = rem / U, u = rem - t * U;
-        const int par = (s - (u >> 1)) & 1;
-        const int edge = s == 0 ? 1 : (s == S - 1 ? 2 : 0);
-        const float4 *pf = reinterpret_cast<const float4 *>(a.pe + ((size_t)((par * 3 + edge) * 14 + t)) * NRX_D + ch0);
-        const float4 x0 = pf[0], x1 = pf[1];
-        pev[i][0] = x0.x; pev[i][1] = x0.y; pev[i][2] = x0.z; pev[i][3] = x0.w;
-        pev[i][4] = x1.x; pev[i][5] = x1.y; pev[i][6] = x1.z; pev[i][7] = x1.w;
+    for (int mb0 = 0; mb0 < MB; mb0 += LB) {
+      float mean[LB * 4], rstd[LB * 4];
+#pragma unroll
+      for (int q = 0; q < LB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float sm = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            acc[mb0 + q][nb][i] += bias[nb];
+            sm += acc[mb0 + q][nb][i];
+          }
+          mean[4 * q + i] = sm;
+        }
+      row_sum16_n<LB * 4>(mean);
+#pragma unroll
+      for (int k = 0; k < LB * 4; ++k) mean[k] *= a.ln_inv;
+      // channels at or beyond the state depth carry exact zeros (zero weights and bias):
+      // each adds mean^2 to the sum of squared deviations, removed in one step
+#pragma unroll
+      for (int q = 0; q < LB; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float sq = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            const float dv = acc[mb0 + q][nb][i] - mean[4 * q + i];
+            sq += dv * dv;
+          }
+          rstd[4 * q + i] = sq;
+        }
+      row_sum16_n<LB * 4>(rstd);
+#pragma unroll
+      for (int k = 0; k < LB * 4; ++k) {
+        const float var = fmaxf(rstd[k] - a.ln_pad * mean[k] * mean[k], 0.f) * a.ln_inv;
+        rstd[k] = rsqrtf(var + 1e-5f);
+      }
+      if constexpr (EPI == EPI_LN_RELU_SAVE) {
+#pragma unroll
+        for (int q = 0; q < LB; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = wave * 16 * MB + (mb0 + q) * 16 + 4 * lk + i;
+            if (r < tl.nrows) {
+              const int64_t grow = g.row_base + tl.row0 + r;
+              float z[8];
+#pragma unroll
+              for (int nb = 0; nb < 8; ++nb) z[nb] = acc[mb0 + q][nb][i];
+              pack8<T>::store(a.save_z + grow * NRX_D + ch0, z);
+              if (lr == 0) { a.save_stats[2 * grow] = mean[4 * q + i]; a.save_stats[2 * grow + 1] = rstd[4 * q + i]; }
+            }
+          }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int q = 0; q < LB; ++q)
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) acc[mb][nb][i] += pev[i][nb];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            const float n = (acc[mb0 + q][nb][i] - mean[4 * q + i]) * (rstd[4 * q + i] * lng[nb]) + lnb[nb];
+            acc[mb0 + q][nb][i] = n > 0.f ? n : 0.f;
+          }
+    }
+  }
+
+  float vmax = 0.f;   // max |output| of this lane (calibration of FP8 scales)
+  // residual rows of the lane (EPI_RESID), requested RB m-blocks at a time before any of
+  // them is used; rows past the tile read row 0 and are not stored
+  constexpr int RB = MB % 2 == 0 ? 2 : 1;
+  v16 rraw[EPI == EPI_RESID ? RB : 1][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    if constexpr (EPI == EPI_RESID && sizeof(T) == 2) {
+      if (mb % RB == 0) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = wave * 16 * MB + (mb + q) * 16 + 4 * lk + i;
+            const int64_t grow = g.row_base + tl.row0 + (r < tl.nrows ? r : 0);
+            rraw[q][i] = ld16(a.resid + grow * NRX_D + ch0);
+          }
+      }
+      // keeps the scheduler from hoisting the next batch above this m-block's stores
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      // every row is computed (straight-line code across rows); rows past the tile are not stored
       const int r = wave * 16 * MB + mb * 16 + 4 * lk + i;
       const bool valid = r < tl.nrows;
-      const int R = tl.row0 + (valid ? r : 0);
-      const int64_t grow = g.row_base + R;
+      const int64_t grow = g.row_base + tl.row0 + (valid ? r : 0);
       float v[8];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) v[nb] = acc[mb][nb][i] + bias[nb];
-      if constexpr (EPI == EPI_LN_RELU) {
-        float sm = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) sm += v[nb];
-        // channels at or beyond the state depth carry exact zeros (zero weights and bias):
-        // each adds mean^2 to the sum of squared deviations, removed in one step
-        const float mean = row_sum16(sm) * a.ln_inv;
-        float sq = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          const float dv = v[nb] - mean;
-          sq += dv * dv;
-        }
-        const float var = fmaxf(row_sum16(sq) - a.ln_pad * mean * mean, 0.f) * a.ln_inv;
-        const float rstd = rsqrtf(var + 1e-5f);
-        if (valid && a.save_z) {
-          pack8<T>::store(a.save_z + grow * NRX_D + ch0, v);
-          if (lr == 0) { a.save_stats[2 * grow] = mean; a.save_stats[2 * grow + 1] = rstd; }
-        }
-#pragma unroll
-        for (int nb = 0; nb < 8; ++nb) {
-          float n = (v[nb] - mean) * rstd * lng[nb] + lnb[nb];
-          v[nb] = n > 0.f ? n : 0.f;
-        }
-      } else if constexpr (EPI == EPI_RESID) {
-        float rsd[8];
+      for (int nb = 0; nb < 8; ++nb) v[nb] = LN ? acc[mb][nb][i] : acc[mb][nb][i] + bias[nb];
+      if constexpr (EPI == EPI_RESID) {
         if constexpr (sizeof(T) == 2) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            rsd[2 * k] = __uint_as_float(rraw[mb % RB][i].w[k] << 16);
-            rsd[2 * k + 1] = __uint_as_float(rraw[mb % RB][i].w[k] & 0xFFFF0000u);
+            v[2 * k] += __uint_as_float(rraw[mb % RB][i].w[k] << 16);
+            v[2 * k + 1] += __uint_as_float(rraw[mb % RB][i].w[k] & 0xFFFF0000u);
           }
         } else {
+          float rsd[8];
           pack8<T>::load(a.resid + grow * NRX_D + ch0, rsd);
-        }
 #pragma unroll
-        for (int nb = 0; nb < 8; ++nb) v[nb] += rsd[nb];   // rows past the tile are not stored
+          for (int nb = 0; nb < 8; ++nb) v[nb] += rsd[nb];
+        }
       }
       if (valid) {
         if (a.out) pack8<T>::store(a.out + grow * NRX_D + ch0, v);

@@ -5,7 +5,7 @@
 
 #include "common.h"
 
-enum { EPI_STORE = 0, EPI_LN_RELU = 1, EPI_RESID = 2, EPI_LN_BWD = 3 };
+enum { EPI_STORE = 0, EPI_LN_RELU = 1, EPI_RESID = 2, EPI_LN_BWD = 3, EPI_LN_RELU_SAVE = 4 };  // 4: EPI_LN_RELU keeping z and its statistics (training)
 
 template <typename T>
 struct ConvArgs {

@@ -590,6 +590,8 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_RELU, OCCV, PF>), dim3(grid), blk, 0, st, a); \
     else if (epi == EPI_RESID)                                                                \
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_RESID, OCCV, PF>), dim3(grid), blk, 0, st, a); \
+    else if (epi == EPI_LN_RELU_SAVE)                                                         \
+      hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_RELU_SAVE, OCCV, PF>), dim3(grid), blk, 0, st, a); \
     else                                                                                      \
       hipLaunchKernelGGL((conv3x3_kernel<T, MBV, EPI_LN_BWD, OCCV, PF>), dim3(grid), blk, 0, st, a); \
     return;                                                                                   \
@@ -607,6 +609,8 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
       hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_RELU, M, NWV>), dim3(grid), b2, 0, st, a);    \
     else if (epi == EPI_RESID)                                                                       \
       hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_RESID, M, NWV>), dim3(grid), b2, 0, st, a);      \
+    else if (epi == EPI_LN_RELU_SAVE)                                                                \
+      hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_RELU_SAVE, M, NWV>), dim3(grid), b2, 0, st, a); \
     else hipLaunchKernelGGL((conv3x3_lds_kernel<T, EPI_LN_BWD, M, NWV>), dim3(grid), b2, 0, st, a);  \
     return;                                                                                          \
   }
@@ -622,6 +626,8 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
       hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_RESID)                                                                          \
       hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+    else if (epi == EPI_LN_RELU_SAVE)                                                                   \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU_SAVE, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     else                                                                                                \
       hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
     return;                                                                                             \

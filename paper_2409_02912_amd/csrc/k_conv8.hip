@@ -204,7 +204,7 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[mb][nb][i] *= sw;
     }
-    conv_epilogue<bf16_t, MB, EPI>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
+    conv_epilogue<bf16_t, MB, EPI, 1>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
   }
 }
 

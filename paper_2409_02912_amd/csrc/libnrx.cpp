@@ -761,7 +761,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ca.out8_inv = inv_scale(C + i);
     }
     if (amax) ca.amax = amax + C + i;
-    conv(ca, EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, f8);
+    conv(ca, save ? EPI_LN_RELU_SAVE : EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, f8);
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
