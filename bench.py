@@ -116,6 +116,18 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
         L.nrx_model_destroy(model)
 
 
+# kernel templates behind the conv variant indices of the library (kConvVariants), for reporting
+CONV_VARIANT_KERNELS = [
+    "conv3x3_kernel<MB 4, OCC 1, weights one tap ahead>", "conv3x3_kernel<MB 4, OCC 2>",
+    "conv3x3_kernel<MB 2, OCC 2, weights one tap ahead>", "conv3x3_kernel<MB 2, OCC 2>",
+    "conv3x3_lds_kernel<MB 6, NW 4>", "conv3x3_lds_kernel<MB 4, NW 8>",
+    "conv3x3_ring_kernel<MB 4, NW 4, G 1, OCC 2, NBUF 2>", "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 1, OCC 1, NBUF 6>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, compiler-scheduled>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, raised wave priority>",
+]
+
+
 def stored_traffic(conv_b_variant):
     """HBM bytes per conv_b launch from the committed FETCH_SIZE / WRITE_SIZE passes, or None when the
     kernel sources or the tile variant differ from the ones the counters were taken on."""
@@ -394,7 +406,8 @@ def main():
         "conv_variant_sweep_ms": results.get("sweep"),
         "kernels_bf16": results["bf16"]["kernels"],
         "batch1_latency_ms": {k: results[k]["batch1_ms"] for k in llrs},
-        "roofline": {"bound": "mfma", "kernel": "conv3x3_kernel (residual conv_b, bf16)", "achieved": achieved / 1e12,
+        "roofline": {"bound": "mfma", "kernel": "conv_b (residual add, bf16): " + CONV_VARIANT_KERNELS[results["variants"]["bf16"]["conv_b"]],
+                     "achieved": achieved / 1e12,
                      "peak": PEAKS["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAKS["bf16"],
                      "traffic": (stored_traffic(results["variants"]["bf16"]["conv_b"])
                                  if args.workload == "m" else None),
