@@ -173,20 +173,49 @@ def nrx_inputs(y, h_ls, cfg):
     return X
 
 
-def forward(W, cfg, y, h_ls, bits_per_sym, keep=False):
+def iteration_ends(cfg):
+    """Number of conv blocks completed at the end of each CGNN iteration.  An iteration is one
+    message-passing round followed by the state-update blocks up to the next round (Sec. II-B), so
+    iteration r ends where round r + 1 begins; a network without message passing is one iteration."""
+    if cfg.R == 0:
+        return [cfg.C]
+    return [((r + 1) * cfg.C) // cfg.R for r in range(cfg.R)]
+
+
+def readout(W, cfg, h, mask):
+    """ReadoutLLRs on the state h [S, T, U, d] -> masked llr [U, T, S, m_max] and (h, r1, q)."""
+    r1 = h @ W["readout.w1"] + W["readout.b1"]
+    q = relu(r1)
+    out = q @ W["readout.w2"] + W["readout.b2"]          # [S, T, U, m_max]
+    return np.transpose(out, (2, 1, 0, 3)) * mask[:, None, None, :], (h, r1, q)
+
+
+def forward(W, cfg, y, h_ls, bits_per_sym, keep=False, n_iter=None, all_iters=False):
     """One slot. y [S,T,Bs], h_ls [S,T,U,Bs] -> llr [U, T, S, m_max] (masked) (+ cache)."""
-    return forward_x(W, cfg, nrx_inputs(y, h_ls, cfg), bits_per_sym, keep)
+    return forward_x(W, cfg, nrx_inputs(y, h_ls, cfg), bits_per_sym, keep, n_iter, all_iters)
 
 
-def forward_x(W, cfg, X, bits_per_sym, keep=False):
-    """Same as forward() from the stacked input features X[s, t, u, 4B+2]."""
+def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False):
+    """Same as forward() from the stacked input features X[s, t, u, 4B+2].
+
+    n_iter runs only the first n_iter CGNN iterations and reads out after the last of them
+    (inference-time depth control, Sec. IV-C); all_iters returns the list of LLRs read out after
+    every iteration run (the multi-loss of Sec. III-C uses all of them), the readout layers shared."""
     U = X.shape[2]
+    ends = iteration_ends(cfg)
+    n_iter = len(ends) if n_iter is None else n_iter
+    assert 1 <= n_iter <= len(ends)
+    c_run = ends[n_iter - 1]
+    mask = np.zeros((U, cfg.m_max))
+    for u in range(U):
+        mask[u, :bits_per_sym[u]] = 1.0
     pe = X[..., 4 * cfg.B:]
-    cache = {"X": X}
+    cache = {"X": X, "mask": mask, "c_run": c_run, "readouts": []}
     h = conv3x3(X, W["conv_in.w"], W["conv_in.b"])
     cache["h0"] = h
     mpb = cfg.mp_blocks()
-    for i in range(cfg.C):
+    llrs = []
+    for i in range(c_run):
         if i in mpb:
             r = mpb.index(i)
             a1 = h @ W[f"mp{r}.w1"] + W[f"mp{r}.b1"]
@@ -203,33 +232,40 @@ def forward_x(W, cfg, X, bits_per_sym, keep=False):
         h_new = h + conv3x3(a, W[f"blk{i}.conv_b.w"], W[f"blk{i}.conv_b.b"])
         cache[f"blk{i}"] = (xin, n, lnc, a)
         h = h_new
-    r1 = h @ W["readout.w1"] + W["readout.b1"]
-    q = relu(r1)
-    out = q @ W["readout.w2"] + W["readout.b2"]          # [S, T, U, m_max]
-    cache["readout"] = (h, r1, q)
-    mask = np.zeros((U, cfg.m_max))
-    for u in range(U):
-        mask[u, :bits_per_sym[u]] = 1.0
-    llr = np.transpose(out, (2, 1, 0, 3)) * mask[:, None, None, :]
-    cache["mask"] = mask
-    return (llr, cache) if keep else llr
+        if (all_iters and i + 1 in ends) or i + 1 == c_run:
+            llr, rc = readout(W, cfg, h, mask)
+            llrs.append(llr)
+            cache["readouts"].append((i + 1, rc))
+    cache["readout"] = cache["readouts"][-1][1]
+    res = llrs if all_iters else llrs[-1]
+    return (res, cache) if keep else res
 
 
 def backward(W, cfg, cache, dllr):
-    """Gradients of sum(dllr * llr) w.r.t. every weight tensor (dict)."""
+    """Gradients of sum_k sum(dllr_k * llr_k) w.r.t. every weight tensor (dict), over the readouts the
+    forward took (dllr is one array for a single readout, or a list aligned with them)."""
     G = {k: np.zeros_like(v) for k, v in W.items()}
-    dout = np.transpose(dllr * cache["mask"][:, None, None, :], (2, 1, 0, 3))   # [S, T, U, m]
-    h, r1, q = cache["readout"]
-    G["readout.w2"] = q.reshape(-1, q.shape[-1]).T @ dout.reshape(-1, dout.shape[-1])
-    G["readout.b2"] = dout.reshape(-1, dout.shape[-1]).sum(axis=0)
-    dq = dout @ W["readout.w2"].T
-    dr1 = dq * (r1 > 0)
-    G["readout.w1"] = h.reshape(-1, h.shape[-1]).T @ dr1.reshape(-1, dr1.shape[-1])
-    G["readout.b1"] = dr1.reshape(-1, dr1.shape[-1]).sum(axis=0)
-    dh = dr1 @ W["readout.w1"].T
+    dl = dllr if isinstance(dllr, list) else [dllr]
+    at = [c for c, _ in cache["readouts"]]
+    assert len(dl) == len(at)
+
+    def readout_back(k):
+        dout = np.transpose(dl[k] * cache["mask"][:, None, None, :], (2, 1, 0, 3))   # [S, T, U, m]
+        h, r1, q = cache["readouts"][k][1]
+        G["readout.w2"] += q.reshape(-1, q.shape[-1]).T @ dout.reshape(-1, dout.shape[-1])
+        G["readout.b2"] += dout.reshape(-1, dout.shape[-1]).sum(axis=0)
+        dq = dout @ W["readout.w2"].T
+        dr1 = dq * (r1 > 0)
+        G["readout.w1"] += h.reshape(-1, h.shape[-1]).T @ dr1.reshape(-1, dr1.shape[-1])
+        G["readout.b1"] += dr1.reshape(-1, dr1.shape[-1]).sum(axis=0)
+        return dr1 @ W["readout.w1"].T
+
     d = cfg.d
     mpb = cfg.mp_blocks()
-    for i in reversed(range(cfg.C)):
+    dh = 0.0
+    for i in reversed(range(cache["c_run"])):
+        if i + 1 in at:
+            dh = dh + readout_back(at.index(i + 1))
         xin, n, lnc, a = cache[f"blk{i}"]
         # h_new = h + conv_b(a)
         da, G[f"blk{i}.conv_b.w"], G[f"blk{i}.conv_b.b"] = conv3x3_backward(a, W[f"blk{i}.conv_b.w"], dh)

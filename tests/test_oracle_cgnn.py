@@ -220,3 +220,64 @@ def test_window_reproduces_full_grid():
         lo, hi = max(0, s0 - 16) & ~1, min(S, s0 + 17)
         win = cgnn.forward(W, net, y[lo:hi], h[lo:hi], d.bits_per_sym)[:, :, s0 - lo, :]
         assert np.array_equal(win, full[:, :, s0, :])
+
+
+def _truncated(W, cfg, k):
+    """The network of the first k CGNN iterations as a network of its own (its config and weights)."""
+    ck = cgnn.iteration_ends(cfg)[k - 1]
+    sub = cgnn.NetConfig(cfg.B, cfg.d, ck, k if cfg.R else 0, cfg.m_max)
+    return {name: W[name] for name, _ in cgnn.layout(sub)}, sub
+
+
+def test_depth_control_equals_shallower_network():
+    # running the first k iterations and reading out (Sec. IV-C) is the plain forward of the network made of
+    # those blocks and rounds only; all_iters returns the same LLRs after every iteration
+    cfg = cgnn.NetConfig(2, 6, 6, 3, 4)
+    assert cgnn.iteration_ends(cfg) == [2, 4, 6]
+    assert cgnn.iteration_ends(cgnn.NetConfig(2, 6, 6, 2, 4)) == [3, 6]
+    assert cgnn.iteration_ends(cgnn.NetConfig(2, 6, 2, 0, 4)) == [2]
+    W = _random_net(cfg, 8)
+    desc, r, h = _slot(seed=9)
+    m_list = [4, 2, 4]
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    every = cgnn.forward_x(W, cfg, X, m_list, all_iters=True)
+    assert len(every) == 3
+    assert np.array_equal(every[-1], cgnn.forward_x(W, cfg, X, m_list))
+    for k in (1, 2, 3):
+        Wk, ck = _truncated(W, cfg, k)
+        assert ck.mp_blocks() == cfg.mp_blocks()[:k]
+        ref = cgnn.forward_x(Wk, ck, X, m_list)
+        assert np.array_equal(cgnn.forward_x(W, cfg, X, m_list, n_iter=k), ref)
+        assert np.array_equal(every[k - 1], ref)
+    # the readouts differ from iteration to iteration (the state keeps changing)
+    assert not np.allclose(every[0], every[1])
+
+
+def test_multi_loss_gradient():
+    # the multi-loss gradient (Sec. III-C: one loss per iteration's readout, readout layers shared) is the sum
+    # of the single-readout gradients of the truncated networks, and matches central differences
+    cfg = cgnn.NetConfig(2, 6, 4, 2, 4)
+    W = _random_net(cfg, 11)
+    desc, r, h = _slot(seed=12)
+    m_list = [4, 4, 2]
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    llrs, cache = cgnn.forward_x(W, cfg, X, m_list, keep=True, all_iters=True)
+    rng = np.random.default_rng(13)
+    dl = [rng.standard_normal(l.shape) for l in llrs]
+    G = cgnn.backward(W, cfg, cache, dl)
+    S = {k: np.zeros_like(v) for k, v in W.items()}
+    for k in (1, 2):
+        Wk, ck = _truncated(W, cfg, k)
+        _, ca = cgnn.forward_x(Wk, ck, X, m_list, keep=True)
+        for name, g in cgnn.backward(Wk, ck, ca, dl[k - 1]).items():
+            S[name] += g
+    for name in W:
+        assert np.allclose(G[name], S[name], rtol=1e-12, atol=1e-12), name
+    eps = 1e-6
+
+    def f(Wx):
+        return sum(np.sum(d * l) for d, l in zip(dl, cgnn.forward_x(Wx, cfg, X, m_list, all_iters=True)))
+    v = {k: rng.standard_normal(w.shape) for k, w in W.items()}
+    fd = (f({k: W[k] + eps * v[k] for k in W}) - f({k: W[k] - eps * v[k] for k in W})) / (2 * eps)
+    an = sum(np.sum(G[k] * v[k]) for k in W)
+    assert abs(fd - an) <= 1e-6 * abs(fd)
