@@ -175,7 +175,7 @@ def nrx_inputs(y, h_ls, cfg):
 
 def iteration_ends(cfg):
     """Number of conv blocks completed at the end of each CGNN iteration.  An iteration is one
-    message-passing round followed by the state-update blocks up to the next round (Sec. II-B), so
+    message-passing round followed by the state-update blocks up to the next round (Sec. II-A), so
     iteration r ends where round r + 1 begins; a network without message passing is one iteration."""
     if cfg.R == 0:
         return [cfg.C]
@@ -199,8 +199,8 @@ def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False)
     """Same as forward() from the stacked input features X[s, t, u, 4B+2].
 
     n_iter runs only the first n_iter CGNN iterations and reads out after the last of them
-    (inference-time depth control, Sec. IV-C); all_iters returns the list of LLRs read out after
-    every iteration run (the multi-loss of Sec. III-C uses all of them), the readout layers shared."""
+    (inference-time depth control, Sec. IV-B); all_iters returns the list of LLRs read out after
+    every iteration run (the multi-loss of Sec. II-B uses all of them), the readout layers shared."""
     U = X.shape[2]
     ends = iteration_ends(cfg)
     n_iter = len(ends) if n_iter is None else n_iter

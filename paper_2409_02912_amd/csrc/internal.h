@@ -155,11 +155,13 @@ struct WgradArgs {
 template <typename T>
 void launch_wgrad(const WgradArgs<T> &a, hipStream_t st);
 void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
-                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st);
+                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st,
+                         bool acc = false);
 template <typename T>
 void launch_colsum(const T *dy, const SlotGeo *geo, int n_slots, float *partial, hipStream_t st);
 void launch_bias_pe(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
-                    float *dw, hipStream_t st);
+                    float *dw, hipStream_t st,
+                    bool acc = false);
 void launch_ln_reduce(const float *part, int n, int64_t g_off, int64_t b_off, float *dw, hipStream_t st);
 
 template <typename T>
@@ -182,7 +184,8 @@ struct RoBwdArgs {
   const float *w2;          // master readout w2 [128][m_max]
   const T *w1t;             // transposed prepped readout w1
   T *dr;                    // hidden-layer gradient [rows][128] (for dW1)
-  T *dh;                    // gradient w.r.t. the final state [rows][128]
+  T *dh;                    // gradient w.r.t. the state read out [rows][128]
+  int accumulate;           // add to dh (a readout before the last CGNN iteration) instead of writing it
   float *part;              // per-workgroup [1032] partials of dW2 (128 x 8) and db2 (8)
   int m_max;
   const SlotGeo *geo;

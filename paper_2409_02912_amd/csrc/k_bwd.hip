@@ -165,9 +165,9 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
         dst[((4 * wm + m) * 16 + 4 * lk + i) * 128 + (4 * wn + n) * 16 + lr] = acc[m][n][i];
 }
 
-// dw[layout] = sum over partitions, fixed order
+// dw[layout] = sum over partitions, fixed order (added to dw when acc)
 __global__ void wgrad_reduce_kernel(const float *partials, int n_part, int n_taps, int tap0, int n_slices,
-                                    int cin_real, int cin_total, int conv, int64_t dst_off, float *dw) {
+                                    int cin_real, int cin_total, int conv, int64_t dst_off, float *dw, int acc) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int njob = n_taps * n_slices;
   if (e >= (int64_t)njob * 128 * 128) return;
@@ -178,7 +178,7 @@ __global__ void wgrad_reduce_kernel(const float *partials, int n_part, int n_tap
   double s = 0.0;
   for (int p = 0; p < n_part; ++p) s += partials[((int64_t)p * njob + job) * 128 * 128 + c * 128 + o];
   const int64_t idx = conv ? ((int64_t)tap * cin_total + cg) * 128 + o : (int64_t)cg * 128 + o;
-  dw[dst_off + idx] = (float)s;
+  dw[dst_off + idx] = acc ? dw[dst_off + idx] + (float)s : (float)s;
 }
 
 // Column sums of dY per (slot, t, class = parity*3 + edge): partial[slot][t][6][128].
@@ -249,12 +249,12 @@ __global__ void colsum_reduce_kernel(const float *partial, int n_slots, float *r
 // Bias gradient (sum of all classes; block 9) and, for layers with a folded PE,
 // the PE weight gradients of tap blockIdx.x (blocks 0..8).  Thread = output channel.
 __global__ void bias_pe_kernel(const float *red, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
-                               float *dw) {
+                               float *dw, int acc) {
   const int o = threadIdx.x, tap = blockIdx.x;
   if (tap == 9) {
     double b = 0.0;
     for (int k = 0; k < 14 * 6; ++k) b += red[k * 128 + o];
-    dw[bias_off + o] = (float)b;
+    dw[bias_off + o] = acc ? dw[bias_off + o] + (float)b : (float)b;
     return;
   }
   if (pe_w_off < 0) return;
@@ -504,6 +504,12 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
           float v[8];
 #pragma unroll
           for (int n = 0; n < 8; ++n) v[n] = acc[m][n][i];
+          if (a.accumulate) {
+            float o[8];
+            pack8<T>::load(a.dh + (gbase + r) * NRX_D + ch0, o);
+#pragma unroll
+            for (int n = 0; n < 8; ++n) v[n] += o[n];
+          }
           pack8<T>::store(a.dh + (gbase + r) * NRX_D + ch0, v);
         }
       }
@@ -555,22 +561,22 @@ void launch_wgrad(const WgradArgs<T> &a, hipStream_t st) {
   hipLaunchKernelGGL(wgrad_kernel<T>, dim3(grid), dim3(256), 0, st, a);
 }
 void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
-                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st) {
+                         int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st, bool acc) {
   const int64_t n = (int64_t)n_taps * n_slices * 128 * 128;
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, partials, n_part,
-                     n_taps, tap0, n_slices, cin_real, cin_total, conv, dst_off, dw);
+                     n_taps, tap0, n_slices, cin_real, cin_total, conv, dst_off, dw, acc ? 1 : 0);
 }
 template <typename T>
 void launch_colsum(const T *dy, const SlotGeo *geo, int n_slots, float *partial, hipStream_t st) {
   hipLaunchKernelGGL(colsum_kernel<T>, dim3(n_slots, 14), dim3(256), 0, st, dy, geo, partial);
 }
 void launch_bias_pe(const float *partial, int n_slots, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch,
-                    float *dw, hipStream_t st) {
+                    float *dw, hipStream_t st, bool acc) {
   // the reduced table lives right after the per-slot partials
   float *red = const_cast<float *>(partial) + (int64_t)n_slots * 14 * 768;
   hipLaunchKernelGGL(colsum_reduce_kernel, dim3((14 * 768 + 255) / 256), dim3(256), 0, st, partial, n_slots, red);
   hipLaunchKernelGGL(bias_pe_kernel, dim3(10), dim3(128), 0, st, (const float *)red, bias_off, pe_w_off, cin_total,
-                     pe_ch, dw);
+                     pe_ch, dw, acc ? 1 : 0);
 }
 void launch_ln_reduce(const float *part, int n, int64_t g_off, int64_t b_off, float *dw, hipStream_t st) {
   hipLaunchKernelGGL(ln_reduce_kernel, dim3(1), dim3(256), 0, st, part, n, g_off, b_off, dw);

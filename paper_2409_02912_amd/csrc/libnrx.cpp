@@ -267,9 +267,11 @@ struct GraphKey {
   bool save;
   uint64_t variants;   // conv kernel variant per layer class, 4 bits each
   uint64_t epoch;      // FP8 activation-scale version (scales are kernel arguments)
+  int iters;           // CGNN iterations run
+  int64_t llr_stride;  // > 0: a readout after every iteration
   bool operator<(const GraphKey &o) const {
-    return std::tie(plan, w, y, h, llr, ws, save, variants, epoch) <
-           std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save, o.variants, o.epoch);
+    return std::tie(plan, w, y, h, llr, ws, save, variants, epoch, iters, llr_stride) <
+           std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save, o.variants, o.epoch, o.iters, o.llr_stride);
   }
 };
 
@@ -320,9 +322,13 @@ struct nrx_model {
   std::vector<hipEvent_t> pool;
   double prof_ms[NRX_K_NCLASS] = {0};
   int64_t prof_n[NRX_K_NCLASS] = {0};
-  // last save_acts forward (for nrx_backward)
+  // CGNN iterations run by the forward (inference-time depth control, Sec. IV-B); 0 = all
+  int n_iter = 0;
+  // last save_acts forward (for nrx_backward): its workspace, batch, depth and readouts kept
   const void *saved_ws = nullptr;
   const Plan *saved_plan = nullptr;
+  int saved_iters = 0;
+  bool saved_multi = false;
   std::mutex mu;
 };
 
@@ -531,6 +537,16 @@ extern "C" nrx_status nrx_weight_tensor(const nrx_model *m, int32_t idx, char *n
 
 namespace {
 
+// Blocks completed at the end of each CGNN iteration: iteration r is message-passing round r and
+// the state-update blocks up to the next round (Sec. II-A); without message passing the whole
+// stack is one iteration.
+std::vector<int> iteration_ends(const nrx_model_config &c) {
+  std::vector<int> e;
+  if (c.n_rounds == 0) e.push_back(c.n_blocks);
+  for (int r = 0; r < c.n_rounds; ++r) e.push_back(((r + 1) * c.n_blocks) / c.n_rounds);
+  return e;
+}
+
 struct FwdLayout {
   size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps;
   size_t h8 = 0, a8 = 0, agg8 = 0, w8 = 0, wsc = 0, f8jobs = 0, amax = 0;   // FP8 models
@@ -538,7 +554,7 @@ struct FwdLayout {
   std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
   std::vector<size_t> stats;  // per block (training)
   std::vector<size_t> agg, m1;  // per round (inference: one agg)
-  size_t q;                   // readout hidden (training)
+  std::vector<size_t> q;      // readout hidden after each CGNN iteration (training)
   // backward (training layout only)
   size_t bjobs = 0, bprep = 0, zero = 0, dh = 0, dz = 0, dagg = 0, dmsg = 0, dm1 = 0, dr = 0;
   size_t wpart = 0, cpart = 0, lpart = 0, rpart = 0;
@@ -577,7 +593,6 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.h.push_back(o); o += act;
     L.a.push_back(o); o += act;
     L.agg.push_back(o); o += act;
-    L.q = 0;
   } else {
     for (int i = 0; i <= C; ++i) { L.h.push_back(o); o += act; }
     for (int i = 0; i < C; ++i) { L.z.push_back(o); o += act; }
@@ -585,7 +600,7 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     for (int i = 0; i < C; ++i) { L.stats.push_back(o); o = align256(o + (size_t)P->rows * 8); }
     for (int r = 0; r < R; ++r) { L.agg.push_back(o); o += act; }
     for (int r = 0; r < R; ++r) { L.m1.push_back(o); o += act; }
-    L.q = o; o += act;
+    for (size_t k = 0; k < iteration_ends(m->cfg).size(); ++k) { L.q.push_back(o); o += act; }
     L.bjobs = o; o = align256(o + sizeof(PrepJob) * m->bjobs.size());
     L.bprep = o; o = align256(o + (size_t)m->bprep_elems * ts);
     L.zero = o; o = align256(o + 128 * 4);
@@ -598,7 +613,7 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.wpart = o; o = align256(o + (size_t)2 * num_cu() * 128 * 128 * 4);   // partitions x jobs <= 2 blocks per CU
     L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
-    L.rpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 1032 * 4);
+    L.rpart = o; o = align256(o + iteration_ends(m->cfg).size() * BWD_GRID_MAX * 1032 * 4);
   }
   L.total = o;
   return L;
@@ -640,7 +655,7 @@ nrx_status model_pinned(nrx_model *m) {
 
 template <typename T>
 nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *y, float *h_ls,
-                        float *llr, bool save, char *ws, hipStream_t st) {
+                        float *llr, bool save, char *ws, hipStream_t st, int n_run = 0, int64_t llr_stride = 0) {
   nrx_status ps = model_pinned(m);
   if (ps != NRX_OK) return ps;
   if (plan_upload(const_cast<Plan *>(P), ws + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
@@ -715,7 +730,29 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   if (f8) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
   if (amax) a0.amax = amax + 0;
   conv(a0, EPI_STORE, NRX_K_CONV_IN, false);
-  for (int i = 0; i < C; ++i) {
+  // CGNN iterations run (depth control) and, with llr_stride > 0, a readout after each of them
+  const std::vector<int> ends = iteration_ends(m->cfg);
+  if (n_run <= 0 || n_run > (int)ends.size()) n_run = (int)ends.size();
+  const int c_run = ends[n_run - 1];
+  auto readout = [&](int blocks_done, int k, bool last) {
+    MlpArgs<T> ra{};
+    ra.h = buf(L.h[save ? blocks_done : 0]);
+    ra.w1 = wprep + m->ro.p1;
+    ra.b1 = vec(m->ro.b1, m->ro.b1pad);
+    ra.b2 = w + m->ro.b2;
+    ra.w2 = wprep + m->ro.p2;
+    ra.save_m1 = save ? buf(L.q[k]) : nullptr;
+    ra.llr = llr + (int64_t)k * llr_stride;
+    ra.m_max = m->cfg.m_max;
+    ra.geo = D.geo;
+    ra.tiles = D.rt;
+    ra.n_tiles = (int)P->rt.size();
+    ra.slot_done = last ? (unsigned int *)(ws + L.done) : nullptr;   // the pass completes at the last readout
+    ra.stamps = last ? (unsigned long long *)(ws + L.stamps) : nullptr;
+    ProfMark pm(m, NRX_K_READOUT, st);
+    launch_readout<T>(ra, grid_mlp, st);
+  };
+  for (int i = 0; i < c_run; ++i) {
     const BlockLayer &B = m->blocks[i];
     T *h_in = buf(L.h[save ? i : 0]);
     T *h_out = buf(L.h[save ? i + 1 : 0]);
@@ -777,25 +814,12 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     }
     if (amax && i + 1 < C) cb.amax = amax + i + 1;
     conv(cb, EPI_RESID, NRX_K_CONV_B, f8);
+    if (llr_stride > 0 && i + 1 < c_run) {
+      for (int k = 0; k < n_run - 1; ++k)
+        if (ends[k] == i + 1) readout(i + 1, k, false);
+    }
   }
-  MlpArgs<T> ra{};
-  ra.h = buf(L.h[save ? C : 0]);
-  ra.w1 = wprep + m->ro.p1;
-  ra.b1 = vec(m->ro.b1, m->ro.b1pad);
-  ra.b2 = w + m->ro.b2;
-  ra.w2 = wprep + m->ro.p2;
-  ra.save_m1 = save ? buf(L.q) : nullptr;
-  ra.llr = llr;
-  ra.m_max = m->cfg.m_max;
-  ra.geo = D.geo;
-  ra.tiles = D.rt;
-  ra.n_tiles = (int)P->rt.size();
-  ra.slot_done = (unsigned int *)(ws + L.done);
-  ra.stamps = (unsigned long long *)(ws + L.stamps);
-  {
-    ProfMark pm(m, NRX_K_READOUT, st);
-    launch_readout<T>(ra, grid_mlp, st);
-  }
+  readout(c_run, llr_stride > 0 ? n_run - 1 : 0, true);
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }
@@ -814,9 +838,10 @@ extern "C" size_t nrx_workspace_bytes(nrx_model *m, const nrx_slot_desc *slots, 
   return fwd_layout(m, P, save_acts != 0).total;
 }
 
-extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *y,
-                                  float *h_ls, float *llr, int32_t save_acts, void *ws, size_t ws_bytes,
-                                  hipStream_t st) {
+namespace {
+nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *y,
+                         float *h_ls, float *llr, int64_t llr_stride, int32_t save_acts, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
   if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
   Plan *P;
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
@@ -825,15 +850,18 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
   if (m->cfg.d != NRX_D && save_acts) return fail(NRX_ERR_UNSUPPORTED, "training needs d = 128 in this build");
   const FwdLayout L = fwd_layout(m, P, save_acts != 0);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
+  const int iters = m->n_iter > 0 ? m->n_iter : (int)iteration_ends(m->cfg).size();
   auto run = [&](hipStream_t s2) {
-    if (m->cfg.precision == NRX_FP32) return forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2);
-    return forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2);
+    if (m->cfg.precision == NRX_FP32)
+      return forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride);
+    return forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride);
   };
   if ((m->cfg.flags & 1) && !m->profile) {
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
     uint64_t vs = 0;
     for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (4 * c);
-    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch}, run, st);
+    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride},
+                      run, st);
   } else {
     s = run(st);
   }
@@ -841,8 +869,36 @@ extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_d
     std::lock_guard<std::mutex> lk(m->mu);
     m->saved_ws = ws;
     m->saved_plan = P;
+    m->saved_iters = iters;
+    m->saved_multi = llr_stride > 0;
   }
   return s;
+}
+}  // namespace
+
+extern "C" nrx_status nrx_forward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *y,
+                                  float *h_ls, float *llr, int32_t save_acts, void *ws, size_t ws_bytes,
+                                  hipStream_t st) {
+  return forward_entry(m, w, slots, n, y, h_ls, llr, 0, save_acts, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_forward_iters(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                        const float *y, float *h_ls, float *llr, int64_t llr_stride, int32_t save_acts,
+                                        void *ws, size_t ws_bytes, hipStream_t st) {
+  if (llr_stride <= 0) return fail(NRX_ERR_INVALID, "llr_stride must be positive");
+  return forward_entry(m, w, slots, n, y, h_ls, llr, llr_stride, save_acts, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_set_iterations(nrx_model *m, int32_t n_iter) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  const int n_max = (int)iteration_ends(m->cfg).size();
+  if (n_iter < 0 || n_iter > n_max) return fail(NRX_ERR_INVALID, "n_iter %d outside 0..%d", n_iter, n_max);
+  m->n_iter = n_iter;
+  return NRX_OK;
+}
+
+extern "C" int32_t nrx_num_iterations(const nrx_model *m) {
+  return m ? (int32_t)iteration_ends(m->cfg).size() : 0;
 }
 
 namespace {
@@ -1044,7 +1100,7 @@ namespace {
 
 template <typename T>
 nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *dllr,
-                         float *dw, char *ws, hipStream_t st) {
+                         float *dw, char *ws, hipStream_t st, int n_run, int64_t llr_stride) {
   {
     std::lock_guard<std::mutex> lk(m->mu);
     if (!m->pinned_bjobs) {
@@ -1062,13 +1118,12 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   const float *zero = (const float *)(ws + L.zero);
   float *wpart = (float *)(ws + L.wpart), *cpart = (float *)(ws + L.cpart);
   float *lpart = (float *)(ws + L.lpart), *rpart = (float *)(ws + L.rpart);
-  const int C = m->cfg.n_blocks;
   const int d = NRX_D;
   const int ti256 = tile_size_index(4);
   const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), std::min(num_cu() * 4, BWD_GRID_MAX));
 
   auto wgrad = [&](const T *src0, int c0, const T *src1, int c1, const T *dy, bool conv, int cin_real, int cin_total,
-                   int64_t dst) {
+                   int64_t dst, bool acc = false) {
     WgradArgs<T> a{};
     a.src0 = src0; a.c0 = c0; a.src1 = src1; a.c1 = c1;
     a.dy = dy;
@@ -1083,11 +1138,11 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.partials = wpart;
     launch_wgrad<T>(a, st);
     launch_wgrad_reduce(wpart, a.n_part, a.n_taps, a.tap0, a.n_slices, cin_real, cin_total, conv ? 1 : 0, dst, dw,
-                        st);
+                        st, acc);
   };
-  auto bias = [&](const T *dy, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch) {
+  auto bias = [&](const T *dy, int64_t bias_off, int64_t pe_w_off, int cin_total, int pe_ch, bool acc = false) {
     launch_colsum<T>(dy, D.geo, P->n, cpart, st);
-    launch_bias_pe(cpart, P->n, bias_off, pe_w_off, cin_total, pe_ch, dw, st);
+    launch_bias_pe(cpart, P->n, bias_off, pe_w_off, cin_total, pe_ch, dw, st, acc);
   };
   auto dgrad = [&](const T *src, const T *wt, int epi, int cls, T *out, const T *resid, const T *z, const float *stats,
                    const float *g) {
@@ -1117,26 +1172,38 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   };
 
   T *dh = buf(L.dh), *dz = buf(L.dz);
-  // readout
-  {
+  // readouts: the last one starts dh; with llr_stride > 0 (multi-loss) the readout after each
+  // earlier CGNN iteration adds its gradient where the reverse pass reaches that iteration's end
+  const std::vector<int> ends = iteration_ends(m->cfg);
+  const int c_run = ends[n_run - 1];
+  const int n_ro = llr_stride > 0 ? n_run : 1;
+  int ro_done = 0;
+  auto readout_back = [&](int k, int blocks_done) {
+    const bool acc = ro_done > 0;
     RoBwdArgs<T> a{};
-    a.dllr = dllr;
-    a.q = buf(L.q);
+    a.dllr = dllr + (int64_t)k * llr_stride;
+    a.q = buf(L.q[k]);
     a.w2 = w + m->ro.w2;
     a.w1t = bp + m->ro.t1;
     a.dr = buf(L.dr);
     a.dh = dh;
-    a.part = rpart;
+    a.accumulate = acc ? 1 : 0;
+    a.part = rpart + (int64_t)ro_done * grid_mlp * 1032;
     a.m_max = m->cfg.m_max;
     a.geo = D.geo;
     a.tiles = D.rt;
     a.n_tiles = (int)P->rt.size();
     launch_readout_bwd<T>(a, grid_mlp, st);
-    launch_readout_w2_reduce(rpart, grid_mlp, m->cfg.m_max, m->ro.w2, m->ro.b2, dw, st);
-    wgrad(buf(L.h[C]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro.w1);
-    bias(buf(L.dr), m->ro.b1, -1, 0, 0);
-  }
-  for (int i = C - 1; i >= 0; --i) {
+    wgrad(buf(L.h[blocks_done]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro.w1, acc);
+    bias(buf(L.dr), m->ro.b1, -1, 0, 0, acc);
+    ++ro_done;
+  };
+  readout_back(n_ro - 1, c_run);
+  for (int i = c_run - 1; i >= 0; --i) {
+    if (n_ro > 1) {
+      for (int k = 0; k < n_ro - 1; ++k)
+        if (ends[k] == i + 1) readout_back(k, i + 1);
+    }
     const BlockLayer &B = m->blocks[i];
     T *h_in = buf(L.h[i]);
     T *a_i = buf(L.a[i]);
@@ -1176,6 +1243,7 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
       dgrad(dz, bp + B.bg_a_h, EPI_RESID, NRX_K_CONV_A, dh, dh, nullptr, nullptr, nullptr);
     }
   }
+  launch_readout_w2_reduce(rpart, n_ro * grid_mlp, m->cfg.m_max, m->ro.w2, m->ro.b2, dw, st);
   // StateInit (no data gradient needed)
   const int B4 = 4 * m->cfg.n_ant;
   wgrad(buf(L.X), m->cx, nullptr, 0, dh, true, B4, B4 + 2, m->conv_in.w);
@@ -1186,21 +1254,40 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
 
 }  // namespace
 
-extern "C" nrx_status nrx_backward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
-                                   const float *dllr, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
+namespace {
+nrx_status backward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *dllr,
+                          int64_t llr_stride, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!m || !w || !dllr || !dw || !ws) return fail(NRX_ERR_INVALID, "null argument");
   Plan *P;
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
   if (s != NRX_OK) return s;
+  int iters;
   {
     std::lock_guard<std::mutex> lk(m->mu);
     if (m->saved_ws != ws || m->saved_plan != P)
       return fail(NRX_ERR_INVALID, "no save_acts forward of this batch on this workspace");
+    if (m->saved_multi != (llr_stride > 0))
+      return fail(NRX_ERR_INVALID, "the saved forward %s per-iteration readouts",
+                  m->saved_multi ? "has" : "has no");
+    iters = m->saved_iters;
   }
   const FwdLayout L = fwd_layout(m, P, true);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
-  if (m->cfg.precision == NRX_FP32) return backward_impl<float>(m, P, L, w, dllr, dw, (char *)ws, st);
-  return backward_impl<bf16_t>(m, P, L, w, dllr, dw, (char *)ws, st);
+  if (m->cfg.precision == NRX_FP32) return backward_impl<float>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride);
+  return backward_impl<bf16_t>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride);
+}
+}  // namespace
+
+extern "C" nrx_status nrx_backward(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                   const float *dllr, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
+  return backward_entry(m, w, slots, n, dllr, 0, dw, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_backward_iters(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                         const float *dllr, int64_t llr_stride, float *dw, void *ws, size_t ws_bytes,
+                                         hipStream_t st) {
+  if (llr_stride <= 0) return fail(NRX_ERR_INVALID, "llr_stride must be positive");
+  return backward_entry(m, w, slots, n, dllr, llr_stride, dw, ws, ws_bytes, st);
 }
 
 // --------------------------------------------------------- model-free calls --

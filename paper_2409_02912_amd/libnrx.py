@@ -65,6 +65,10 @@ _SIGS = {
     "nrx_workspace_bytes": (_sz, [_vp, _DESC, _i32, _i32]),
     "nrx_forward": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
     "nrx_backward": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "nrx_num_iterations": (_i32, [_vp]),
+    "nrx_set_iterations": (_i32, [_vp, _i32]),
+    "nrx_forward_iters": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "nrx_backward_iters": (_i32, [_vp, _vp, _DESC, _i32, _vp, _i64, _vp, _vp, _sz, _vp]),
     "nrx_bce_workspace_bytes": (_sz, [_DESC, _i32, _i32]),
     "nrx_bce": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nrx_adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _f, _f, _f, _f, _vp]),
@@ -194,6 +198,26 @@ def nrx_backward(model, w, slots, dllr, dw, ws, stream=None):
     arr, n = _descs(slots)
     _check(_lib.nrx_backward(model, _ptr(w), arr, n, _ptr(dllr), _ptr(dw), _ptr(ws),
                              ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_num_iterations(model):
+    return int(_lib.nrx_num_iterations(model))
+
+
+def nrx_set_iterations(model, n_iter):
+    _check(_lib.nrx_set_iterations(model, int(n_iter)))
+
+
+def nrx_forward_iters(model, w, slots, y, llr, llr_stride, ws, h_ls=None, save_acts=False, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_forward_iters(model, _ptr(w), arr, n, _ptr(y), _ptr(h_ls), _ptr(llr), int(llr_stride),
+                                  int(save_acts), _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_backward_iters(model, w, slots, dllr, llr_stride, dw, ws, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_backward_iters(model, _ptr(w), arr, n, _ptr(dllr), int(llr_stride), _ptr(dw), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def nrx_bce_workspace_bytes(slots, m_max):

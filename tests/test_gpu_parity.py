@@ -192,7 +192,7 @@ def test_bce_and_adam_match_oracle():
     assert np.allclose(tv.cpu().numpy(), ev, rtol=1e-6, atol=1e-7)
 
 
-def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4):
+def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4, all_iters=False):
     """Weights whose ReLU units all lie far from their kink on this batch.
 
     The gradient of a ReLU network jumps where a pre-activation crosses zero.  The fp32 path sums in another
@@ -201,7 +201,8 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4):
     front of every ReLU (LayerNorm beta, the first bias of the message and readout MLPs) is set per channel so
     that the channel's pre-activations over the batch sit at +-`sigmas` standard deviations (signs alternate
     over channels, so both branches are taken), iterated because each layer's inputs depend on the earlier
-    biases.  Returns the weights and the smallest |pre-activation| relative to its layer's RMS."""
+    biases (with all_iters, over the readouts after every CGNN iteration).  Returns the weights and the smallest
+    |pre-activation| relative to its layer's RMS."""
     w = w.astype(np.float64).copy()
     offs, off = {}, 0
     for name, shape in cgnn.layout(net):
@@ -216,9 +217,12 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4):
         pre = {k: [] for k, _, _ in units}
         for r in ref_slots:
             h = receiver.ls_estimate(r["y32"], r["desc"])
-            _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True)
+            _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True, all_iters=all_iters)
             for k, _, j in units:
-                pre[k].append(cache[k][j].reshape(-1, net.d))
+                if k == "readout":
+                    pre[k] += [rc[1].reshape(-1, net.d) for _, rc in cache["readouts"]]
+                else:
+                    pre[k].append(cache[k][j].reshape(-1, net.d))
         margin = np.inf
         for k, bname, _ in units:
             x = np.concatenate(pre[k])
@@ -230,39 +234,46 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4):
     return w.astype(np.float32), margin
 
 
-def _grad_case(prec, tol, cos_min, seed=21, variant=1):
+def _grad_case(prec, tol, cos_min, seed=21, variant=1, multi=False):
     shapes = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
               dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 2], slot_number=2)]
     m_max = 4
-    net = cgnn.NetConfig(4, 128, 3, 1, m_max)
-    log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R} conv variant {variant}")
+    net = cgnn.NetConfig(4, 128, 4, 2, m_max) if multi else cgnn.NetConfig(4, 128, 3, 1, m_max)
+    n_ro = len(cgnn.iteration_ends(net)) if multi else 1
+    log(f"nrx_backward: prec={prec} slots={len(shapes)} C={net.C} R={net.R} conv variant {variant} readouts {n_ro}")
     ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), seed, 0, m_max)
-    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), seed, perturb=True), net, ref_slots)
+    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), seed, perturb=True), net, ref_slots,
+                                 all_iters=multi)
     log(f"  smallest |ReLU input| / layer RMS {margin:.2e}")
-    assert margin > 5e-4
+    assert margin > 1e-4   # a hundred times the ~1e-6 displacement by rounding
     W = cgnn.unflatten(w.astype(np.float64), net)
     rng = np.random.default_rng(seed)
     descs, sz = L.make_slots(shapes, m_max)
-    dllr_np = rng.standard_normal(sz["llr"]).astype(np.float32)
-    dparts = split_llr(dllr_np.astype(np.float64), shapes, m_max)
+    stride = sz["llr"]
+    dllr_np = rng.standard_normal(n_ro * stride).astype(np.float32)
+    dparts = [split_llr(dllr_np[k * stride:(k + 1) * stride].astype(np.float64), shapes, m_max) for k in range(n_ro)]
     G = {k: np.zeros_like(v) for k, v in W.items()}
     for i, r in enumerate(ref_slots):
         h = receiver.ls_estimate(r["y32"], r["desc"])
-        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True)
-        g = cgnn.backward(W, net, cache, dparts[i])
+        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True, all_iters=multi)
+        g = cgnn.backward(W, net, cache, [dparts[k][i] for k in range(n_ro)] if multi else dparts[0][i])
         for k in G:
             G[k] += g[k]
     ref = cgnn.flatten(G, net)
     model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
     try:
         y = _upload_batch(shapes, ref_slots)
-        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        llr = torch.zeros(n_ro * stride, dtype=torch.float32, device="cuda")
         ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
         dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
         wt = dev(w)
         L.set_all_conv_variants(model, variant)
-        L.nrx_forward(model, wt, descs, y, llr, ws, save_acts=True)
-        L.nrx_backward(model, wt, descs, dev(dllr_np), dw, ws)
+        if multi:
+            L.nrx_forward_iters(model, wt, descs, y, llr, stride, ws, save_acts=True)
+            L.nrx_backward_iters(model, wt, descs, dev(dllr_np), stride, dw, ws)
+        else:
+            L.nrx_forward(model, wt, descs, y, llr, ws, save_acts=True)
+            L.nrx_backward(model, wt, descs, dev(dllr_np), dw, ws)
         torch.cuda.synchronize()
         got = dw.cpu().numpy().astype(np.float64)
         assert np.all(np.isfinite(got)), "gradient entries left unwritten"
@@ -284,6 +295,58 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1):
 @pytest.mark.parametrize("variant", [1, 4, 5, 6, 7, 8])
 def test_nrx_backward_fp32_matches_oracle(variant):
     _grad_case(0, 1e-4, 0.9999999, variant=variant)
+
+
+def test_nrx_backward_multi_loss_fp32_matches_oracle():
+    # the multi-loss gradient (Sec. II-B): readouts after both CGNN iterations, one dllr each
+    _grad_case(0, 1e-4, 0.9999999, variant=7, multi=True)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_forward_depth_control(prec, tol):
+    """Inference-time depth control (Sec. IV-B): the first k CGNN iterations and a readout, against the oracle
+    at depth k; and the readouts after every iteration in one pass."""
+    shapes = [s for s in RAGGED if s["n_ant"] <= 8]
+    net = cgnn.NetConfig(8, 128, 4, 2, 6)
+    m_max = 6
+    log(f"depth control: prec={prec} C={net.C} R={net.R} iterations {cgnn.iteration_ends(net)}")
+    ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 5, 0, m_max)
+    w = synth.he_weights(cgnn.layout(net), 5, perturb=True)
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    exp = []
+    for r in ref_slots:
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        exp.append(cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, all_iters=True))
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec)
+    try:
+        assert L.nrx_num_iterations(model) == 2
+        descs, sz = L.make_slots(shapes, m_max)
+        y = _upload_batch(shapes, ref_slots)
+        stride = sz["llr"]
+        llr = torch.zeros(2 * stride, dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        wt = dev(w)
+        L.set_all_conv_variants(model, 7)
+        for k in (1, 2):
+            L.nrx_set_iterations(model, k)
+            llr.zero_()
+            L.nrx_forward(model, wt, descs, y, llr, ws)
+            torch.cuda.synchronize()
+            got = split_llr(llr[:stride].cpu().numpy(), shapes, m_max)
+            worst = max(check_llr(got[i], exp[i][k - 1], tol) for i in range(len(shapes)))
+            log(f"  depth {k}: worst relative error {worst:.2e}")
+        L.nrx_set_iterations(model, 0)
+        llr.zero_()
+        L.nrx_forward_iters(model, wt, descs, y, llr, stride, ws)
+        torch.cuda.synchronize()
+        for k in (0, 1):
+            got = split_llr(llr[k * stride:(k + 1) * stride].cpu().numpy(), shapes, m_max)
+            worst = max(check_llr(got[i], exp[i][k], tol) for i in range(len(shapes)))
+            log(f"  readout after iteration {k + 1} (one pass): worst relative error {worst:.2e}")
+        with pytest.raises(L.NrxError):
+            L.nrx_set_iterations(model, 3)
+    finally:
+        L.nrx_model_destroy(model)
 
 
 def test_nrx_backward_bf16_close_to_oracle():

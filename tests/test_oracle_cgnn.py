@@ -230,7 +230,7 @@ def _truncated(W, cfg, k):
 
 
 def test_depth_control_equals_shallower_network():
-    # running the first k iterations and reading out (Sec. IV-C) is the plain forward of the network made of
+    # running the first k iterations and reading out (Sec. IV-B) is the plain forward of the network made of
     # those blocks and rounds only; all_iters returns the same LLRs after every iteration
     cfg = cgnn.NetConfig(2, 6, 6, 3, 4)
     assert cgnn.iteration_ends(cfg) == [2, 4, 6]
@@ -254,7 +254,7 @@ def test_depth_control_equals_shallower_network():
 
 
 def test_multi_loss_gradient():
-    # the multi-loss gradient (Sec. III-C: one loss per iteration's readout, readout layers shared) is the sum
+    # the multi-loss gradient (Sec. II-B: one loss per iteration's readout, readout layers shared) is the sum
     # of the single-readout gradients of the truncated networks, and matches central differences
     cfg = cgnn.NetConfig(2, 6, 4, 2, 4)
     W = _random_net(cfg, 11)
