@@ -22,6 +22,9 @@ WORKLOADS = {
     # small training workload (learning test: trains in about a minute)
     "t": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
               snr=(0.0, 15.0), d=128, n_blocks=2, n_rounds=1),
+    # the small training workload with two CGNN iterations (multi-loss and depth control)
+    "t2": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
+               snr=(0.0, 15.0), d=128, n_blocks=4, n_rounds=2),
     # headline workload: 273 PRB, 4 UEs, 8 antennas, 16-QAM, batch 32
     "m": dict(n_slots=32, n_prb=273, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
               snr=(10.0, 10.0), d=128, n_blocks=6, n_rounds=2),

@@ -4,7 +4,9 @@ Every step draws a fresh batch of slots with slot_sim (batch index = step, so a
 run is a pure function of the seed and resumes bit-exactly from a checkpoint),
 runs nrx_forward keeping activations, the BCE loss on the coded bits of the data
 REs (nrx_bce, fp64 reduction), nrx_backward and one Adam step on the fp32 master
-weights.  All work is enqueued on one stream; the host only reads the loss every
+weights.  With multi_loss the readout follows every CGNN iteration and the loss is
+the sum of their BCEs (Sec. II-B), so the trained network can later run at any
+depth (nrx_set_iterations, Sec. IV-B).  All work is enqueued on one stream; the host only reads the loss every
 `log_every` steps.
 
     python -m paper_2409_02912_amd.train --workload c5 --steps 2000 --out weights.npy
@@ -31,7 +33,8 @@ def weight_layout(model):
 
 
 class Trainer:
-    def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None):
+    def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None,
+                 multi_loss=False):
         import torch
         self.torch = torch
         self.w = w
@@ -51,9 +54,14 @@ class Trainer:
         self.grad = torch.zeros_like(self.params)
         self.y = torch.empty(2 * sz["y"], dtype=torch.float32, device=dev)
         self.bits = torch.empty(sz["bits"], dtype=torch.uint8, device=dev)
-        self.llr = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
-        self.dllr = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
-        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        # one LLR (and gradient) array per readout: every CGNN iteration with multi_loss, else the last
+        self.n_ro = L.nrx_num_iterations(self.model) if multi_loss else 1
+        self.multi = multi_loss
+        self.stride = sz["llr"]
+        self.llr = torch.empty(self.n_ro * sz["llr"], dtype=torch.float32, device=dev)
+        self.dllr = torch.empty(self.n_ro * sz["llr"], dtype=torch.float32, device=dev)
+        self.losses = torch.zeros(self.n_ro, dtype=torch.float64, device=dev)
+        self.loss = self.losses[self.n_ro - 1:]          # BCE of the last readout
         self.nerr = torch.zeros(1, dtype=torch.int64, device=dev)
         self.ws = torch.empty(L.nrx_workspace_bytes(self.model, self.descs, save_acts=True), dtype=torch.uint8,
                               device=dev)
@@ -63,7 +71,7 @@ class Trainer:
         self.n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in self.shapes)
         # pick the convolution tile shapes for this batch (forward timing only)
         L.slot_sim(self.sim, self.seed, 0, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
-        L.nrx_autotune(self.model, self.params, self.descs, self.y, self.llr, self.ws)
+        L.nrx_autotune(self.model, self.params, self.descs, self.y, self.llr[:self.stride], self.ws)
 
     def load(self, path):
         z = np.load(path, allow_pickle=False)
@@ -78,9 +86,18 @@ class Trainer:
 
     def train_step(self):
         L.slot_sim(self.sim, self.seed, self.step, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
-        L.nrx_forward(self.model, self.params, self.descs, self.y, self.llr, self.ws, save_acts=True)
-        L.nrx_bce(self.descs, self.m_max, self.llr, self.bits, self.dllr, self.loss, self.nerr, self.bws)
-        L.nrx_backward(self.model, self.params, self.descs, self.dllr, self.grad, self.ws)
+        if self.multi:
+            L.nrx_forward_iters(self.model, self.params, self.descs, self.y, self.llr, self.stride, self.ws,
+                                save_acts=True)
+            for k in range(self.n_ro):
+                sl = slice(k * self.stride, (k + 1) * self.stride)
+                L.nrx_bce(self.descs, self.m_max, self.llr[sl], self.bits, self.dllr[sl], self.losses[k:k + 1],
+                          self.nerr, self.bws)
+            L.nrx_backward_iters(self.model, self.params, self.descs, self.dllr, self.stride, self.grad, self.ws)
+        else:
+            L.nrx_forward(self.model, self.params, self.descs, self.y, self.llr, self.ws, save_acts=True)
+            L.nrx_bce(self.descs, self.m_max, self.llr, self.bits, self.dllr, self.loss, self.nerr, self.bws)
+            L.nrx_backward(self.model, self.params, self.descs, self.dllr, self.grad, self.ws)
         self.step += 1
         L.nrx_adam(self.params, self.grad, self.m, self.v, self.step, lr=self.lr)
 
@@ -88,8 +105,9 @@ class Trainer:
         L.nrx_model_destroy(self.model)
 
 
-def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None):
-    """BER of the NRX and of LS + LMMSE on held-out slots (a seed not used in training) at a fixed SNR."""
+def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, n_iter=0):
+    """BER of the NRX and of LS + LMMSE on held-out slots (a seed not used in training) at a fixed SNR;
+    n_iter > 0 runs the NRX at that many CGNN iterations."""
     import torch
     m_max = w["m"]
     shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
@@ -98,6 +116,7 @@ def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=Non
                        snr_db_lo=snr_db, snr_db_hi=snr_db)
     model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision)
     try:
+        L.nrx_set_iterations(model, n_iter)
         dev = "cuda"
         params = w_params if isinstance(w_params, torch.Tensor) else torch.from_numpy(w_params).to(dev)
         y = torch.empty(2 * sz["y"], dtype=torch.float32, device=dev)
@@ -146,11 +165,12 @@ def main():
     ap.add_argument("--time-limit", type=float, default=1e9, help="stop (and checkpoint) after this many seconds")
     ap.add_argument("--eval-batches", type=int, default=0)
     ap.add_argument("--eval-snr", type=float, default=10.0)
+    ap.add_argument("--multi-loss", action="store_true", help="readout and BCE after every CGNN iteration")
     args = ap.parse_args()
     import torch
     w = synth.WORKLOADS[args.workload]
     prec = L.NRX_BF16 if args.precision == "bf16" else L.NRX_FP32
-    tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb)
+    tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb, multi_loss=args.multi_loss)
     if args.ckpt and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(json.dumps({"resumed_at": tr.step}), flush=True)
@@ -161,7 +181,8 @@ def main():
         if tr.step % args.log_every == 0 or tr.step == args.steps:
             torch.cuda.synchronize()
             el = time.time() - t0
-            print(json.dumps({"step": tr.step, "loss": tr.loss.item(), "ber": tr.nerr.item() / tr.n_bits,
+            print(json.dumps({"step": tr.step, "loss": tr.loss.item(), "losses": tr.losses.tolist(),
+                              "ber": tr.nerr.item() / tr.n_bits,
                               "s_per_step": el / max(tr.step - start, 1)}), flush=True)
         if args.ckpt and tr.step % args.ckpt_every == 0:
             tr.save(args.ckpt)
@@ -173,9 +194,10 @@ def main():
     if args.out:
         np.save(args.out, tr.params.cpu().numpy())
     if args.eval_batches:
-        r = evaluate(tr.params, w, seed=args.seed + 1000003, batches=args.eval_batches, snr_db=args.eval_snr,
-                     precision=prec, batch=args.batch, n_prb=args.n_prb)
-        print(json.dumps({"eval": r, "snr_db": args.eval_snr, "step": tr.step}), flush=True)
+        for k in range(1, tr.n_ro + 1) if args.multi_loss else [0]:
+            r = evaluate(tr.params, w, seed=args.seed + 1000003, batches=args.eval_batches, snr_db=args.eval_snr,
+                         precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k)
+            print(json.dumps({"eval": r, "snr_db": args.eval_snr, "step": tr.step, "n_iter": k}), flush=True)
     tr.close()
 
 
