@@ -181,6 +181,11 @@ __global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
   const int lr = lane & 15, lk = lane >> 4;
   const int ch0 = 8 * lr;
   float vmax = 0.f;
+  // biases of this lane's channels, read once: a global load inside the tile loop would make the
+  // compiler wait for every outstanding vector-memory operation, the next tile's copy included
+  float bias1[8], bias2[8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb) { bias1[nb] = a.b1[ch0 + nb]; bias2[nb] = a.b2[ch0 + nb]; }
 
   // weights: 2 x 32 KB, 16 DMA instructions of 1 KB per wave (64-byte rows, swizzled pieces)
   {
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
         float v[8];
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
-          const float x = acc[mb][nb][i] + a.b1[ch0 + nb];
+          const float x = acc[mb][nb][i] + bias1[nb];
           v[nb] = x > 0.f ? x : 0.f;
         }
         v16 q;
@@ -256,9 +261,6 @@ __global__ __launch_bounds__(64 * NW, 1) void mp_lds_kernel(MlpArgs<bf16_t> a) {
         st16(t + apos(r, lr), q);
       }
     gemm(lw2);
-    float bias2[8];
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb) bias2[nb] = a.b2[ch0 + nb];
     auto emit = [&](int r, const float *v) {
       if (r < tl.nrows) {
         const int64_t grow = g.row_base + tl.row0 + r;
@@ -347,6 +349,12 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
   const int ch0 = 8 * lr;
   const int M = a.m_max;
   const float b2 = lr < M ? a.b2[lr] : 0.f;
+  // first-layer biases of this lane's channels, read once (a global load inside the tile loop
+  // would make the compiler wait for every outstanding vector-memory operation, the next
+  // tile's copy included)
+  float bias1[8];
+#pragma unroll
+  for (int nb = 0; nb < 8; ++nb) bias1[nb] = a.b1[ch0 + nb];
   {
     const i32x4_t r1 = rsrc_words(a.w1, WB), r2 = rsrc_words(a.w2, W2B);
 #pragma unroll
@@ -408,7 +416,7 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
         float v[8];
 #pragma unroll
         for (int nb = 0; nb < 8; ++nb) {
-          const float x = acc[mb][nb][i] + a.b1[ch0 + nb];
+          const float x = acc[mb][nb][i] + bias1[nb];
           v[nb] = x > 0.f ? x : 0.f;
         }
         v16 q;
@@ -430,6 +438,9 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
     }
     if (lr < M) {
       const int S = g.S;
+      // bits per symbol of the slot's UEs by scalar loads (a per-lane load would wait as above)
+      const int mu0 = ldc(&a.geo[tl.slot].m[0]), mu1 = ldc(&a.geo[tl.slot].m[1]);
+      const int mu2 = ldc(&a.geo[tl.slot].m[2]), mu3 = ldc(&a.geo[tl.slot].m[3]);
 #pragma unroll
       for (int mb = 0; mb < MBW; ++mb)
 #pragma unroll
@@ -440,7 +451,7 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
             const int s = R / (14 * U);
             const int rem = R - s * 14 * U;
             const int tt = rem / U, u = rem - tt * U;
-            const int mu = a.geo[tl.slot].m[u];
+            const int mu = u == 0 ? mu0 : (u == 1 ? mu1 : (u == 2 ? mu2 : mu3));
             a.llr[llr_off + (((int64_t)u * 14 + tt) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
           }
         }
