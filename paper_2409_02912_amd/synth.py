@@ -16,6 +16,11 @@ WORKLOADS = {
                snr=(5.0, 30.0), d=128, n_blocks=8, n_rounds=3),
     "c5": dict(n_slots=64, n_prb=106, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
                snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
+    # a fixed "site" (stand-in for the site-specific data of Sec. V): the C5 shape with one channel profile of its
+    # own, 6 taps of 150 ns decay, BS-array correlation 0.7, UE speeds uniform in 0..8 m/s (Doppler up to 93 Hz
+    # at a 3.5 GHz carrier)
+    "site": dict(n_slots=64, n_prb=106, n_ant=8, n_ue=4, m=4, n_taps=6, decay_ns=150.0, doppler=93.0, rho=0.7,
+                 snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
     # uneven batch: per slot PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM (ragged_shapes)
     "c4": dict(n_slots=256, ragged=True, n_prb=273, n_ant=16, n_ue=4, m=8, n_taps=12, decay_ns=487.42,
                doppler=0.0, rho=0.0, snr=(0.0, 30.0), d=128, n_blocks=6, n_rounds=2),

@@ -34,12 +34,13 @@ def weight_layout(model):
 
 class Trainer:
     def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None,
-                 multi_loss=False):
+                 multi_loss=False, data_batches=0):
         import torch
         self.torch = torch
         self.w = w
         self.seed = seed
         self.lr = lr
+        self.data_batches = data_batches   # > 0: a finite training set of this many batches, cycled
         self.m_max = w["m"]
         self.shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
         self.descs, sz = L.make_slots(self.shapes, self.m_max)
@@ -85,7 +86,8 @@ class Trainer:
                  step=np.int64(self.step))
 
     def train_step(self):
-        L.slot_sim(self.sim, self.seed, self.step, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
+        bi = self.step % self.data_batches if self.data_batches else self.step
+        L.slot_sim(self.sim, self.seed, bi, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
         if self.multi:
             L.nrx_forward_iters(self.model, self.params, self.descs, self.y, self.llr, self.stride, self.ws,
                                 save_acts=True)
@@ -166,18 +168,40 @@ def main():
     ap.add_argument("--eval-batches", type=int, default=0)
     ap.add_argument("--eval-snr", type=float, default=10.0)
     ap.add_argument("--multi-loss", action="store_true", help="readout and BCE after every CGNN iteration")
+    ap.add_argument("--init", default=None, help="start from these fp32 weights (.npy), e.g. to fine-tune")
+    ap.add_argument("--data-batches", type=int, default=0, help="train on a finite set of this many batches")
+    ap.add_argument("--eval-every", type=int, default=0, help="evaluate every this many steps (and at the start)")
+    ap.add_argument("--eval-workloads", default=None,
+                    help="comma-separated workloads to evaluate on (default: the training workload)")
     args = ap.parse_args()
     import torch
     w = synth.WORKLOADS[args.workload]
     prec = L.NRX_BF16 if args.precision == "bf16" else L.NRX_FP32
-    tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb, multi_loss=args.multi_loss)
+    tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb, multi_loss=args.multi_loss,
+                 data_batches=args.data_batches)
     if args.ckpt and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(json.dumps({"resumed_at": tr.step}), flush=True)
+    elif args.init:
+        tr.params.copy_(torch.from_numpy(np.load(args.init, allow_pickle=False)))
+        print(json.dumps({"init": args.init}), flush=True)
+    evals = (args.eval_workloads or args.workload).split(",")
+
+    def eval_all():
+        for name in evals:
+            for k in range(1, tr.n_ro + 1) if args.multi_loss else [0]:
+                r = evaluate(tr.params, synth.WORKLOADS[name], seed=args.seed + 1000003, batches=args.eval_batches,
+                             snr_db=args.eval_snr, precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k)
+                print(json.dumps({"eval": r, "workload": name, "snr_db": args.eval_snr, "step": tr.step,
+                                  "n_iter": k}), flush=True)
     t0 = time.time()
     start = tr.step
+    if args.eval_every and args.eval_batches:
+        eval_all()
     while tr.step < args.steps:
         tr.train_step()
+        if args.eval_every and args.eval_batches and tr.step % args.eval_every == 0:
+            eval_all()
         if tr.step % args.log_every == 0 or tr.step == args.steps:
             torch.cuda.synchronize()
             el = time.time() - t0
@@ -193,11 +217,8 @@ def main():
         tr.save(args.ckpt)
     if args.out:
         np.save(args.out, tr.params.cpu().numpy())
-    if args.eval_batches:
-        for k in range(1, tr.n_ro + 1) if args.multi_loss else [0]:
-            r = evaluate(tr.params, w, seed=args.seed + 1000003, batches=args.eval_batches, snr_db=args.eval_snr,
-                         precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k)
-            print(json.dumps({"eval": r, "snr_db": args.eval_snr, "step": tr.step, "n_iter": k}), flush=True)
+    if args.eval_batches and not (args.eval_every and tr.step % args.eval_every == 0):
+        eval_all()
     tr.close()
 
 
