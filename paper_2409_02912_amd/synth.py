@@ -21,6 +21,9 @@ WORKLOADS = {
     # at a 3.5 GHz carrier)
     "site": dict(n_slots=64, n_prb=106, n_ant=8, n_ue=4, m=4, n_taps=6, decay_ns=150.0, doppler=93.0, rho=0.7,
                  snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
+    # the small training workload on the site channel (fine-tuning test)
+    "t_site": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=6, decay_ns=150.0, doppler=93.0, rho=0.7,
+                   snr=(0.0, 15.0), d=128, n_blocks=2, n_rounds=1),
     # uneven batch: per slot PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM (ragged_shapes)
     "c4": dict(n_slots=256, ragged=True, n_prb=273, n_ant=16, n_ue=4, m=8, n_taps=12, decay_ns=487.42,
                doppler=0.0, rho=0.0, snr=(0.0, 30.0), d=128, n_blocks=6, n_rounds=2),
