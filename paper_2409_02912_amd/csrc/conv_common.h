@@ -57,6 +57,15 @@ __device__ __forceinline__ void dma16(const i32x4_t &rsrc, uint32_t lds, uint32_
                : "memory");
 }
 
+// The lane id, recomputed where it is used: the empty volatile assembly hides the value, so
+// offsets derived from it are computed in place instead of being hoisted out of the K loop
+// and held (or spilled) in registers across it.
+__device__ __forceinline__ int lane_here() {
+  int l = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 // Workgroup barrier for the DMA-pipelined kernels.  __syncthreads() carries a
 // workgroup release fence, which drains every outstanding vector-memory operation,
 // including the LDS DMA deliberately left in flight across the barrier.  Here each

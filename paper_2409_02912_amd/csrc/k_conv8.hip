@@ -65,11 +65,12 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
   // weights of step k (chunk k / 5, pair k % 5) into ring slot b
   auto stage_b = [&](int k, int b) {
     const uint32_t base = (uint32_t)k * BSLOT;
+    const int ln = lane_here();
 #pragma unroll
     for (int j = 0; j < BPW; ++j) {
       const int ins = wave + NW * j;
-      const int row = ins * 8 + (lane >> 3);
-      const int piece = (lane & 7) ^ bswz(row);
+      const int row = ins * 8 + (ln >> 3);
+      const int piece = (ln & 7) ^ bswz(row);
       dma16(wrs, lds_addr(&lds_b[b][ins * 1024]), base + row * BROWB + piece * 16);
     }
   };
@@ -96,11 +97,12 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
     if (c * KC < a.c0) { src = a.src8_0; cs = a.c0; coff = c * KC; }
     else { src = a.src8_1; cs = a.c1; coff = c * KC - a.c0; }
     const i32x4_t rs = rsrc_words(src + q.row_base * cs + coff, q.S * q.rps * cs);
+    const int ln = lane_here();
 #pragma unroll
     for (int j = 0; j < APW; ++j) {
       const int ins = wave + NW * j;
-      const int h = ins * 16 + (lane >> 2);
-      const int piece = (lane & 3) ^ swz(h);
+      const int h = ins * 16 + (ln >> 2);
+      const int piece = (ln & 3) ^ swz(h);
       // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
       const uint32_t voff = h < q.halo ? (uint32_t)((q.rel0 + h) * cs + piece * 16) : 0x80000000u;
       dma16(rs, lds_addr(&lds_a[b][ins * 16 * ROWB]), voff);
