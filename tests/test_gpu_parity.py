@@ -437,7 +437,8 @@ def test_trained_nrx_beats_lmmse():
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_graph_replay_matches_eager(prec, tol):
     """Model flag bit 0: the forward pass captured once and replayed on new inputs in the same
-    buffers gives the eager result on every replay, with unrelated eager work in between."""
+    buffers gives the eager result on every replay, with unrelated eager work in between, also
+    when the depth changes between replays."""
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
     net, m_max = cgnn.NetConfig(8, 128, 3, 2, 6), 6
     w = synth.he_weights(cgnn.layout(net), 5, perturb=True)
@@ -452,7 +453,11 @@ def test_graph_replay_matches_eager(prec, tol):
         ws_e = ws_tensor(L.nrx_workspace_bytes(eager, descs))
         ws_g = ws_tensor(L.nrx_workspace_bytes(graph, descs))
         for rep in range(4):
-            log(f"graph replay {rep}: prec={prec}")
+            # replay 2 runs the first CGNN iteration only (a graph of its own); replay 3 reuses the full one
+            depth = 1 if rep == 2 else 0
+            L.nrx_set_iterations(graph, depth)
+            L.nrx_set_iterations(eager, depth)
+            log(f"graph replay {rep}: prec={prec} depth {depth or 'all'}")
             ref_slots = oracle_batch(shapes, sim_cfg_oracle(SIMCFG), 11, rep, m_max)
             y.copy_(torch.from_numpy(pack_complex([r["y32"] for r in ref_slots])))
             llr_g.fill_(float("nan"))
