@@ -8,7 +8,10 @@ distance to the pilots] to a real state of depth d per UE and RE; N_it CGNN
 iterations, each a message-passing step (an MLP turns every UE's state into a
 message; each UE receives the sum of the messages of all *other* UEs) followed by
 a CNN that updates the state from [previous state, aggregated messages, PE];
-and ReadoutLLRs, an MLP from the final state to m LLRs per UE and RE.  Unused
+and ReadoutLLRs, an MLP from the final state to m LLRs per UE and RE.  With the
+double readout (Sec. II-A, II-B) a second MLP, ReadoutChEst, maps the same state to
+a refined channel estimate per UE, RE and antenna, trained by a gamma-scaled MSE
+against the true channel added to the BCE.  Unused
 higher-order LLR outputs are masked for lower-order QAM (Sec. III).  Training
 minimises the BCE between LLRs and bit labels, averaged over the batch
 (Sec. II-B).
@@ -23,6 +26,8 @@ structure) are fixed here and listed in the design notes:
   * R message-passing rounds, round r placed before block floor(r*C/R); the first
     conv of that block sees [h, agg, pe_t, pe_f] (2d+2 channels), others see h;
   * MP MLP m = W2 ReLU(W1 h + b1) + b2 (d -> d -> d); readout d -> d -> m_max;
+  * ReadoutChEst d -> d -> 2B, the same two-layer form, outputs interleaved
+    (Re h_b, Im h_b) per antenna b; MSE = mean over the slot's complex entries of |ĥ - h|^2;
   * PE: pe_t = standardised distance (in symbols) to the nearest DMRS symbol,
     pe_f = +1/-1 for REs off/on this UE's DMRS comb.
 """
@@ -34,12 +39,13 @@ EPS_LN = 1e-5
 
 
 class NetConfig:
-    def __init__(self, n_ant, d, n_blocks, n_rounds, m_max):
+    def __init__(self, n_ant, d, n_blocks, n_rounds, m_max, chest=False):
         self.B = n_ant
         self.d = d
         self.C = n_blocks
         self.R = n_rounds
         self.m_max = m_max
+        self.chest = chest      # second readout (ReadoutChEst)
 
     def mp_blocks(self):
         return [(r * self.C) // self.R for r in range(self.R)]
@@ -59,6 +65,9 @@ def layout(cfg):
         L += [(f"mp{r}.w1", (d, d)), (f"mp{r}.b1", (d,)), (f"mp{r}.w2", (d, d)), (f"mp{r}.b2", (d,))]
     L += [("readout.w1", (d, d)), ("readout.b1", (d,)),
           ("readout.w2", (d, cfg.m_max)), ("readout.b2", (cfg.m_max,))]
+    if cfg.chest:
+        L += [("readout_ch.w1", (d, d)), ("readout_ch.b1", (d,)),
+              ("readout_ch.w2", (d, 2 * B)), ("readout_ch.b2", (2 * B,))]
     return L
 
 
@@ -190,18 +199,30 @@ def readout(W, cfg, h, mask):
     return np.transpose(out, (2, 1, 0, 3)) * mask[:, None, None, :], (h, r1, q)
 
 
+def readout_chest(W, h, n_ant):
+    """ReadoutChEst on the state h [S, T, U, d] -> channel estimate [S, T, U, n_ant] (complex) and
+    (h, r1, q); outputs 2b and 2b + 1 are the real and imaginary part for antenna b."""
+    r1 = h @ W["readout_ch.w1"] + W["readout_ch.b1"]
+    q = relu(r1)
+    out = q @ W["readout_ch.w2"] + W["readout_ch.b2"]    # [S, T, U, 2B]
+    return out[..., 0:2 * n_ant:2] + 1j * out[..., 1:2 * n_ant:2], (h, r1, q)
+
+
 def forward(W, cfg, y, h_ls, bits_per_sym, keep=False, n_iter=None, all_iters=False):
     """One slot. y [S,T,Bs], h_ls [S,T,U,Bs] -> llr [U, T, S, m_max] (masked) (+ cache)."""
-    return forward_x(W, cfg, nrx_inputs(y, h_ls, cfg), bits_per_sym, keep, n_iter, all_iters)
+    return forward_x(W, cfg, nrx_inputs(y, h_ls, cfg), bits_per_sym, keep, n_iter, all_iters, y.shape[2])
 
 
-def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False):
+def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False, n_ant=None):
     """Same as forward() from the stacked input features X[s, t, u, 4B+2].
 
     n_iter runs only the first n_iter CGNN iterations and reads out after the last of them
     (inference-time depth control, Sec. IV-B); all_iters returns the list of LLRs read out after
-    every iteration run (the multi-loss of Sec. II-B uses all of them), the readout layers shared."""
+    every iteration run (the multi-loss of Sec. II-B uses all of them), the readout layers shared.
+    With cfg.chest every readout also applies ReadoutChEst; its estimates for the slot's n_ant
+    antennas are in cache["hests"] (one per readout)."""
     U = X.shape[2]
+    n_ant = cfg.B if n_ant is None else n_ant
     ends = iteration_ends(cfg)
     n_iter = len(ends) if n_iter is None else n_iter
     assert 1 <= n_iter <= len(ends)
@@ -210,7 +231,7 @@ def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False)
     for u in range(U):
         mask[u, :bits_per_sym[u]] = 1.0
     pe = X[..., 4 * cfg.B:]
-    cache = {"X": X, "mask": mask, "c_run": c_run, "readouts": []}
+    cache = {"X": X, "mask": mask, "c_run": c_run, "readouts": [], "hests": [], "chest": []}
     h = conv3x3(X, W["conv_in.w"], W["conv_in.b"])
     cache["h0"] = h
     mpb = cfg.mp_blocks()
@@ -236,18 +257,39 @@ def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False)
             llr, rc = readout(W, cfg, h, mask)
             llrs.append(llr)
             cache["readouts"].append((i + 1, rc))
+            if cfg.chest:
+                he, cc = readout_chest(W, h, n_ant)
+                cache["hests"].append(he)
+                cache["chest"].append(cc)
     cache["readout"] = cache["readouts"][-1][1]
     res = llrs if all_iters else llrs[-1]
     return (res, cache) if keep else res
 
 
-def backward(W, cfg, cache, dllr):
+def backward(W, cfg, cache, dllr, dhest=None):
     """Gradients of sum_k sum(dllr_k * llr_k) w.r.t. every weight tensor (dict), over the readouts the
-    forward took (dllr is one array for a single readout, or a list aligned with them)."""
+    forward took (dllr is one array for a single readout, or a list aligned with them).  dhest (same
+    form, complex [S, T, U, n_ant]: real part the gradient w.r.t. Re ĥ, imaginary part w.r.t. Im ĥ)
+    adds the term sum(Re dhest * Re ĥ + Im dhest * Im ĥ) of the ReadoutChEst outputs."""
     G = {k: np.zeros_like(v) for k, v in W.items()}
     dl = dllr if isinstance(dllr, list) else [dllr]
     at = [c for c, _ in cache["readouts"]]
     assert len(dl) == len(at)
+    dhe = None if dhest is None else (dhest if isinstance(dhest, list) else [dhest])
+    assert dhe is None or len(dhe) == len(at)
+
+    def chest_back(k):
+        h, r1, q = cache["chest"][k]
+        nb = dhe[k].shape[-1]
+        dout = np.zeros(q.shape[:-1] + (2 * cfg.B,))
+        dout[..., 0:2 * nb:2] = dhe[k].real
+        dout[..., 1:2 * nb:2] = dhe[k].imag
+        G["readout_ch.w2"] += q.reshape(-1, q.shape[-1]).T @ dout.reshape(-1, dout.shape[-1])
+        G["readout_ch.b2"] += dout.reshape(-1, dout.shape[-1]).sum(axis=0)
+        dr1 = (dout @ W["readout_ch.w2"].T) * (r1 > 0)
+        G["readout_ch.w1"] += h.reshape(-1, h.shape[-1]).T @ dr1.reshape(-1, dr1.shape[-1])
+        G["readout_ch.b1"] += dr1.reshape(-1, dr1.shape[-1]).sum(axis=0)
+        return dr1 @ W["readout_ch.w1"].T
 
     def readout_back(k):
         dout = np.transpose(dl[k] * cache["mask"][:, None, None, :], (2, 1, 0, 3))   # [S, T, U, m]
@@ -266,6 +308,8 @@ def backward(W, cfg, cache, dllr):
     for i in reversed(range(cache["c_run"])):
         if i + 1 in at:
             dh = dh + readout_back(at.index(i + 1))
+            if dhe is not None:
+                dh = dh + chest_back(at.index(i + 1))
         xin, n, lnc, a = cache[f"blk{i}"]
         # h_new = h + conv_b(a)
         da, G[f"blk{i}.conv_b.w"], G[f"blk{i}.conv_b.b"] = conv3x3_backward(a, W[f"blk{i}.conv_b.w"], dh)
@@ -319,6 +363,16 @@ def sigmoid(x):
 
 def bce_grad(llr, labels, valid, n_total):
     return (sigmoid(llr) - labels) * valid / n_total
+
+
+def mse_grad(hests, h_trues, gamma):
+    """Channel-estimate loss of the double readout (Sec. II-B): MSE = mean over every complex entry of
+    the batch (all slots, REs, UEs, antennas) of |ĥ - h|^2.  Returns MSE and, per slot, the gradient of
+    gamma * MSE (real part w.r.t. Re ĥ, imaginary part w.r.t. Im ĥ: 2 gamma (ĥ - h) / N)."""
+    n = sum(h.size for h in h_trues)
+    err = [he - h for he, h in zip(hests, h_trues)]
+    mse = sum(float(np.sum(np.abs(e) ** 2)) for e in err) / n
+    return mse, [2.0 * gamma * e / n for e in err]
 
 
 def adam_step(w, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -281,3 +281,64 @@ def test_multi_loss_gradient():
     fd = (f({k: W[k] + eps * v[k] for k in W}) - f({k: W[k] - eps * v[k] for k in W})) / (2 * eps)
     an = sum(np.sum(G[k] * v[k]) for k in W)
     assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def test_double_readout_gradient():
+    # double readout (Sec. II-A, II-B): loss = sum(dl * llr) + gamma * MSE(ĥ, h) over the readouts of every
+    # iteration; the backward with the MSE gradient matches central differences of the forward, on a slot
+    # with fewer antennas than the network (the unused ReadoutChEst outputs get no gradient)
+    cfg = cgnn.NetConfig(3, 6, 4, 2, 4, chest=True)
+    W = _random_net(cfg, 21)
+    desc, r, h = _slot(B=2, seed=22)
+    m_list = [4, 4, 4]
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    gamma = 0.7
+    llrs, cache = cgnn.forward_x(W, cfg, X, m_list, keep=True, all_iters=True, n_ant=2)
+    assert len(cache["hests"]) == 2 and cache["hests"][0].shape == r["h"].shape
+    rng = np.random.default_rng(23)
+    dl = [rng.standard_normal(l.shape) for l in llrs]
+    dhe = [cgnn.mse_grad([he], [r["h"]], gamma)[1][0] for he in cache["hests"]]
+    G = cgnn.backward(W, cfg, cache, dl, dhe)
+    assert np.all(G["readout_ch.w2"][:, 4:] == 0) and np.all(G["readout_ch.b2"][4:] == 0)
+
+    def f(Wx):
+        ls, c = cgnn.forward_x(Wx, cfg, X, m_list, keep=True, all_iters=True, n_ant=2)
+        return (sum(np.sum(d * l) for d, l in zip(dl, ls))
+                + gamma * sum(cgnn.mse_grad([he], [r["h"]], gamma)[0] for he in c["hests"]))
+    eps = 1e-8     # small enough that no ReLU of this seed changes side within the step
+    v = {k: rng.standard_normal(w.shape) for k, w in W.items()}
+    fd = (f({k: W[k] + eps * v[k] for k in W}) - f({k: W[k] - eps * v[k] for k in W})) / (2 * eps)
+    an = sum(np.sum(G[k] * v[k]) for k in W)
+    assert abs(fd - an) <= 1e-6 * abs(fd)
+    # the LLR readout and its gradient are those of the same network without ReadoutChEst
+    c0 = cgnn.NetConfig(3, 6, 4, 2, 4)
+    W0 = {name: W[name] for name, _ in cgnn.layout(c0)}
+    l0, ca0 = cgnn.forward_x(W0, c0, X, m_list, keep=True, all_iters=True, n_ant=2)
+    assert all(np.array_equal(a, b) for a, b in zip(l0, llrs))
+    G0 = cgnn.backward(W0, c0, ca0, dl)
+    Gl = cgnn.backward(W, cfg, cache, dl)
+    for name in W0:
+        assert np.allclose(G0[name], Gl[name], rtol=1e-12, atol=1e-14), name
+
+
+def test_chest_readout_closed_form_with_zero_second_layer():
+    # with a zero second layer every RE's estimate is the bias pair (b_2b + i b_2b+1) of its antenna, so
+    # the MSE and its bias gradient have closed forms: mean |c_b - h|^2 and 2 gamma sum_{antenna b} (c_b - h) / N
+    cfg = cgnn.NetConfig(2, 6, 2, 1, 4, chest=True)
+    W = _random_net(cfg, 31)
+    W["readout_ch.w2"][:] = 0.0
+    desc, r, h = _slot(B=2, seed=32)
+    X = cgnn.nrx_inputs(r["y"], h, cfg)
+    _, cache = cgnn.forward_x(W, cfg, X, [4, 4, 4], keep=True)
+    c = W["readout_ch.b2"][0::2] + 1j * W["readout_ch.b2"][1::2]
+    assert np.allclose(cache["hests"][0], np.broadcast_to(c, r["h"].shape), rtol=0, atol=1e-15)
+    gamma = 0.3
+    mse, (g,) = cgnn.mse_grad(cache["hests"], [r["h"]], gamma)
+    H = r["h"].reshape(-1, 2)
+    assert abs(mse - np.mean(np.abs(H - c) ** 2)) <= 1e-12 * mse
+    G = cgnn.backward(W, cfg, cache, np.zeros((3, 14, r["y"].shape[0], 4)), g)
+    want = 2 * gamma * np.sum(c - H, axis=0) / H.size
+    assert np.allclose(G["readout_ch.b2"][0::2], want.real, rtol=1e-10, atol=1e-14)
+    assert np.allclose(G["readout_ch.b2"][1::2], want.imag, rtol=1e-10, atol=1e-14)
+    # the first layer of the head gets no gradient through a zero second layer
+    assert np.all(G["readout_ch.w1"] == 0) and np.all(G["readout_ch.b1"] == 0)
