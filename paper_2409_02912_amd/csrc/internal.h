@@ -114,6 +114,8 @@ struct MlpArgs {
   unsigned int *amax;             // MP: max |aggregate| (float bits, atomicMax) or null
   unsigned int *slot_done;        // readout: finished tiles per slot (zeroed by launch_stamp_start)
   unsigned long long *stamps;     // readout: wall-clock time at which each slot's last tile finished
+  int chest;                      // readout: ReadoutChEst -- llr is a channel estimate in the h layout
+                                  // ([s][t][u][b] complex at geo.h_off), outputs j < 2B of the slot
 };
 template <typename T>
 void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st);
@@ -187,7 +189,10 @@ struct RoBwdArgs {
   T *dh;                    // gradient w.r.t. the state read out [rows][128]
   int accumulate;           // add to dh (a readout before the last CGNN iteration) instead of writing it
   float *part;              // per-workgroup [1032] partials of dW2 (128 x 8) and db2 (8)
-  int m_max;
+  int m_max;                // outputs of the readout (columns of w2)
+  int j0;                   // first of the 8 output columns this call handles
+  int chest;                // ReadoutChEst: dllr is the gradient of a channel estimate (h layout)
+  int acc_dr;               // add this call's hidden gradient to dr (the second column group)
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;
@@ -195,11 +200,15 @@ struct RoBwdArgs {
 template <typename T>
 void launch_readout_bwd(const RoBwdArgs<T> &a, int grid, hipStream_t st);
 void launch_readout_w2_reduce(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off, float *dw,
-                              hipStream_t st);
+                              hipStream_t st, int j0 = 0);
 
 // Training kernels.
 void launch_bce(const SlotGeo *geo, const int64_t *re_base, int n_slots, int64_t n_re, int m_max,
                 const float *llr, const uint8_t *bits, float *dllr, double *partials, int n_part,
                 double *loss, unsigned long long *nerr, double inv_n, hipStream_t st);
+// Double-readout channel loss: per slot, sum over its h-layout entries of (hest - htrue)^2 (fp64),
+// dhest = gscale * (hest - htrue); *loss = total * inv_n.
+void launch_mse(const SlotGeo *geo, int n_slots, const float *hest, const float *htrue, float *dhest, float gscale,
+                double *partials, int n_part, double *loss, double inv_n, hipStream_t st);
 void launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                  float b2, float eps, float c1, float c2, hipStream_t st);

@@ -423,7 +423,9 @@ __global__ __launch_bounds__(256) void mp_bwd_kernel(MpBwdArgs<T> a) {
 }
 
 // Readout backward.  dl (llr layout, masked to j < m_u) -> dr = (dl W2^T) [q > 0],
-// dh = dr W1^T.  Per-workgroup partials of dW2 = q^T dl and db2 = sum dl.
+// dh = dr W1^T.  Per-workgroup partials of dW2 = q^T dl and db2 = sum dl.  One call handles the
+// 8 output columns j0 .. j0 + 7; ReadoutChEst (up to 16 outputs, the gradient in the h layout)
+// takes two calls, the second adding its hidden gradient to dr.
 template <typename T>
 __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
   constexpr int PB = OpTileB<T>::PITCHB;
@@ -431,12 +433,12 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
   __shared__ float red[4][8 * 128 + 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4, ch0 = 8 * lr;
-  const int M = a.m_max;
+  const int M = a.m_max, J0 = a.j0;
   float w2[8][8];
 #pragma unroll
   for (int n = 0; n < 8; ++n)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) w2[n][j] = j < M ? a.w2[(ch0 + n) * M + j] : 0.f;
+    for (int j = 0; j < 8; ++j) w2[n][j] = J0 + j < M ? a.w2[(ch0 + n) * M + J0 + j] : 0.f;
   float pw[8][8], pb[8];   // this lane's dW2 rows (its 8 channels) and db2
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
@@ -465,10 +467,17 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
           const int s = R / (14 * U);
           const int rem = R - s * 14 * U;
           const int t = rem / U, u = rem - t * U;
-          const int mu = a.geo[tl.slot].m[u];
-          const float *src = a.dllr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
+          if (a.chest) {
+            // h layout: row R is entry R of the slot, 2B floats
+            const float *src = a.dllr + (g.h_off + (int64_t)R * g.B) * 2;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) dl[j] = (j < M && j < mu) ? src[j] : 0.f;
+            for (int j = 0; j < 8; ++j) dl[j] = J0 + j < 2 * g.B ? src[J0 + j] : 0.f;
+          } else {
+            const int mu = a.geo[tl.slot].m[u];
+            const float *src = a.dllr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) dl[j] = (J0 + j < M && J0 + j < mu) ? src[J0 + j] : 0.f;
+          }
           pack8<T>::load(a.q + (gbase + r) * NRX_D + ch0, qv);
         }
         float dr[8];
@@ -489,7 +498,17 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
 #pragma unroll
           for (int n = 0; n < 8; ++n) dr[n] = bf2f(f2bf(dr[n]));
         }
-        if (valid) pack8<T>::store(a.dr + (gbase + r) * NRX_D + ch0, dr);
+        if (valid) {
+          if (a.acc_dr) {
+            float o[8], v[8];
+            pack8<T>::load(a.dr + (gbase + r) * NRX_D + ch0, o);
+#pragma unroll
+            for (int n = 0; n < 8; ++n) v[n] = o[n] + dr[n];
+            pack8<T>::store(a.dr + (gbase + r) * NRX_D + ch0, v);
+          } else {
+            pack8<T>::store(a.dr + (gbase + r) * NRX_D + ch0, dr);
+          }
+        }
         pack8<T>::store(reinterpret_cast<T *>(lds + r * PB) + ch0, dr);
       }
     __syncthreads();
@@ -540,16 +559,16 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
 }
 
 __global__ void readout_w2_reduce_kernel(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off,
-                                         float *dw) {
+                                         float *dw, int j0) {
   const int e = threadIdx.x + blockIdx.x * blockDim.x;   // 0..1031
   if (e >= 1032) return;
   double s = 0.0;
   for (int k = 0; k < n; ++k) s += part[(int64_t)k * 1032 + e];
   if (e < 1024) {
-    const int c = e / 8, j = e % 8;
+    const int c = e / 8, j = j0 + e % 8;
     if (j < m_max) dw[w2_off + c * m_max + j] = (float)s;
-  } else if (e - 1024 < m_max) {
-    dw[b2_off + e - 1024] = (float)s;
+  } else if (j0 + e - 1024 < m_max) {
+    dw[b2_off + j0 + e - 1024] = (float)s;
   }
 }
 
@@ -590,8 +609,8 @@ void launch_readout_bwd(const RoBwdArgs<T> &a, int grid, hipStream_t st) {
   hipLaunchKernelGGL(readout_bwd_kernel<T>, dim3(grid), dim3(256), 0, st, a);
 }
 void launch_readout_w2_reduce(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off, float *dw,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(readout_w2_reduce_kernel, dim3(5), dim3(256), 0, st, part, n, m_max, w2_off, b2_off, dw);
+                              hipStream_t st, int j0) {
+  hipLaunchKernelGGL(readout_w2_reduce_kernel, dim3(5), dim3(256), 0, st, part, n, m_max, w2_off, b2_off, dw, j0);
 }
 
 template void launch_wgrad<float>(const WgradArgs<float> &, hipStream_t);

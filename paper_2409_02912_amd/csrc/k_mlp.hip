@@ -436,7 +436,20 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
       for (int mb = 0; mb < MBW; ++mb)
         o[mb] = mfma_bf16(ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk)), bf, o[mb]);
     }
-    if (lr < M) {
+    if (a.chest) {
+      // ReadoutChEst: row R = (s * 14 + t) * U + u is entry R of the slot's h layout
+      const int Bs = ldc(&a.geo[tl.slot].B);
+      const int64_t h_off = ldc(&a.geo[tl.slot].h_off);
+      if (lr < 2 * Bs) {
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = rbase + mb * 16 + 4 * lk + i;
+            if (r < tl.nrows) a.llr[(h_off + (int64_t)(tl.row0 + r) * Bs) * 2 + lr] = o[mb][i] + b2;
+          }
+      }
+    } else if (lr < M) {
       const int S = g.S;
       // bits per symbol of the slot's UEs by scalar loads (a per-lane load would wait as above)
       const int mu0 = ldc(&a.geo[tl.slot].m[0]), mu1 = ldc(&a.geo[tl.slot].m[1]);
@@ -519,7 +532,18 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
         o[mb] = mma<T>::run(OpTile<T>::frag(lds, wave * 16 * MLP_MB + mb * 16 + lr, c, lk), bf, o[mb]);
     }
     const int U = g.U, S = g.S;
-    if (lr < M) {
+    if (a.chest) {
+      // ReadoutChEst: row R = (s * 14 + t) * U + u is entry R of the slot's h layout
+      if (lr < 2 * g.B) {
+#pragma unroll
+        for (int mb = 0; mb < MLP_MB; ++mb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
+            if (r < tl.nrows) a.llr[(g.h_off + (int64_t)(tl.row0 + r) * g.B) * 2 + lr] = o[mb][i] + b2;
+          }
+      }
+    } else if (lr < M) {
 #pragma unroll
       for (int mb = 0; mb < MLP_MB; ++mb)
 #pragma unroll

@@ -169,6 +169,36 @@ __global__ void reduce_kernel(const double *partials, const unsigned long long *
   }
 }
 
+// Channel-estimate loss of the double readout: one thread per (s, t, u) row of the h layout, its
+// B complex entries (2B floats) of the slot.
+__global__ void mse_kernel(const SlotGeo *geo, const float *hest, const float *htrue, float *dhest, float gscale,
+                           double *partials, unsigned long long *pzero) {
+  const int slot = blockIdx.y;
+  const SlotGeo g = geo[slot];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  double loss = 0.0;
+  if (idx < g.S * 14 * g.U) {
+    const int64_t o = (g.h_off + (int64_t)idx * g.B) * 2;
+    for (int j = 0; j < 2 * g.B; ++j) {
+      const double e = (double)hest[o + j] - (double)htrue[o + j];
+      loss += e * e;
+      if (dhest) dhest[o + j] = (float)((double)gscale * e);
+    }
+  }
+  __shared__ double sl[256];
+  sl[threadIdx.x] = loss;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sl[threadIdx.x] += sl[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t pi = (int64_t)slot * gridDim.x + blockIdx.x;
+    partials[pi] = sl[0];
+    pzero[pi] = 0ull;
+  }
+}
+
 __global__ void adam_kernel(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                             float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,6 +231,15 @@ void launch_bce(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_ut
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, (const double *)partials,
                      (const unsigned long long *)perr, (int64_t)n_slots * n_part_per_slot, loss, nerr, inv_n);
   (void)max_ute;
+}
+
+void launch_mse(const SlotGeo *geo, int n_slots, const float *hest, const float *htrue, float *dhest, float gscale,
+                double *partials, int n_part, double *loss, double inv_n, hipStream_t st) {
+  unsigned long long *pz = reinterpret_cast<unsigned long long *>(partials + (int64_t)n_slots * n_part);
+  hipLaunchKernelGGL(mse_kernel, dim3(n_part, n_slots), dim3(256), 0, st, geo, hest, htrue, dhest, gscale, partials,
+                     pz);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, st, (const double *)partials,
+                     (const unsigned long long *)pz, (int64_t)n_slots * n_part, loss, nullptr, inv_n);
 }
 
 void launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,

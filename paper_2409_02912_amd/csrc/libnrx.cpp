@@ -269,9 +269,12 @@ struct GraphKey {
   uint64_t epoch;      // FP8 activation-scale version (scales are kernel arguments)
   int iters;           // CGNN iterations run
   int64_t llr_stride;  // > 0: a readout after every iteration
+  const void *hest;    // ReadoutChEst output or null
+  int64_t h_stride;
   bool operator<(const GraphKey &o) const {
-    return std::tie(plan, w, y, h, llr, ws, save, variants, epoch, iters, llr_stride) <
-           std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save, o.variants, o.epoch, o.iters, o.llr_stride);
+    return std::tie(plan, w, y, h, llr, ws, save, variants, epoch, iters, llr_stride, hest, h_stride) <
+           std::tie(o.plan, o.w, o.y, o.h, o.llr, o.ws, o.save, o.variants, o.epoch, o.iters, o.llr_stride, o.hest,
+                    o.h_stride);
   }
 };
 
@@ -293,6 +296,8 @@ struct nrx_model {
   std::vector<BlockLayer> blocks;
   std::vector<DenseLayer> mp;
   DenseLayer ro;
+  bool chest = false;                   // flags bit 1: second readout ReadoutChEst (double readout)
+  DenseLayer ro_ch;
   std::vector<PrepJob> jobs;
   int64_t prep_elems = 0, field_elems = 0, prep_total = 0;
   void *pinned_jobs = nullptr;
@@ -329,6 +334,7 @@ struct nrx_model {
   const Plan *saved_plan = nullptr;
   int saved_iters = 0;
   bool saved_multi = false;
+  bool saved_chest = false;
   std::mutex mu;
 };
 
@@ -361,7 +367,10 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
   if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
+  if ((c.flags & 2) && c.n_ant > 8)
+    return fail(NRX_ERR_SHAPE, "ReadoutChEst has 2 n_ant outputs, at most 16: n_ant %d > 8", c.n_ant);
   auto m = std::make_unique<nrx_model>();
+  m->chest = (c.flags & 2) != 0;
   m->cfg = c;
   m->tsize = c.precision == NRX_FP32 ? 4 : 2;   // FP8 models keep BF16 for everything but the block convs
   m->fp8 = c.precision == NRX_FP8;
@@ -394,6 +403,12 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   add_tensor(m.get(), "readout.b1", {d});
   add_tensor(m.get(), "readout.w2", {d, c.m_max});
   add_tensor(m.get(), "readout.b2", {c.m_max});
+  if (m->chest) {   // appended, so a weight vector without them is a prefix of this one
+    add_tensor(m.get(), "readout_ch.w1", {d, d});
+    add_tensor(m.get(), "readout_ch.b1", {d});
+    add_tensor(m.get(), "readout_ch.w2", {d, 2 * B});
+    add_tensor(m.get(), "readout_ch.b2", {2 * B});
+  }
 
   // weight preparation jobs
   const int KC = 64 / (int)m->tsize;
@@ -461,6 +476,16 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     m->jobs.push_back(j);
     m->prep_elems += j.count;
   }
+  if (m->chest) {
+    DenseLayer &L = m->ro_ch;
+    L.w1 = toff(m.get(), "readout_ch.w1"); L.b1 = toff(m.get(), "readout_ch.b1");
+    L.w2 = toff(m.get(), "readout_ch.w2"); L.b2 = toff(m.get(), "readout_ch.b2");
+    dense_job(L.w1, L.p1);
+    L.p2 = m->prep_elems;
+    PrepJob j{4, d, d, NRX_D / KC, 0, 2 * B, L.w2, L.p2, (int64_t)NRX_D * 16, d, 0};
+    m->jobs.push_back(j);
+    m->prep_elems += j.count;
+  }
   // backward jobs: flipped/transposed conv weights and transposed dense weights
   auto bjob = [&](int kind, int64_t src, int cin_total, int cin_first, int64_t count) {
     const int64_t off = m->bprep_elems;
@@ -479,6 +504,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     m->mp[r].t2 = bjob(5, m->mp[r].w2, d, 0, (int64_t)d * 128);
   }
   m->ro.t1 = bjob(5, m->ro.w1, d, 0, (int64_t)d * 128);
+  if (m->chest) m->ro_ch.t1 = bjob(5, m->ro_ch.w1, d, 0, (int64_t)d * 128);
   if (d < NRX_D) {
     pad_vec(m->conv_in.b, &m->conv_in.bpad);
     for (auto &L : m->blocks) {
@@ -489,6 +515,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     }
     for (auto &L : m->mp) { pad_vec(L.b1, &L.b1pad); pad_vec(L.b2, &L.b2pad); }
     pad_vec(m->ro.b1, &m->ro.b1pad);
+    if (m->chest) pad_vec(m->ro_ch.b1, &m->ro_ch.b1pad);
     for (auto &pv : pads) {
       *pv.second = m->field_elems;
       m->jobs.push_back(PrepJob{6, d, d, 0, 0, 0, pv.first, m->field_elems, NRX_D, d, 0});
@@ -555,6 +582,7 @@ struct FwdLayout {
   std::vector<size_t> stats;  // per block (training)
   std::vector<size_t> agg, m1;  // per round (inference: one agg)
   std::vector<size_t> q;      // readout hidden after each CGNN iteration (training)
+  std::vector<size_t> q_ch;   // the same for ReadoutChEst
   // backward (training layout only)
   size_t bjobs = 0, bprep = 0, zero = 0, dh = 0, dz = 0, dagg = 0, dmsg = 0, dm1 = 0, dr = 0;
   size_t wpart = 0, cpart = 0, lpart = 0, rpart = 0;
@@ -601,6 +629,8 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     for (int r = 0; r < R; ++r) { L.agg.push_back(o); o += act; }
     for (int r = 0; r < R; ++r) { L.m1.push_back(o); o += act; }
     for (size_t k = 0; k < iteration_ends(m->cfg).size(); ++k) { L.q.push_back(o); o += act; }
+    if (m->chest)
+      for (size_t k = 0; k < iteration_ends(m->cfg).size(); ++k) { L.q_ch.push_back(o); o += act; }
     L.bjobs = o; o = align256(o + sizeof(PrepJob) * m->bjobs.size());
     L.bprep = o; o = align256(o + (size_t)m->bprep_elems * ts);
     L.zero = o; o = align256(o + 128 * 4);
@@ -613,7 +643,8 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.wpart = o; o = align256(o + (size_t)2 * num_cu() * 128 * 128 * 4);   // partitions x jobs <= 2 blocks per CU
     L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
-    L.rpart = o; o = align256(o + iteration_ends(m->cfg).size() * BWD_GRID_MAX * 1032 * 4);
+    // dW2 partials: one set per readout for ReadoutLLRs, two (column groups) for ReadoutChEst
+    L.rpart = o; o = align256(o + (m->chest ? 3 : 1) * iteration_ends(m->cfg).size() * BWD_GRID_MAX * 1032 * 4);
   }
   L.total = o;
   return L;
@@ -655,7 +686,8 @@ nrx_status model_pinned(nrx_model *m) {
 
 template <typename T>
 nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *y, float *h_ls,
-                        float *llr, bool save, char *ws, hipStream_t st, int n_run = 0, int64_t llr_stride = 0) {
+                        float *llr, bool save, char *ws, hipStream_t st, int n_run = 0, int64_t llr_stride = 0,
+                        float *hest = nullptr, int64_t h_stride = 0) {
   nrx_status ps = model_pinned(m);
   if (ps != NRX_OK) return ps;
   if (plan_upload(const_cast<Plan *>(P), ws + L.meta, st) != NRX_OK) return NRX_ERR_HIP;
@@ -749,8 +781,25 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ra.n_tiles = (int)P->rt.size();
     ra.slot_done = last ? (unsigned int *)(ws + L.done) : nullptr;   // the pass completes at the last readout
     ra.stamps = last ? (unsigned long long *)(ws + L.stamps) : nullptr;
-    ProfMark pm(m, NRX_K_READOUT, st);
-    launch_readout<T>(ra, grid_mlp, st);
+    {
+      ProfMark pm(m, NRX_K_READOUT, st);
+      launch_readout<T>(ra, grid_mlp, st);
+    }
+    if (hest) {   // ReadoutChEst on the same state (double readout)
+      MlpArgs<T> ca = ra;
+      ca.w1 = wprep + m->ro_ch.p1;
+      ca.b1 = vec(m->ro_ch.b1, m->ro_ch.b1pad);
+      ca.b2 = w + m->ro_ch.b2;
+      ca.w2 = wprep + m->ro_ch.p2;
+      ca.save_m1 = save ? buf(L.q_ch[k]) : nullptr;
+      ca.llr = hest + (int64_t)k * h_stride;
+      ca.m_max = 2 * m->cfg.n_ant;
+      ca.chest = 1;
+      ca.slot_done = nullptr;
+      ca.stamps = nullptr;
+      ProfMark pm(m, NRX_K_READOUT, st);
+      launch_readout<T>(ca, grid_mlp, st);
+    }
   };
   for (int i = 0; i < c_run; ++i) {
     const BlockLayer &B = m->blocks[i];
@@ -841,7 +890,7 @@ extern "C" size_t nrx_workspace_bytes(nrx_model *m, const nrx_slot_desc *slots, 
 namespace {
 nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *y,
                          float *h_ls, float *llr, int64_t llr_stride, int32_t save_acts, void *ws, size_t ws_bytes,
-                         hipStream_t st) {
+                         hipStream_t st, float *hest = nullptr, int64_t h_stride = 0) {
   if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
   Plan *P;
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
@@ -853,14 +902,18 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
   const int iters = m->n_iter > 0 ? m->n_iter : (int)iteration_ends(m->cfg).size();
   auto run = [&](hipStream_t s2) {
     if (m->cfg.precision == NRX_FP32)
-      return forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride);
-    return forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride);
+      return forward_impl<float>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride, hest,
+                                 h_stride);
+    return forward_impl<bf16_t>(m, P, L, w, y, h_ls, llr, save_acts != 0, (char *)ws, s2, iters, llr_stride, hest,
+                                h_stride);
   };
   if ((m->cfg.flags & 1) && !m->profile) {
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
     uint64_t vs = 0;
     for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (4 * c);
-    s = graph_forward(m, P, GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride},
+    s = graph_forward(m, P,
+                      GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride, hest,
+                               h_stride},
                       run, st);
   } else {
     s = run(st);
@@ -871,6 +924,7 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
     m->saved_plan = P;
     m->saved_iters = iters;
     m->saved_multi = llr_stride > 0;
+    m->saved_chest = hest != nullptr;
   }
   return s;
 }
@@ -887,6 +941,17 @@ extern "C" nrx_status nrx_forward_iters(nrx_model *m, const float *w, const nrx_
                                         void *ws, size_t ws_bytes, hipStream_t st) {
   if (llr_stride <= 0) return fail(NRX_ERR_INVALID, "llr_stride must be positive");
   return forward_entry(m, w, slots, n, y, h_ls, llr, llr_stride, save_acts, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_forward_chest(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                        const float *y, float *h_ls, float *llr, int64_t llr_stride, float *h_est,
+                                        int64_t h_stride, int32_t save_acts, void *ws, size_t ws_bytes,
+                                        hipStream_t st) {
+  if (!m || !h_est) return fail(NRX_ERR_INVALID, "null argument");
+  if (!m->chest) return fail(NRX_ERR_INVALID, "the model has no ReadoutChEst (config flags bit 1)");
+  if (llr_stride < 0 || (llr_stride > 0 && h_stride <= 0))
+    return fail(NRX_ERR_INVALID, "llr_stride must be >= 0, and h_stride positive with per-iteration readouts");
+  return forward_entry(m, w, slots, n, y, h_ls, llr, llr_stride, save_acts, ws, ws_bytes, st, h_est, h_stride);
 }
 
 extern "C" nrx_status nrx_set_iterations(nrx_model *m, int32_t n_iter) {
@@ -1100,7 +1165,8 @@ namespace {
 
 template <typename T>
 nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const float *w, const float *dllr,
-                         float *dw, char *ws, hipStream_t st, int n_run, int64_t llr_stride) {
+                         float *dw, char *ws, hipStream_t st, int n_run, int64_t llr_stride,
+                         const float *dhest = nullptr, int64_t h_stride = 0) {
   {
     std::lock_guard<std::mutex> lk(m->mu);
     if (!m->pinned_bjobs) {
@@ -1178,6 +1244,10 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   const int c_run = ends[n_run - 1];
   const int n_ro = llr_stride > 0 ? n_run : 1;
   int ro_done = 0;
+  // dW2 partial sets of ReadoutChEst column group g, after those of ReadoutLLRs
+  auto chest_part = [&](int g) {
+    return rpart + (int64_t)(1 + g) * (int64_t)ends.size() * BWD_GRID_MAX * 1032;
+  };
   auto readout_back = [&](int k, int blocks_done) {
     const bool acc = ro_done > 0;
     RoBwdArgs<T> a{};
@@ -1196,6 +1266,25 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     launch_readout_bwd<T>(a, grid_mlp, st);
     wgrad(buf(L.h[blocks_done]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro.w1, acc);
     bias(buf(L.dr), m->ro.b1, -1, 0, 0, acc);
+    if (dhest) {
+      // ReadoutChEst on the same state: its 2B outputs in groups of 8 columns, adding to dh
+      RoBwdArgs<T> c = a;
+      c.dllr = dhest + (int64_t)k * h_stride;
+      c.q = buf(L.q_ch[k]);
+      c.w2 = w + m->ro_ch.w2;
+      c.w1t = bp + m->ro_ch.t1;
+      c.accumulate = 1;
+      c.m_max = 2 * m->cfg.n_ant;
+      c.chest = 1;
+      for (int g = 0; 8 * g < c.m_max; ++g) {
+        c.j0 = 8 * g;
+        c.acc_dr = g > 0;
+        c.part = chest_part(g) + (int64_t)ro_done * grid_mlp * 1032;
+        launch_readout_bwd<T>(c, grid_mlp, st);
+      }
+      wgrad(buf(L.h[blocks_done]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro_ch.w1, acc);
+      bias(buf(L.dr), m->ro_ch.b1, -1, 0, 0, acc);
+    }
     ++ro_done;
   };
   readout_back(n_ro - 1, c_run);
@@ -1244,6 +1333,14 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     }
   }
   launch_readout_w2_reduce(rpart, n_ro * grid_mlp, m->cfg.m_max, m->ro.w2, m->ro.b2, dw, st);
+  if (dhest) {
+    for (int g = 0; 8 * g < 2 * m->cfg.n_ant; ++g)
+      launch_readout_w2_reduce(chest_part(g), n_ro * grid_mlp, 2 * m->cfg.n_ant, m->ro_ch.w2, m->ro_ch.b2, dw, st,
+                               8 * g);
+  } else if (m->chest) {
+    // no channel-estimate loss: ReadoutChEst gets a zero gradient (its tensors close the vector)
+    HIPCHK(hipMemsetAsync(dw + m->ro_ch.w1, 0, (size_t)(m->n_w - m->ro_ch.w1) * sizeof(float), st));
+  }
   // StateInit (no data gradient needed)
   const int B4 = 4 * m->cfg.n_ant;
   wgrad(buf(L.X), m->cx, nullptr, 0, dh, true, B4, B4 + 2, m->conv_in.w);
@@ -1256,7 +1353,8 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
 
 namespace {
 nrx_status backward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n, const float *dllr,
-                          int64_t llr_stride, float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
+                          int64_t llr_stride, float *dw, void *ws, size_t ws_bytes, hipStream_t st,
+                          const float *dhest = nullptr, int64_t h_stride = 0) {
   if (!m || !w || !dllr || !dw || !ws) return fail(NRX_ERR_INVALID, "null argument");
   Plan *P;
   nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
@@ -1269,12 +1367,14 @@ nrx_status backward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slo
     if (m->saved_multi != (llr_stride > 0))
       return fail(NRX_ERR_INVALID, "the saved forward %s per-iteration readouts",
                   m->saved_multi ? "has" : "has no");
+    if (dhest && !m->saved_chest) return fail(NRX_ERR_INVALID, "the saved forward ran no ReadoutChEst");
     iters = m->saved_iters;
   }
   const FwdLayout L = fwd_layout(m, P, true);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
-  if (m->cfg.precision == NRX_FP32) return backward_impl<float>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride);
-  return backward_impl<bf16_t>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride);
+  if (m->cfg.precision == NRX_FP32)
+    return backward_impl<float>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride, dhest, h_stride);
+  return backward_impl<bf16_t>(m, P, L, w, dllr, dw, (char *)ws, st, iters, llr_stride, dhest, h_stride);
 }
 }  // namespace
 
@@ -1288,6 +1388,16 @@ extern "C" nrx_status nrx_backward_iters(nrx_model *m, const float *w, const nrx
                                          hipStream_t st) {
   if (llr_stride <= 0) return fail(NRX_ERR_INVALID, "llr_stride must be positive");
   return backward_entry(m, w, slots, n, dllr, llr_stride, dw, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_backward_chest(nrx_model *m, const float *w, const nrx_slot_desc *slots, int32_t n,
+                                         const float *dllr, int64_t llr_stride, const float *dh_est, int64_t h_stride,
+                                         float *dw, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!m || !dh_est) return fail(NRX_ERR_INVALID, "null argument");
+  if (!m->chest) return fail(NRX_ERR_INVALID, "the model has no ReadoutChEst (config flags bit 1)");
+  if (llr_stride < 0 || (llr_stride > 0 && h_stride <= 0))
+    return fail(NRX_ERR_INVALID, "llr_stride must be >= 0, and h_stride positive with per-iteration readouts");
+  return backward_entry(m, w, slots, n, dllr, llr_stride, dw, ws, ws_bytes, st, dh_est, h_stride);
 }
 
 // --------------------------------------------------------- model-free calls --
@@ -1423,6 +1533,33 @@ extern "C" nrx_status nrx_bce(const nrx_slot_desc *slots, int32_t n, int32_t m_m
   const Dev D = dev_tables(P, w);
   launch_bce(D.geo, nullptr, P->n, P->max_ute, m_max, llr, bits, dllr, (double *)(w + align256(P->meta_bytes)),
              (int)nb, loss, nerr, 1.0 / (double)P->n_data_bits, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" size_t nrx_mse_workspace_bytes(const nrx_slot_desc *slots, int32_t n) {
+  Plan *P;
+  if (get_plan(slots, n, 16, 8, 0, &P) != NRX_OK) return 0;
+  const int64_t nb = (P->max_ute + 255) / 256;
+  return align256(P->meta_bytes) + align256((size_t)n * nb * 16);
+}
+
+extern "C" nrx_status nrx_mse(const nrx_slot_desc *slots, int32_t n, const float *h_est, const float *h_true,
+                              float gamma, float *dh_est, double *loss, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!h_est || !h_true || !ws) return fail(NRX_ERR_INVALID, "null argument");
+  Plan *P;
+  nrx_status s = get_plan(slots, n, 16, 8, 0, &P);
+  if (s != NRX_OK) return s;
+  const int64_t nb = (P->max_ute + 255) / 256;
+  const size_t need = align256(P->meta_bytes) + align256((size_t)n * nb * 16);
+  if (ws_bytes < need) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  int64_t n_c = 0;   // complex entries of the batch
+  for (auto &g : P->geo) n_c += (int64_t)g.S * 14 * g.U * g.B;
+  char *w = (char *)ws;
+  if (plan_upload(P, w, st) != NRX_OK) return NRX_ERR_HIP;
+  const Dev D = dev_tables(P, w);
+  launch_mse(D.geo, P->n, h_est, h_true, dh_est, (float)(2.0 * (double)gamma / (double)n_c),
+             (double *)(w + align256(P->meta_bytes)), (int)nb, loss, 1.0 / (double)n_c, st);
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }

@@ -69,6 +69,10 @@ _SIGS = {
     "nrx_set_iterations": (_i32, [_vp, _i32]),
     "nrx_forward_iters": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _i64, _i32, _vp, _sz, _vp]),
     "nrx_backward_iters": (_i32, [_vp, _vp, _DESC, _i32, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "nrx_forward_chest": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _i64, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "nrx_backward_chest": (_i32, [_vp, _vp, _DESC, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "nrx_mse_workspace_bytes": (_sz, [_DESC, _i32]),
+    "nrx_mse": (_i32, [_DESC, _i32, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _sz, _vp]),
     "nrx_bce_workspace_bytes": (_sz, [_DESC, _i32, _i32]),
     "nrx_bce": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nrx_adam": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _f, _f, _f, _f, _vp]),
@@ -218,6 +222,32 @@ def nrx_backward_iters(model, w, slots, dllr, llr_stride, dw, ws, stream=None):
     arr, n = _descs(slots)
     _check(_lib.nrx_backward_iters(model, _ptr(w), arr, n, _ptr(dllr), int(llr_stride), _ptr(dw), _ptr(ws),
                                    ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_forward_chest(model, w, slots, y, llr, h_est, ws, llr_stride=0, h_stride=0, h_ls=None, save_acts=False,
+                      stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_forward_chest(model, _ptr(w), arr, n, _ptr(y), _ptr(h_ls), _ptr(llr), int(llr_stride),
+                                  _ptr(h_est), int(h_stride), int(save_acts), _ptr(ws),
+                                  ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_backward_chest(model, w, slots, dllr, dh_est, dw, ws, llr_stride=0, h_stride=0, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_backward_chest(model, _ptr(w), arr, n, _ptr(dllr), int(llr_stride), _ptr(dh_est),
+                                   int(h_stride), _ptr(dw), _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream(stream)))
+
+
+def nrx_mse_workspace_bytes(slots):
+    arr, n = _descs(slots)
+    return int(_lib.nrx_mse_workspace_bytes(arr, n))
+
+
+def nrx_mse(slots, h_est, h_true, gamma, dh_est, loss, ws, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_mse(arr, n, _ptr(h_est), _ptr(h_true), float(gamma), _ptr(dh_est), _ptr(loss), _ptr(ws),
+                        ws.numel() * ws.element_size(), _stream(stream)))
 
 
 def nrx_bce_workspace_bytes(slots, m_max):

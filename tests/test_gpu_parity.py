@@ -211,6 +211,8 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4, all_iters=False):
     sign = np.where(np.arange(net.d) % 2 == 0, 1.0, -1.0)
     units = [(f"blk{i}", f"blk{i}.ln.b", 1) for i in range(net.C)] + \
             [(f"mp{r}", f"mp{r}.b1", 1) for r in range(net.R)] + [("readout", "readout.b1", 1)]
+    if getattr(net, "chest", False):
+        units.append(("readout_ch", "readout_ch.b1", 1))
     margin = 0.0
     for it in range(iters + 1):
         W = cgnn.unflatten(w, net)
@@ -221,6 +223,8 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4, all_iters=False):
             for k, _, j in units:
                 if k == "readout":
                     pre[k] += [rc[1].reshape(-1, net.d) for _, rc in cache["readouts"]]
+                elif k == "readout_ch":
+                    pre[k] += [cc[1].reshape(-1, net.d) for cc in cache["chest"]]
                 else:
                     pre[k].append(cache[k][j].reshape(-1, net.d))
         margin = np.inf
@@ -300,6 +304,136 @@ def test_nrx_backward_fp32_matches_oracle(variant):
 def test_nrx_backward_multi_loss_fp32_matches_oracle():
     # the multi-loss gradient (Sec. II-B): readouts after both CGNN iterations, one dllr each
     _grad_case(0, 1e-4, 0.9999999, variant=7, multi=True)
+
+
+CHEST_SHAPES = [dict(n_prb=4, n_ant=8, n_ue=2, bits=[4, 2], slot_number=1),
+                dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 2], slot_number=2)]
+
+
+def _pack_h(parts):
+    """Per-slot complex [S, T, U, B] arrays -> the flat interleaved h layout (fp32)."""
+    c = np.concatenate([p.reshape(-1) for p in parts])
+    return np.stack([c.real, c.imag], axis=-1).reshape(-1).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_chest_forward_matches_oracle(prec, tol):
+    """Double readout (Sec. II-A): ReadoutChEst after both CGNN iterations, 16 outputs for the 8-antenna network,
+    a 4-antenna slot using the first 8; LLRs of the same pass unchanged."""
+    net = cgnn.NetConfig(8, 128, 4, 2, 4, chest=True)
+    m_max = 4
+    log(f"chest forward: prec={prec} C={net.C} R={net.R}")
+    ref_slots = oracle_batch(CHEST_SHAPES, sim_cfg_oracle(SIMCFG), 43, 0, m_max)
+    w = synth.he_weights(cgnn.layout(net), 43, perturb=True)
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    ref_l, ref_h = [], []
+    for r in ref_slots:
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        ls, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True, all_iters=True)
+        ref_l.append(ls)
+        ref_h.append(cache["hests"])
+    descs, sz = L.make_slots(CHEST_SHAPES, m_max)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, prec, flags=2)
+    try:
+        assert L.nrx_weight_count(model) == len(w)
+        y = _upload_batch(CHEST_SHAPES, ref_slots)
+        ls_, hs_ = sz["llr"], 2 * sz["h"]
+        llr = torch.zeros(2 * ls_, dtype=torch.float32, device="cuda")
+        hest = torch.full((2 * hs_,), float("nan"), dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        L.nrx_forward_chest(model, dev(w), descs, y, llr, hest, ws, llr_stride=ls_, h_stride=hs_)
+        torch.cuda.synchronize()
+        gl, gh = llr.cpu().numpy().astype(np.float64), hest.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(gh)), "channel-estimate entries left unwritten"
+        for k in range(2):
+            el = rel_err(np.concatenate([x.reshape(-1) for x in split_llr(gl[k * ls_:(k + 1) * ls_], CHEST_SHAPES,
+                                                                        m_max)]),
+                         np.concatenate([ref_l[i][k].reshape(-1) for i in range(len(ref_slots))]))
+            hk = gh[k * hs_:(k + 1) * hs_]
+            eh = rel_err(hk, _pack_h([ref_h[i][k] for i in range(len(ref_slots))]).astype(np.float64))
+            log(f"  readout {k}: LLR relative error {el:.2e}, channel estimate {eh:.2e}")
+            assert el <= tol and eh <= tol
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_nrx_backward_chest_fp32_matches_oracle():
+    """Double-readout gradient (Sec. II-B): BCE-side dllr and channel-side dh_est after both CGNN iterations."""
+    net = cgnn.NetConfig(8, 128, 4, 2, 4, chest=True)
+    m_max = 4
+    log(f"chest backward: fp32 C={net.C} R={net.R}")
+    ref_slots = oracle_batch(CHEST_SHAPES, sim_cfg_oracle(SIMCFG), 47, 0, m_max)
+    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), 47, perturb=True), net, ref_slots,
+                                 all_iters=True)
+    log(f"  smallest |ReLU input| / layer RMS {margin:.2e}")
+    assert margin > 1e-4
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    rng = np.random.default_rng(47)
+    descs, sz = L.make_slots(CHEST_SHAPES, m_max)
+    ls_, hs_ = sz["llr"], 2 * sz["h"]
+    dllr_np = rng.standard_normal(2 * ls_).astype(np.float32)
+    dh_np = rng.standard_normal(2 * hs_).astype(np.float32)
+    dl = [split_llr(dllr_np[k * ls_:(k + 1) * ls_].astype(np.float64), CHEST_SHAPES, m_max) for k in range(2)]
+    dhc = [split_h(dh_np[k * hs_:(k + 1) * hs_].astype(np.float64).view(np.complex128), CHEST_SHAPES)
+           for k in range(2)]
+    G = {k: np.zeros_like(v) for k, v in W.items()}
+    for i, r in enumerate(ref_slots):
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True, all_iters=True)
+        g = cgnn.backward(W, net, cache, [dl[k][i] for k in range(2)], [dhc[k][i] for k in range(2)])
+        for k in G:
+            G[k] += g[k]
+    ref = cgnn.flatten(G, net)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, 0, flags=2)
+    try:
+        y = _upload_batch(CHEST_SHAPES, ref_slots)
+        llr = torch.zeros(2 * ls_, dtype=torch.float32, device="cuda")
+        hest = torch.zeros(2 * hs_, dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
+        dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
+        wt = dev(w)
+        L.set_all_conv_variants(model, 7)
+        L.nrx_forward_chest(model, wt, descs, y, llr, hest, ws, llr_stride=ls_, h_stride=hs_, save_acts=True)
+        L.nrx_backward_chest(model, wt, descs, dev(dllr_np), dev(dh_np), dw, ws, llr_stride=ls_, h_stride=hs_)
+        torch.cuda.synchronize()
+        got = dw.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got)), "gradient entries left unwritten"
+        off = 0
+        for name, shape in cgnn.layout(net):
+            n = int(np.prod(shape))
+            et = rel_err(got[off:off + n], ref[off:off + n])
+            assert et <= 1e-4, f"{name}: relative error {et:.3e}"
+            off += n
+        e = rel_err(got, ref)
+        log(f"  gradient relative error (all weights) {e:.2e}")
+        assert e <= 1e-4
+        # the plain multi-loss backward after this forward leaves the ReadoutChEst gradient zero
+        L.nrx_backward_iters(model, wt, descs, dev(dllr_np), ls_, dw, ws)
+        torch.cuda.synchronize()
+        g2 = dw.cpu().numpy()
+        n_ch = sum(int(np.prod(sh)) for nm, sh in cgnn.layout(net) if nm.startswith("readout_ch"))
+        assert np.all(g2[len(w) - n_ch:] == 0) and np.all(np.isfinite(g2))
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_nrx_mse_matches_oracle():
+    """Channel-estimate loss of the double readout (Sec. II-B): MSE over the batch and its gamma-scaled gradient."""
+    log("nrx_mse: 2 slots")
+    descs, sz = L.make_slots(CHEST_SHAPES, 4)
+    rng = np.random.default_rng(5)
+    he = rng.standard_normal(2 * sz["h"]).astype(np.float32)
+    ht = rng.standard_normal(2 * sz["h"]).astype(np.float32)
+    hec = split_h(he.astype(np.float64).view(np.complex128), CHEST_SHAPES)
+    htc = split_h(ht.astype(np.float64).view(np.complex128), CHEST_SHAPES)
+    mse, g = cgnn.mse_grad(hec, htc, 0.25)
+    dh = torch.full((2 * sz["h"],), float("nan"), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ws = ws_tensor(L.nrx_mse_workspace_bytes(descs))
+    L.nrx_mse(descs, dev(he), dev(ht), 0.25, dh, loss, ws)
+    torch.cuda.synchronize()
+    assert abs(float(loss.item()) - mse) <= 1e-12 * mse
+    assert rel_err(dh.cpu().numpy().astype(np.float64), _pack_h(g).astype(np.float64)) <= 1e-6
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
