@@ -45,7 +45,7 @@ class SimConfig:
 
 
 class SlotDesc:
-    def __init__(self, n_prb, n_ant, n_ue, bits_per_sym, slot_number=0, n_id=0, n_scid=0):
+    def __init__(self, n_prb, n_ant, n_ue, bits_per_sym, slot_number=0, n_id=0, n_scid=0, snr_offset_db=0.0):
         self.n_prb = n_prb
         self.n_ant = n_ant
         self.n_ue = n_ue
@@ -53,6 +53,7 @@ class SlotDesc:
         self.slot_number = slot_number
         self.n_id = n_id
         self.n_scid = n_scid
+        self.snr_offset_db = snr_offset_db   # added to the drawn SNR (mixed-MCS training offsets, Sec. III-A)
 
     @property
     def n_sc(self):
@@ -146,6 +147,7 @@ def noise(seed, batch_index, slot, desc, n0):
 def simulate_slot(seed, batch_index, slot, cfg, desc, m_max):
     """Returns dict with y [S,T,B], h [S,T,U,B], bits [U,n_data,m_max], snr_db, n0."""
     snr_db, _ = slot_params(seed, batch_index, slot, cfg, desc.n_ue)
+    snr_db += desc.snr_offset_db
     n0 = 10.0 ** (-snr_db / 10.0)
     H = channel(seed, batch_index, slot, cfg, desc)
     b = bits(seed, batch_index, slot, desc, m_max)

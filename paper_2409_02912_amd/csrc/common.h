@@ -174,7 +174,7 @@ struct SlotGeo {
   int32_t m[4];       // bits per symbol of each UE
   int32_t slot_number, n_id, n_scid;
   float n0;
-  int32_t pad;
+  float snr_off;      // slot_sim: dB added to the drawn SNR
   int64_t row_base;   // first activation row of the slot
   int64_t y_off;      // complex elements
   int64_t h_off;      // complex elements

@@ -54,7 +54,7 @@ __global__ void sim_params_kernel(SimParams p, const SlotGeo *geo, int n_slots, 
                                   float *n0_ws) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= n_slots) return;
-  const float snr = p.snr_lo + (p.snr_hi - p.snr_lo) * unif(draw(p, slot, 4, 0).x);
+  const float snr = p.snr_lo + (p.snr_hi - p.snr_lo) * unif(draw(p, slot, 4, 0).x) + geo[slot].snr_off;
   const float nv = powf(10.f, -snr / 10.f);
   if (snr_db) snr_db[slot] = snr;
   if (n0) n0[slot] = nv;

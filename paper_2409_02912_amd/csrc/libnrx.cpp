@@ -135,6 +135,7 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
       return fail(NRX_ERR_SHAPE, "slot %d: DMRS scrambling parameters out of range", i);
     if (s.y_offset < 0 || s.h_offset < 0 || s.llr_offset < 0 || s.bits_offset < 0)
       return fail(NRX_ERR_INVALID, "slot %d: negative offset", i);
+    if (!(std::fabs(s.snr_offset_db) <= 60.f)) return fail(NRX_ERR_SHAPE, "slot %d: snr_offset_db outside -60..60", i);
   }
   uint64_t key = fnv(d, sizeof(nrx_slot_desc) * (size_t)n);
   key = fnv(&n, sizeof n, key);
@@ -157,6 +158,7 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
     g.n_id = s.n_id;
     g.n_scid = s.n_scid;
     g.n0 = s.n0;
+    g.snr_off = s.snr_offset_db;
     g.row_base = row;
     g.y_off = s.y_offset;
     g.h_off = s.h_offset;

@@ -33,7 +33,7 @@ class SlotDesc(ctypes.Structure):
     _fields_ = [("n_prb", ctypes.c_int32), ("n_ant", ctypes.c_int32), ("n_ue", ctypes.c_int32),
                 ("bits_per_sym", ctypes.c_int32 * 4), ("slot_number", ctypes.c_int32),
                 ("n_id", ctypes.c_int32), ("n_scid", ctypes.c_int32), ("n0", ctypes.c_float),
-                ("reserved", ctypes.c_int32), ("y_offset", ctypes.c_int64), ("h_offset", ctypes.c_int64),
+                ("snr_offset_db", ctypes.c_float), ("y_offset", ctypes.c_int64), ("h_offset", ctypes.c_int64),
                 ("llr_offset", ctypes.c_int64), ("bits_offset", ctypes.c_int64)]
 
 
@@ -126,7 +126,7 @@ def _descs(slots):
 
 def make_slots(shapes, m_max, model_b=None):
     """Builds packed descriptors. shapes: list of dicts with n_prb, n_ant, n_ue, bits (list), optional
-    slot_number, n_id, n_scid, n0.  Returns (descs, sizes) with the element counts of y, h, llr, bits."""
+    slot_number, n_id, n_scid, n0, snr_offset_db.  Returns (descs, sizes) with the element counts of y, h, llr, bits."""
     out = []
     yo = ho = lo = bo = 0
     for i, sh in enumerate(shapes):
@@ -141,6 +141,7 @@ def make_slots(shapes, m_max, model_b=None):
         d.n_id = sh.get("n_id", 0)
         d.n_scid = sh.get("n_scid", 0)
         d.n0 = sh.get("n0", 0.0)
+        d.snr_offset_db = sh.get("snr_offset_db", 0.0)
         d.y_offset, d.h_offset, d.llr_offset, d.bits_offset = yo, ho, lo, bo
         yo += S * 14 * B
         ho += S * 14 * U * B

@@ -30,6 +30,9 @@ WORKLOADS = {
     # small training workload (learning test: trains in about a minute)
     "t": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
               snr=(0.0, 15.0), d=128, n_blocks=2, n_rounds=1),
+    # the small workload for mixed-MCS training: QPSK, 16-QAM and 64-QAM UEs (LLRs masked to m_u), up to 2 UEs
+    "tm": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=6, mcs=[2, 4, 6], n_taps=12, decay_ns=487.42, doppler=0.0,
+               rho=0.0, snr=(0.0, 15.0), d=128, n_blocks=2, n_rounds=1),
     # the small training workload with two CGNN iterations (multi-loss and depth control)
     "t2": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
                snr=(0.0, 15.0), d=128, n_blocks=4, n_rounds=2),
@@ -68,9 +71,36 @@ def ragged_shapes(n_slots, seed, max_prb=273, ants=(4, 8, 16), mods=(2, 4, 6, 8)
     return out
 
 
-def uniform_shapes(w, n_slots=None, n_prb=None):
+def uniform_shapes(w, n_slots=None, n_prb=None, bits=None):
+    """The workload's batch of identical slots; bits overrides the modulation (bits per symbol) of every UE."""
     n = n_slots or w["n_slots"]
     if w.get("ragged"):
         return ragged_shapes(n, 0, max_prb=n_prb or w["n_prb"])
-    return [dict(n_prb=n_prb or w["n_prb"], n_ant=w["n_ant"], n_ue=w["n_ue"], bits=[w["m"]] * w["n_ue"],
+    return [dict(n_prb=n_prb or w["n_prb"], n_ant=w["n_ant"], n_ue=w["n_ue"], bits=[bits or w["m"]] * w["n_ue"],
                  slot_number=i % 20) for i in range(n)]
+
+
+# Mixed-MCS training (Sec. III-A with the U_A draw of Sec. II-B).  Readings where the paper gives no numbers:
+#   * U_A, the number of active UEs of a batch, is drawn from the discrete triangular law P(U_A = k) = 2k / (U(U+1))
+#     on 1..U (more UEs more likely);
+#   * every active UE of every slot draws its modulation iid and uniform from the workload's set;
+#   * the SNR offset of a slot is the mean over its UEs of a per-modulation offset (roughly the SNR gap between
+#     Gray-QAM orders at equal uncoded BER, 16-QAM = 0 dB) plus a fixed step per UE beyond the first.
+MOD_SNR_OFFSET_DB = {2: -6.0, 4: 0.0, 6: 6.0, 8: 12.0}
+UE_SNR_STEP_DB = 1.0
+
+
+def mixed_mcs_shapes(w, rng, n_slots=None, n_prb=None):
+    """One training batch of the mixed-MCS scheme: U_A active UEs for the whole batch (triangular), an iid
+    modulation per UE and slot from w["mcs"], and the per-slot SNR offset."""
+    n = n_slots or w["n_slots"]
+    U = w["n_ue"]
+    k = np.arange(1, U + 1)
+    ua = int(rng.choice(k, p=2.0 * k / (U * (U + 1))))
+    out = []
+    for i in range(n):
+        bits = [int(b) for b in rng.choice(w["mcs"], size=ua)]
+        off = float(np.mean([MOD_SNR_OFFSET_DB[b] for b in bits])) + UE_SNR_STEP_DB * (ua - 1)
+        out.append(dict(n_prb=n_prb or w["n_prb"], n_ant=w["n_ant"], n_ue=ua, bits=bits, slot_number=i % 20,
+                        snr_offset_db=off))
+    return out

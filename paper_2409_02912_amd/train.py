@@ -36,7 +36,7 @@ def weight_layout(model):
 
 class Trainer:
     def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None,
-                 multi_loss=False, data_batches=0, gamma=0.0):
+                 multi_loss=False, data_batches=0, gamma=0.0, mixed_pool=0):
         import torch
         self.torch = torch
         self.w = w
@@ -44,14 +44,25 @@ class Trainer:
         self.lr = lr
         self.data_batches = data_batches   # > 0: a finite training set of this many batches, cycled
         self.m_max = w["m"]
-        self.shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
-        self.descs, sz = L.make_slots(self.shapes, self.m_max)
+        if mixed_pool > 0:
+            # mixed-MCS training (Sec. III-A): a pool of batches with random U_A, per-UE modulations and SNR
+            # offsets, drawn once (each batch shape is planned once) and cycled; the slots are fresh every step
+            rng = np.random.default_rng(seed + 7919)
+            pool = [synth.mixed_mcs_shapes(w, rng, n_slots=batch, n_prb=n_prb) for _ in range(mixed_pool)]
+        else:
+            pool = [synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)]
+        self.pool = [(shapes,) + L.make_slots(shapes, self.m_max) for shapes in pool]
+        sz = {k: max(e[2][k] for e in self.pool) for k in ("y", "h", "llr", "bits")}
+        self.shapes, self.descs = self.pool[0][0], self.pool[0][1]
         snr = snr or w["snr"]
         self.sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
                                 rho=w["rho"], snr_db_lo=snr[0], snr_db_hi=snr[1])
         self.gamma = float(gamma)
         self.model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], self.m_max, precision,
                                         flags=2 if self.gamma > 0 else 0)
+
+        def pool_max(f):
+            return max(f(e[1]) for e in self.pool)
         dev = "cuda"
         self.params = torch.from_numpy(synth.he_weights(weight_layout(self.model), seed)).to(dev)
         self.m = torch.zeros_like(self.params)
@@ -75,13 +86,16 @@ class Trainer:
             self.hest = torch.empty(self.n_ro * self.hstride, dtype=torch.float32, device=dev)
             self.dhest = torch.empty_like(self.hest)
             self.mses = torch.zeros(self.n_ro, dtype=torch.float64, device=dev)
-            self.mws = torch.empty(L.nrx_mse_workspace_bytes(self.descs), dtype=torch.uint8, device=dev)
-        self.ws = torch.empty(L.nrx_workspace_bytes(self.model, self.descs, save_acts=True), dtype=torch.uint8,
-                              device=dev)
-        self.sws = torch.empty(L.slot_sim_workspace_bytes(self.sim, self.descs), dtype=torch.uint8, device=dev)
-        self.bws = torch.empty(L.nrx_bce_workspace_bytes(self.descs, self.m_max), dtype=torch.uint8, device=dev)
+            self.mws = torch.empty(pool_max(L.nrx_mse_workspace_bytes), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(pool_max(lambda d: L.nrx_workspace_bytes(self.model, d, save_acts=True)),
+                              dtype=torch.uint8, device=dev)
+        self.sws = torch.empty(pool_max(lambda d: L.slot_sim_workspace_bytes(self.sim, d)), dtype=torch.uint8,
+                               device=dev)
+        self.bws = torch.empty(pool_max(lambda d: L.nrx_bce_workspace_bytes(d, self.m_max)), dtype=torch.uint8,
+                               device=dev)
         self.step = 0
-        self.n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in self.shapes)
+        self.pool_bits = [sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in e[0]) for e in self.pool]
+        self.n_bits = self.pool_bits[0]
         # pick the convolution tile shapes for this batch (forward timing only)
         L.slot_sim(self.sim, self.seed, 0, self.descs, self.m_max, self.y, self.sws, bits=self.bits)
         L.nrx_autotune(self.model, self.params, self.descs, self.y, self.llr[:self.stride], self.ws)
@@ -106,6 +120,9 @@ class Trainer:
 
     def train_step(self):
         bi = self.step % self.data_batches if self.data_batches else self.step
+        if len(self.pool) > 1:
+            p = bi % len(self.pool)
+            self.shapes, self.descs, self.n_bits = self.pool[p][0], self.pool[p][1], self.pool_bits[p]
         L.slot_sim(self.sim, self.seed, bi, self.descs, self.m_max, self.y, self.sws, bits=self.bits,
                    h_true=self.h_true if self.gamma > 0 else None)
         if self.gamma > 0:
@@ -141,12 +158,13 @@ class Trainer:
         L.nrx_model_destroy(self.model)
 
 
-def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, n_iter=0):
+def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, n_iter=0, bits=None):
     """BER of the NRX and of LS + LMMSE on held-out slots (a seed not used in training) at a fixed SNR;
-    n_iter > 0 runs the NRX at that many CGNN iterations."""
+    n_iter > 0 runs the NRX at that many CGNN iterations; bits sets every UE's modulation (default the workload's,
+    which is also the network's LLR count m_max: lower orders read the first bits outputs, Sec. III)."""
     import torch
     m_max = w["m"]
-    shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb)
+    shapes = synth.uniform_shapes(w, n_slots=batch or w["n_slots"], n_prb=n_prb, bits=bits)
     descs, sz = L.make_slots(shapes, m_max)
     sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
                        snr_db_lo=snr_db, snr_db_hi=snr_db)
@@ -242,6 +260,8 @@ def main():
     ap.add_argument("--eval-batches", type=int, default=0)
     ap.add_argument("--eval-snr", type=float, default=10.0)
     ap.add_argument("--multi-loss", action="store_true", help="readout and BCE after every CGNN iteration")
+    ap.add_argument("--mixed-pool", type=int, default=0,
+                    help="mixed-MCS training: cycle this many pre-drawn batch shapes (workloads with an mcs set)")
     ap.add_argument("--gamma", type=float, default=0.0,
                     help="double readout: add gamma x the channel-estimate MSE of ReadoutChEst to the loss")
     ap.add_argument("--init", default=None, help="start from these fp32 weights (.npy), e.g. to fine-tune")
@@ -254,7 +274,7 @@ def main():
     w = synth.WORKLOADS[args.workload]
     prec = L.NRX_BF16 if args.precision == "bf16" else L.NRX_FP32
     tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb, multi_loss=args.multi_loss,
-                 data_batches=args.data_batches, gamma=args.gamma)
+                 data_batches=args.data_batches, gamma=args.gamma, mixed_pool=args.mixed_pool)
     if args.ckpt and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(json.dumps({"resumed_at": tr.step}), flush=True)
@@ -269,11 +289,14 @@ def main():
                                precision=prec, batch=args.batch, n_prb=args.n_prb)
             print(json.dumps({"eval_chest": r, "snr_db": args.eval_snr, "step": tr.step}), flush=True)
         for name in evals:
+            we = synth.WORKLOADS[name]
             for k in range(1, tr.n_ro + 1) if args.multi_loss else [0]:
-                r = evaluate(tr.params, synth.WORKLOADS[name], seed=args.seed + 1000003, batches=args.eval_batches,
-                             snr_db=args.eval_snr, precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k)
-                print(json.dumps({"eval": r, "workload": name, "snr_db": args.eval_snr, "step": tr.step,
-                                  "n_iter": k}), flush=True)
+                for bits in we.get("mcs", [None]):   # mixed-MCS workloads: every modulation on its own
+                    r = evaluate(tr.params, we, seed=args.seed + 1000003, batches=args.eval_batches,
+                                 snr_db=args.eval_snr, precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k,
+                                 bits=bits)
+                    print(json.dumps({"eval": r, "workload": name, "snr_db": args.eval_snr, "step": tr.step,
+                                      "n_iter": k, "bits": bits}), flush=True)
     t0 = time.time()
     start = tr.step
     if args.eval_every and args.eval_batches:

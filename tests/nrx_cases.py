@@ -26,7 +26,8 @@ def oracle_batch(shapes, cfg, seed, batch, m_max):
     out = []
     for i, sh in enumerate(shapes):
         d = slot_sim.SlotDesc(sh["n_prb"], sh["n_ant"], sh["n_ue"], sh["bits"], slot_number=sh.get("slot_number", 0),
-                              n_id=sh.get("n_id", 0), n_scid=sh.get("n_scid", 0))
+                              n_id=sh.get("n_id", 0), n_scid=sh.get("n_scid", 0),
+                              snr_offset_db=sh.get("snr_offset_db", 0.0))
         r = slot_sim.simulate_slot(seed, batch, i, cfg, d, m_max)
         r["desc"] = d
         r["y32"] = r["y"].astype(np.complex64).astype(np.complex128)

@@ -178,3 +178,18 @@ def test_bits_and_rg_mapping():
     assert np.isclose(x[5, 3, 1], nr.qam_map(b[1, nr.data_re_index(5, 3, 48), :6], 6))
     assert np.allclose(x[:, 2, 0], nr.dmrs_grid(0, 48, 0, 2))
     assert np.allclose(x[:, 11, 1], nr.dmrs_grid(1, 48, 0, 11))
+
+
+def test_snr_offset_scales_only_the_noise():
+    # a per-slot SNR offset (mixed-MCS training, Sec. III-A) shifts the drawn SNR by exactly that many dB and
+    # scales the same noise draw by 10^(-offset/20); channel, bits and symbols are unchanged
+    cfg = slot_sim.SimConfig(n_taps=4, tap_decay_ns=100, snr_db_lo=0, snr_db_hi=10)
+    d0 = slot_sim.SlotDesc(2, 2, 2, [4, 2])
+    d1 = slot_sim.SlotDesc(2, 2, 2, [4, 2], snr_offset_db=7.5)
+    a = slot_sim.simulate_slot(3, 1, 0, cfg, d0, 4)
+    b = slot_sim.simulate_slot(3, 1, 0, cfg, d1, 4)
+    assert abs(b["snr_db"] - a["snr_db"] - 7.5) < 1e-12
+    assert np.array_equal(a["h"], b["h"]) and np.array_equal(a["bits"], b["bits"])
+    na = a["y"] - np.einsum('stub,stu->stb', a["h"], a["x"])
+    nb = b["y"] - np.einsum('stub,stu->stb', b["h"], b["x"])
+    assert np.allclose(nb, na * 10 ** (-7.5 / 20), rtol=1e-10, atol=1e-14)
