@@ -44,6 +44,22 @@ def test_weight_layout_matches_oracle(B, d, C, R, m):
         L.nrx_model_destroy(model)
 
 
+@pytest.mark.parametrize("B", [4, 8])
+def test_chest_weight_layout_matches_oracle(B):
+    # double readout: ReadoutChEst tensors close the vector, so the vector without them is a prefix
+    net = cgnn.NetConfig(B, 128, 4, 2, 4, chest=True)
+    model = L.nrx_model_create(B, 128, 4, 2, 4, flags=2)
+    try:
+        lay = L.weight_layout(model)
+        ref = cgnn.layout(net)
+        assert [(n, tuple(s)) for n, _, s in lay] == [(n, tuple(s)) for n, s in ref]
+        assert lay[-2][0] == "readout_ch.w2" and tuple(lay[-2][2]) == (128, 2 * B)
+        assert L.nrx_weight_count(model) == cgnn.n_params(net)
+        assert cgnn.n_params(cgnn.NetConfig(B, 128, 4, 2, 4)) == lay[-4][1]
+    finally:
+        L.nrx_model_destroy(model)
+
+
 def test_model_config_errors():
     with pytest.raises(L.NrxError) as e:
         L.nrx_model_create(8, 100, 6, 2, 4)          # state depth not a multiple of 8
@@ -60,6 +76,9 @@ def test_model_config_errors():
     with pytest.raises(L.NrxError) as e:
         L.nrx_model_create(8, 128, 6, 2, 5)
     assert e.value.status == L.NRX_ERR_SHAPE
+    with pytest.raises(L.NrxError) as e:
+        L.nrx_model_create(16, 128, 6, 2, 4, flags=2)   # ReadoutChEst has at most 16 outputs
+    assert e.value.status == L.NRX_ERR_SHAPE
 
 
 def test_workspace_sizes_and_slot_validation():
@@ -75,6 +94,8 @@ def test_workspace_sizes_and_slot_validation():
         assert L.nrx_workspace_bytes(model, bad) == 0            # m_u above m_max
         bad, _ = L.make_slots([dict(n_prb=300, n_ant=8, n_ue=1, bits=[4])], 4)
         assert L.nrx_workspace_bytes(model, bad) == 0
+        bad, _ = L.make_slots([dict(n_prb=4, n_ant=8, n_ue=1, bits=[4], snr_offset_db=75.0)], 4)
+        assert L.nrx_workspace_bytes(model, bad) == 0            # SNR offset beyond 60 dB
     finally:
         L.nrx_model_destroy(model)
 
@@ -96,6 +117,26 @@ def test_entry_points_reject_before_enqueueing():
         with pytest.raises(L.NrxError) as e:
             L.lmmse_demap(ok, 3, t, t, t, stream=type("S", (), {"cuda_stream": 0})())
         assert e.value.status == L.NRX_ERR_SHAPE
+        st = type("S", (), {"cuda_stream": 0})()
+        with pytest.raises(L.NrxError) as e:                     # no ReadoutChEst in this model
+            L.nrx_forward_chest(model, t, ok, t, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_INVALID
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_mse(ok, t, t, 1.0, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_WORKSPACE
+        cm = L.nrx_model_create(4, 128, 2, 0, 2, flags=2)
+        try:
+            with pytest.raises(L.NrxError) as e:
+                L.nrx_forward_chest(cm, t, ok, t, t, t, t, llr_stride=-1, stream=st)
+            assert e.value.status == L.NRX_ERR_INVALID
+            with pytest.raises(L.NrxError) as e:
+                L.nrx_forward_chest(cm, t, ok, t, t, t, t, llr_stride=64, h_stride=0, stream=st)
+            assert e.value.status == L.NRX_ERR_INVALID
+            with pytest.raises(L.NrxError) as e:                 # no saved forward on this workspace
+                L.nrx_backward_chest(cm, t, ok, t, t, t, t, stream=st)
+            assert e.value.status == L.NRX_ERR_INVALID
+        finally:
+            L.nrx_model_destroy(cm)
         cfg = L.sim_config(n_taps=40)
         with pytest.raises(L.NrxError) as e:
             L.slot_sim(cfg, 0, 0, ok, 2, t, t, stream=type("S", (), {"cuda_stream": 0})())
