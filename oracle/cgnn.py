@@ -11,7 +11,8 @@ a CNN that updates the state from [previous state, aggregated messages, PE];
 and ReadoutLLRs, an MLP from the final state to m LLRs per UE and RE.  With the
 double readout (Sec. II-A, II-B) a second MLP, ReadoutChEst, maps the same state to
 a refined channel estimate per UE, RE and antenna, trained by a gamma-scaled MSE
-against the true channel added to the BCE.  Unused
+against the true channel added to the BCE.  Under Var-IO (Sec. III) every
+modulation has its own ReadoutLLRs with just its m outputs, the rest shared.  Unused
 higher-order LLR outputs are masked for lower-order QAM (Sec. III).  Training
 minimises the BCE between LLRs and bit labels, averaged over the batch
 (Sec. II-B).
@@ -39,13 +40,18 @@ EPS_LN = 1e-5
 
 
 class NetConfig:
-    def __init__(self, n_ant, d, n_blocks, n_rounds, m_max, chest=False):
+    def __init__(self, n_ant, d, n_blocks, n_rounds, m_max, chest=False, var_io=False):
         self.B = n_ant
         self.d = d
         self.C = n_blocks
         self.R = n_rounds
         self.m_max = m_max
         self.chest = chest      # second readout (ReadoutChEst)
+        self.var_io = var_io    # one ReadoutLLRs per modulation (Var-IO output layers)
+
+    def mods(self):
+        """Modulations (bits per symbol) with a ReadoutLLRs of their own under Var-IO."""
+        return list(range(2, self.m_max + 1, 2))
 
     def mp_blocks(self):
         return [(r * self.C) // self.R for r in range(self.R)]
@@ -63,8 +69,13 @@ def layout(cfg):
               (f"blk{i}.conv_b.w", (3, 3, d, d)), (f"blk{i}.conv_b.b", (d,))]
     for r in range(cfg.R):
         L += [(f"mp{r}.w1", (d, d)), (f"mp{r}.b1", (d,)), (f"mp{r}.w2", (d, d)), (f"mp{r}.b2", (d,))]
-    L += [("readout.w1", (d, d)), ("readout.b1", (d,)),
-          ("readout.w2", (d, cfg.m_max)), ("readout.b2", (cfg.m_max,))]
+    if cfg.var_io:
+        for m in cfg.mods():
+            L += [(f"readout.m{m}.w1", (d, d)), (f"readout.m{m}.b1", (d,)),
+                  (f"readout.m{m}.w2", (d, m)), (f"readout.m{m}.b2", (m,))]
+    else:
+        L += [("readout.w1", (d, d)), ("readout.b1", (d,)),
+              ("readout.w2", (d, cfg.m_max)), ("readout.b2", (cfg.m_max,))]
     if cfg.chest:
         L += [("readout_ch.w1", (d, d)), ("readout_ch.b1", (d,)),
               ("readout_ch.w2", (d, 2 * B)), ("readout_ch.b2", (2 * B,))]
@@ -191,12 +202,29 @@ def iteration_ends(cfg):
     return [((r + 1) * cfg.C) // cfg.R for r in range(cfg.R)]
 
 
+def readout_weights(cfg, m):
+    """Names of the ReadoutLLRs tensors that serve a UE with m bits per symbol (Var-IO: its modulation's own)."""
+    p = f"readout.m{m}." if cfg.var_io else "readout."
+    return p + "w1", p + "b1", p + "w2", p + "b2"
+
+
 def readout(W, cfg, h, mask):
-    """ReadoutLLRs on the state h [S, T, U, d] -> masked llr [U, T, S, m_max] and (h, r1, q)."""
-    r1 = h @ W["readout.w1"] + W["readout.b1"]
-    q = relu(r1)
-    out = q @ W["readout.w2"] + W["readout.b2"]          # [S, T, U, m_max]
-    return np.transpose(out, (2, 1, 0, 3)) * mask[:, None, None, :], (h, r1, q)
+    """ReadoutLLRs on the state h [S, T, U, d] -> masked llr [U, T, S, m_max] and (h, r1, q).  Under Var-IO each UE
+    goes through the readout of its modulation (m_u outputs; the rest of the m_max are zero)."""
+    if not cfg.var_io:
+        r1 = h @ W["readout.w1"] + W["readout.b1"]
+        q = relu(r1)
+        out = q @ W["readout.w2"] + W["readout.b2"]          # [S, T, U, m_max]
+        return np.transpose(out, (2, 1, 0, 3)) * mask[:, None, None, :], (h, r1, q)
+    S, T, U, d = h.shape
+    r1 = np.zeros_like(h)
+    out = np.zeros((S, T, U, cfg.m_max))
+    for u in range(U):
+        m = int(mask[u].sum())
+        w1, b1, w2, b2 = readout_weights(cfg, m)
+        r1[:, :, u] = h[:, :, u] @ W[w1] + W[b1]
+        out[:, :, u, :m] = relu(r1[:, :, u]) @ W[w2] + W[b2]
+    return np.transpose(out, (2, 1, 0, 3)), (h, r1, relu(r1))
 
 
 def readout_chest(W, h, n_ant):
@@ -294,6 +322,20 @@ def backward(W, cfg, cache, dllr, dhest=None):
     def readout_back(k):
         dout = np.transpose(dl[k] * cache["mask"][:, None, None, :], (2, 1, 0, 3))   # [S, T, U, m]
         h, r1, q = cache["readouts"][k][1]
+        if cfg.var_io:
+            dh_ = np.zeros_like(h)
+            for u in range(h.shape[2]):
+                m = int(cache["mask"][u].sum())
+                w1, b1, w2, b2 = readout_weights(cfg, m)
+                du = dout[:, :, u, :m].reshape(-1, m)
+                qu, hu = q[:, :, u].reshape(-1, h.shape[-1]), h[:, :, u].reshape(-1, h.shape[-1])
+                G[w2] += qu.T @ du
+                G[b2] += du.sum(axis=0)
+                dr1 = (du @ W[w2].T) * (r1[:, :, u].reshape(-1, h.shape[-1]) > 0)
+                G[w1] += hu.T @ dr1
+                G[b1] += dr1.sum(axis=0)
+                dh_[:, :, u] = (dr1 @ W[w1].T).reshape(h.shape[0], h.shape[1], -1)
+            return dh_
         G["readout.w2"] += q.reshape(-1, q.shape[-1]).T @ dout.reshape(-1, dout.shape[-1])
         G["readout.b2"] += dout.reshape(-1, dout.shape[-1]).sum(axis=0)
         dq = dout @ W["readout.w2"].T
