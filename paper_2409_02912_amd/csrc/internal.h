@@ -116,6 +116,8 @@ struct MlpArgs {
   unsigned long long *stamps;     // readout: wall-clock time at which each slot's last tile finished
   int chest;                      // readout: ReadoutChEst -- llr is a channel estimate in the h layout
                                   // ([s][t][u][b] complex at geo.h_off), outputs j < 2B of the slot
+  int n_out;                      // readout: columns of w2 / b2 (0: m_max)
+  int only_m;                     // readout (Var-IO): write only the rows of UEs with this many bits (0: all)
 };
 template <typename T>
 void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st);
@@ -193,6 +195,8 @@ struct RoBwdArgs {
   int j0;                   // first of the 8 output columns this call handles
   int chest;                // ReadoutChEst: dllr is the gradient of a channel estimate (h layout)
   int acc_dr;               // add this call's hidden gradient to dr (the second column group)
+  int n_out;                // columns of w2 (0: m_max)
+  int only_m;               // Var-IO: only the rows of UEs with this many bits contribute (0: all)
   const SlotGeo *geo;
   const Tile *tiles;
   int n_tiles;

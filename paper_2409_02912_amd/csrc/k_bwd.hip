@@ -434,11 +434,12 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4, ch0 = 8 * lr;
   const int M = a.m_max, J0 = a.j0;
+  const int NO = a.n_out ? a.n_out : M;   // columns of w2
   float w2[8][8];
 #pragma unroll
   for (int n = 0; n < 8; ++n)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) w2[n][j] = J0 + j < M ? a.w2[(ch0 + n) * M + J0 + j] : 0.f;
+    for (int j = 0; j < 8; ++j) w2[n][j] = J0 + j < NO ? a.w2[(ch0 + n) * NO + J0 + j] : 0.f;
   float pw[8][8], pb[8];   // this lane's dW2 rows (its 8 channels) and db2
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
@@ -474,9 +475,10 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
             for (int j = 0; j < 8; ++j) dl[j] = J0 + j < 2 * g.B ? src[J0 + j] : 0.f;
           } else {
             const int mu = a.geo[tl.slot].m[u];
+            const int mv = (!a.only_m || mu == a.only_m) ? mu : 0;   // Var-IO: other modulations' rows
             const float *src = a.dllr + g.llr_off + (((int64_t)u * 14 + t) * S + s) * M;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) dl[j] = (J0 + j < M && J0 + j < mu) ? src[J0 + j] : 0.f;
+            for (int j = 0; j < 8; ++j) dl[j] = (J0 + j < M && J0 + j < mv) ? src[J0 + j] : 0.f;
           }
           pack8<T>::load(a.q + (gbase + r) * NRX_D + ch0, qv);
         }

@@ -348,7 +348,8 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
   const int lr = lane & 15, lk = lane >> 4;
   const int ch0 = 8 * lr;
   const int M = a.m_max;
-  const float b2 = lr < M ? a.b2[lr] : 0.f;
+  const int NO = a.n_out ? a.n_out : M;
+  const float b2 = lr < NO ? a.b2[lr] : 0.f;
   // first-layer biases of this lane's channels, read once (a global load inside the tile loop
   // would make the compiler wait for every outstanding vector-memory operation, the next
   // tile's copy included)
@@ -465,7 +466,8 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
             const int rem = R - s * 14 * U;
             const int tt = rem / U, u = rem - tt * U;
             const int mu = u == 0 ? mu0 : (u == 1 ? mu1 : (u == 2 ? mu2 : mu3));
-            a.llr[llr_off + (((int64_t)u * 14 + tt) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
+            if (!a.only_m || mu == a.only_m)
+              a.llr[llr_off + (((int64_t)u * 14 + tt) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
           }
         }
     }
@@ -488,7 +490,8 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
   const int lr = lane & 15, lk = lane >> 4;
   const int ch0 = 8 * lr;
   const int M = a.m_max;
-  const float b2 = lr < M ? a.b2[lr] : 0.f;
+  const int NO = a.n_out ? a.n_out : M;
+  const float b2 = lr < NO ? a.b2[lr] : 0.f;
 
   for (int tile = blockIdx.x; tile < a.n_tiles; tile += gridDim.x) {
     const Tile tl = a.tiles[tile];
@@ -517,7 +520,9 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
           for (int nb = 0; nb < 8; ++nb) q[nb] = bf2f(f2bf(q[nb]));
         }
         OpTile<T>::put8(lds, r, ch0, q);
-        if (a.save_m1 && r < tl.nrows) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, q);
+        // Var-IO: every readout keeps the hidden layer of its own modulation's rows only
+        const bool mine = !a.only_m || a.geo[tl.slot].m[(tl.row0 + r) % g.U] == a.only_m;
+        if (a.save_m1 && r < tl.nrows && mine) pack8<T>::store(a.save_m1 + (gbase + r) * NRX_D + ch0, q);
       }
     __syncthreads();
     // second layer: one 16-column MFMA block (outputs j < m_max, rest zero weights)
@@ -555,7 +560,8 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
             const int rem = R - s * 14 * U;
             const int t = rem / U, u = rem - t * U;
             const int mu = a.geo[tl.slot].m[u];
-            a.llr[g.llr_off + (((int64_t)u * 14 + t) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
+            if (!a.only_m || mu == a.only_m)
+              a.llr[g.llr_off + (((int64_t)u * 14 + t) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
           }
         }
     }

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -297,7 +298,10 @@ struct nrx_model {
   ConvLayer conv_in;
   std::vector<BlockLayer> blocks;
   std::vector<DenseLayer> mp;
-  DenseLayer ro;
+  // ReadoutLLRs: one shared layer (m = 0, m_max outputs, masked to m_u), or under Var-IO (flags bit 2)
+  // one per modulation m = 2, 4, .. m_max with m outputs, each applied to the UEs of its modulation
+  struct Readout { DenseLayer l; int m; };
+  std::vector<Readout> ros;
   bool chest = false;                   // flags bit 1: second readout ReadoutChEst (double readout)
   DenseLayer ro_ch;
   std::vector<PrepJob> jobs;
@@ -369,6 +373,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
   if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
+  if ((c.flags & 4) && c.precision == NRX_FP8) return fail(NRX_ERR_UNSUPPORTED, "Var-IO needs FP32 or BF16");
   if ((c.flags & 2) && c.n_ant > 8)
     return fail(NRX_ERR_SHAPE, "ReadoutChEst has 2 n_ant outputs, at most 16: n_ant %d > 8", c.n_ant);
   auto m = std::make_unique<nrx_model>();
@@ -401,10 +406,18 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     add_tensor(m.get(), p + ".w2", {d, d});
     add_tensor(m.get(), p + ".b2", {d});
   }
-  add_tensor(m.get(), "readout.w1", {d, d});
-  add_tensor(m.get(), "readout.b1", {d});
-  add_tensor(m.get(), "readout.w2", {d, c.m_max});
-  add_tensor(m.get(), "readout.b2", {c.m_max});
+  std::vector<int> ro_mods;   // modulation of each ReadoutLLRs (0: shared)
+  if (c.flags & 4)
+    for (int mm = 2; mm <= c.m_max; mm += 2) ro_mods.push_back(mm);
+  else
+    ro_mods.push_back(0);
+  for (int mm : ro_mods) {
+    const std::string p = mm ? "readout.m" + std::to_string(mm) + "." : "readout.";
+    add_tensor(m.get(), p + "w1", {d, d});
+    add_tensor(m.get(), p + "b1", {d});
+    add_tensor(m.get(), p + "w2", {d, mm ? mm : c.m_max});
+    add_tensor(m.get(), p + "b2", {mm ? mm : c.m_max});
+  }
   if (m->chest) {   // appended, so a weight vector without them is a prefix of this one
     add_tensor(m.get(), "readout_ch.w1", {d, d});
     add_tensor(m.get(), "readout_ch.b1", {d});
@@ -469,14 +482,18 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     dense_job(L.w1, L.p1);
     dense_job(L.w2, L.p2);
   }
-  m->ro.w1 = toff(m.get(), "readout.w1"); m->ro.b1 = toff(m.get(), "readout.b1");
-  m->ro.w2 = toff(m.get(), "readout.w2"); m->ro.b2 = toff(m.get(), "readout.b2");
-  dense_job(m->ro.w1, m->ro.p1);
-  {
-    m->ro.p2 = m->prep_elems;
-    PrepJob j{4, d, d, NRX_D / KC, 0, c.m_max, m->ro.w2, m->ro.p2, (int64_t)NRX_D * 16, d, 0};
+  for (int mm : ro_mods) {
+    const std::string p = mm ? "readout.m" + std::to_string(mm) + "." : "readout.";
+    nrx_model::Readout R;
+    R.m = mm;
+    R.l.w1 = toff(m.get(), p + "w1"); R.l.b1 = toff(m.get(), p + "b1");
+    R.l.w2 = toff(m.get(), p + "w2"); R.l.b2 = toff(m.get(), p + "b2");
+    dense_job(R.l.w1, R.l.p1);
+    R.l.p2 = m->prep_elems;
+    PrepJob j{4, d, d, NRX_D / KC, 0, mm ? mm : c.m_max, R.l.w2, R.l.p2, (int64_t)NRX_D * 16, d, 0};
     m->jobs.push_back(j);
     m->prep_elems += j.count;
+    m->ros.push_back(R);
   }
   if (m->chest) {
     DenseLayer &L = m->ro_ch;
@@ -505,7 +522,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     m->mp[r].t1 = bjob(5, m->mp[r].w1, d, 0, (int64_t)d * 128);
     m->mp[r].t2 = bjob(5, m->mp[r].w2, d, 0, (int64_t)d * 128);
   }
-  m->ro.t1 = bjob(5, m->ro.w1, d, 0, (int64_t)d * 128);
+  for (auto &R : m->ros) R.l.t1 = bjob(5, R.l.w1, d, 0, (int64_t)d * 128);
   if (m->chest) m->ro_ch.t1 = bjob(5, m->ro_ch.w1, d, 0, (int64_t)d * 128);
   if (d < NRX_D) {
     pad_vec(m->conv_in.b, &m->conv_in.bpad);
@@ -516,7 +533,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
       pad_vec(L.beta, &L.betapad);
     }
     for (auto &L : m->mp) { pad_vec(L.b1, &L.b1pad); pad_vec(L.b2, &L.b2pad); }
-    pad_vec(m->ro.b1, &m->ro.b1pad);
+    for (auto &R : m->ros) pad_vec(R.l.b1, &R.l.b1pad);
     if (m->chest) pad_vec(m->ro_ch.b1, &m->ro_ch.b1pad);
     for (auto &pv : pads) {
       *pv.second = m->field_elems;
@@ -646,7 +663,8 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
     // dW2 partials: one set per readout for ReadoutLLRs, two (column groups) for ReadoutChEst
-    L.rpart = o; o = align256(o + (m->chest ? 3 : 1) * iteration_ends(m->cfg).size() * BWD_GRID_MAX * 1032 * 4);
+    L.rpart = o;
+    o = align256(o + (m->ros.size() + (m->chest ? 2 : 0)) * iteration_ends(m->cfg).size() * BWD_GRID_MAX * 1032 * 4);
   }
   L.total = o;
   return L;
@@ -768,22 +786,37 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   const std::vector<int> ends = iteration_ends(m->cfg);
   if (n_run <= 0 || n_run > (int)ends.size()) n_run = (int)ends.size();
   const int c_run = ends[n_run - 1];
+  // ReadoutLLRs to run: the shared one, or (Var-IO) those of the modulations the batch uses
+  std::vector<const nrx_model::Readout *> ros_run;
+  for (auto &R : m->ros)
+    if (!R.m || std::any_of(P->geo.begin(), P->geo.end(), [&](const SlotGeo &g) {
+          for (int u = 0; u < g.U; ++u)
+            if (g.m[u] == R.m) return true;
+          return false;
+        }))
+      ros_run.push_back(&R);
   auto readout = [&](int blocks_done, int k, bool last) {
     MlpArgs<T> ra{};
-    ra.h = buf(L.h[save ? blocks_done : 0]);
-    ra.w1 = wprep + m->ro.p1;
-    ra.b1 = vec(m->ro.b1, m->ro.b1pad);
-    ra.b2 = w + m->ro.b2;
-    ra.w2 = wprep + m->ro.p2;
-    ra.save_m1 = save ? buf(L.q[k]) : nullptr;
-    ra.llr = llr + (int64_t)k * llr_stride;
-    ra.m_max = m->cfg.m_max;
-    ra.geo = D.geo;
-    ra.tiles = D.rt;
-    ra.n_tiles = (int)P->rt.size();
-    ra.slot_done = last ? (unsigned int *)(ws + L.done) : nullptr;   // the pass completes at the last readout
-    ra.stamps = last ? (unsigned long long *)(ws + L.stamps) : nullptr;
-    {
+    for (size_t i = 0; i < ros_run.size(); ++i) {
+      const nrx_model::Readout &R = *ros_run[i];
+      ra = MlpArgs<T>{};
+      ra.h = buf(L.h[save ? blocks_done : 0]);
+      ra.w1 = wprep + R.l.p1;
+      ra.b1 = vec(R.l.b1, R.l.b1pad);
+      ra.b2 = w + R.l.b2;
+      ra.w2 = wprep + R.l.p2;
+      ra.save_m1 = save ? buf(L.q[k]) : nullptr;
+      ra.llr = llr + (int64_t)k * llr_stride;
+      ra.m_max = m->cfg.m_max;
+      ra.n_out = R.m;
+      ra.only_m = R.m;
+      ra.geo = D.geo;
+      ra.tiles = D.rt;
+      ra.n_tiles = (int)P->rt.size();
+      // the pass completes at the last launch of the last readout
+      const bool fin = last && i + 1 == ros_run.size();
+      ra.slot_done = fin ? (unsigned int *)(ws + L.done) : nullptr;
+      ra.stamps = fin ? (unsigned long long *)(ws + L.stamps) : nullptr;
       ProfMark pm(m, NRX_K_READOUT, st);
       launch_readout<T>(ra, grid_mlp, st);
     }
@@ -796,6 +829,8 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ca.save_m1 = save ? buf(L.q_ch[k]) : nullptr;
       ca.llr = hest + (int64_t)k * h_stride;
       ca.m_max = 2 * m->cfg.n_ant;
+      ca.n_out = 0;
+      ca.only_m = 0;
       ca.chest = 1;
       ca.slot_done = nullptr;
       ca.stamps = nullptr;
@@ -1246,28 +1281,48 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   const int c_run = ends[n_run - 1];
   const int n_ro = llr_stride > 0 ? n_run : 1;
   int ro_done = 0;
-  // dW2 partial sets of ReadoutChEst column group g, after those of ReadoutLLRs
-  auto chest_part = [&](int g) {
-    return rpart + (int64_t)(1 + g) * (int64_t)ends.size() * BWD_GRID_MAX * 1032;
-  };
+  // dW2 partial sets: per ReadoutLLRs (one, or one per Var-IO modulation), then the two column groups
+  // of ReadoutChEst; each holds the partials of every readout
+  const int64_t set_floats = (int64_t)ends.size() * BWD_GRID_MAX * 1032;
+  auto chest_part = [&](int g) { return rpart + (int64_t)(m->ros.size() + g) * set_floats; };
+  // the ReadoutLLRs the forward ran (Var-IO: the batch's modulations); the others get a zero gradient
+  std::vector<int> ro_run;
+  for (size_t i = 0; i < m->ros.size(); ++i) {
+    const int mm = m->ros[i].m;
+    bool used = mm == 0;
+    for (auto &g : P->geo)
+      for (int u = 0; u < g.U; ++u) used = used || g.m[u] == mm;
+    if (used) {
+      ro_run.push_back((int)i);
+    } else {
+      const DenseLayer &l = m->ros[i].l;
+      HIPCHK(hipMemsetAsync(dw + l.w1, 0, (size_t)(l.b2 + mm - l.w1) * sizeof(float), st));
+    }
+  }
   auto readout_back = [&](int k, int blocks_done) {
     const bool acc = ro_done > 0;
     RoBwdArgs<T> a{};
-    a.dllr = dllr + (int64_t)k * llr_stride;
-    a.q = buf(L.q[k]);
-    a.w2 = w + m->ro.w2;
-    a.w1t = bp + m->ro.t1;
-    a.dr = buf(L.dr);
-    a.dh = dh;
-    a.accumulate = acc ? 1 : 0;
-    a.part = rpart + (int64_t)ro_done * grid_mlp * 1032;
-    a.m_max = m->cfg.m_max;
-    a.geo = D.geo;
-    a.tiles = D.rt;
-    a.n_tiles = (int)P->rt.size();
-    launch_readout_bwd<T>(a, grid_mlp, st);
-    wgrad(buf(L.h[blocks_done]), d, nullptr, 0, buf(L.dr), false, d, d, m->ro.w1, acc);
-    bias(buf(L.dr), m->ro.b1, -1, 0, 0, acc);
+    for (size_t i = 0; i < ro_run.size(); ++i) {
+      const nrx_model::Readout &R = m->ros[ro_run[i]];
+      a = RoBwdArgs<T>{};
+      a.dllr = dllr + (int64_t)k * llr_stride;
+      a.q = buf(L.q[k]);
+      a.w2 = w + R.l.w2;
+      a.w1t = bp + R.l.t1;
+      a.dr = buf(L.dr);
+      a.dh = dh;
+      a.accumulate = (acc || i > 0) ? 1 : 0;
+      a.part = rpart + (int64_t)ro_run[i] * set_floats + (int64_t)ro_done * grid_mlp * 1032;
+      a.m_max = m->cfg.m_max;
+      a.n_out = R.m;
+      a.only_m = R.m;
+      a.geo = D.geo;
+      a.tiles = D.rt;
+      a.n_tiles = (int)P->rt.size();
+      launch_readout_bwd<T>(a, grid_mlp, st);
+      wgrad(buf(L.h[blocks_done]), d, nullptr, 0, buf(L.dr), false, d, d, R.l.w1, acc);
+      bias(buf(L.dr), R.l.b1, -1, 0, 0, acc);
+    }
     if (dhest) {
       // ReadoutChEst on the same state: its 2B outputs in groups of 8 columns, adding to dh
       RoBwdArgs<T> c = a;
@@ -1277,6 +1332,8 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
       c.w1t = bp + m->ro_ch.t1;
       c.accumulate = 1;
       c.m_max = 2 * m->cfg.n_ant;
+      c.n_out = 0;
+      c.only_m = 0;
       c.chest = 1;
       for (int g = 0; 8 * g < c.m_max; ++g) {
         c.j0 = 8 * g;
@@ -1334,7 +1391,11 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
       dgrad(dz, bp + B.bg_a_h, EPI_RESID, NRX_K_CONV_A, dh, dh, nullptr, nullptr, nullptr);
     }
   }
-  launch_readout_w2_reduce(rpart, n_ro * grid_mlp, m->cfg.m_max, m->ro.w2, m->ro.b2, dw, st);
+  for (int i : ro_run) {
+    const nrx_model::Readout &R = m->ros[i];
+    launch_readout_w2_reduce(rpart + (int64_t)i * set_floats, n_ro * grid_mlp, R.m ? R.m : m->cfg.m_max, R.l.w2,
+                             R.l.b2, dw, st);
+  }
   if (dhest) {
     for (int g = 0; 8 * g < 2 * m->cfg.n_ant; ++g)
       launch_readout_w2_reduce(chest_part(g), n_ro * grid_mlp, 2 * m->cfg.n_ant, m->ro_ch.w2, m->ro_ch.b2, dw, st,

@@ -36,7 +36,7 @@ def weight_layout(model):
 
 class Trainer:
     def __init__(self, w, precision=L.NRX_BF16, seed=0, lr=1e-3, batch=None, n_prb=None, snr=None,
-                 multi_loss=False, data_batches=0, gamma=0.0, mixed_pool=0):
+                 multi_loss=False, data_batches=0, gamma=0.0, mixed_pool=0, var_io=False):
         import torch
         self.torch = torch
         self.w = w
@@ -58,8 +58,9 @@ class Trainer:
         self.sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
                                 rho=w["rho"], snr_db_lo=snr[0], snr_db_hi=snr[1])
         self.gamma = float(gamma)
+        self.var_io = var_io   # one ReadoutLLRs per modulation (Sec. III)
         self.model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], self.m_max, precision,
-                                        flags=2 if self.gamma > 0 else 0)
+                                        flags=(2 if self.gamma > 0 else 0) | (4 if var_io else 0))
 
         def pool_max(f):
             return max(f(e[1]) for e in self.pool)
@@ -158,7 +159,8 @@ class Trainer:
         L.nrx_model_destroy(self.model)
 
 
-def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, n_iter=0, bits=None):
+def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, n_iter=0, bits=None,
+             var_io=False):
     """BER of the NRX and of LS + LMMSE on held-out slots (a seed not used in training) at a fixed SNR;
     n_iter > 0 runs the NRX at that many CGNN iterations; bits sets every UE's modulation (default the workload's,
     which is also the network's LLR count m_max: lower orders read the first bits outputs, Sec. III)."""
@@ -168,7 +170,8 @@ def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=Non
     descs, sz = L.make_slots(shapes, m_max)
     sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
                        snr_db_lo=snr_db, snr_db_hi=snr_db)
-    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision)
+    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision,
+                               flags=4 if var_io else 0)
     try:
         L.nrx_set_iterations(model, n_iter)
         dev = "cuda"
@@ -203,7 +206,7 @@ def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=Non
         L.nrx_model_destroy(model)
 
 
-def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None):
+def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, var_io=False):
     """Held-out channel-estimation MSE (mean |ĥ - h|^2 over the batch's complex entries) of the ReadoutChEst output
     after the last CGNN iteration, next to that of the LS estimate with linear interpolation the network starts from
     (Sec. II-A), on fresh slots at one SNR."""
@@ -214,7 +217,8 @@ def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, bat
     descs, sz = L.make_slots(shapes, m_max)
     sim = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
                        snr_db_lo=snr_db, snr_db_hi=snr_db)
-    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision, flags=2)
+    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, precision,
+                               flags=6 if var_io else 2)
     try:
         params = torch.as_tensor(w_params, dtype=torch.float32, device=dev)
         if params.numel() != L.nrx_weight_count(model):
@@ -262,6 +266,7 @@ def main():
     ap.add_argument("--multi-loss", action="store_true", help="readout and BCE after every CGNN iteration")
     ap.add_argument("--mixed-pool", type=int, default=0,
                     help="mixed-MCS training: cycle this many pre-drawn batch shapes (workloads with an mcs set)")
+    ap.add_argument("--var-io", action="store_true", help="one ReadoutLLRs per modulation (Var-IO output layers)")
     ap.add_argument("--gamma", type=float, default=0.0,
                     help="double readout: add gamma x the channel-estimate MSE of ReadoutChEst to the loss")
     ap.add_argument("--init", default=None, help="start from these fp32 weights (.npy), e.g. to fine-tune")
@@ -274,7 +279,7 @@ def main():
     w = synth.WORKLOADS[args.workload]
     prec = L.NRX_BF16 if args.precision == "bf16" else L.NRX_FP32
     tr = Trainer(w, prec, args.seed, args.lr, args.batch, args.n_prb, multi_loss=args.multi_loss,
-                 data_batches=args.data_batches, gamma=args.gamma, mixed_pool=args.mixed_pool)
+                 data_batches=args.data_batches, gamma=args.gamma, mixed_pool=args.mixed_pool, var_io=args.var_io)
     if args.ckpt and os.path.exists(args.ckpt):
         tr.load(args.ckpt)
         print(json.dumps({"resumed_at": tr.step}), flush=True)
@@ -286,7 +291,7 @@ def main():
     def eval_all():
         if args.gamma > 0:
             r = evaluate_chest(tr.params, w, seed=args.seed + 1000003, batches=args.eval_batches, snr_db=args.eval_snr,
-                               precision=prec, batch=args.batch, n_prb=args.n_prb)
+                               precision=prec, batch=args.batch, n_prb=args.n_prb, var_io=args.var_io)
             print(json.dumps({"eval_chest": r, "snr_db": args.eval_snr, "step": tr.step}), flush=True)
         for name in evals:
             we = synth.WORKLOADS[name]
@@ -294,7 +299,7 @@ def main():
                 for bits in we.get("mcs", [None]):   # mixed-MCS workloads: every modulation on its own
                     r = evaluate(tr.params, we, seed=args.seed + 1000003, batches=args.eval_batches,
                                  snr_db=args.eval_snr, precision=prec, batch=args.batch, n_prb=args.n_prb, n_iter=k,
-                                 bits=bits)
+                                 bits=bits, var_io=args.var_io)
                     print(json.dumps({"eval": r, "workload": name, "snr_db": args.eval_snr, "step": tr.step,
                                       "n_iter": k, "bits": bits}), flush=True)
     t0 = time.time()

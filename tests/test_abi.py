@@ -60,6 +60,24 @@ def test_chest_weight_layout_matches_oracle(B):
         L.nrx_model_destroy(model)
 
 
+@pytest.mark.parametrize("m", [2, 6, 8])
+def test_var_io_weight_layout_matches_oracle(m):
+    # Var-IO output layers: one ReadoutLLRs per modulation 2..m_max, each with its own number of outputs
+    net = cgnn.NetConfig(8, 128, 6, 2, m, var_io=True, chest=True)
+    model = L.nrx_model_create(8, 128, 6, 2, m, flags=6)
+    try:
+        lay = L.weight_layout(model)
+        assert [(n, tuple(s)) for n, _, s in lay] == [(n, tuple(s)) for n, s in cgnn.layout(net)]
+        assert L.nrx_weight_count(model) == cgnn.n_params(net)
+        assert [n for n, _, _ in lay if n.endswith(".b2") and n.startswith("readout.m")] == \
+            [f"readout.m{k}.b2" for k in range(2, m + 1, 2)]
+    finally:
+        L.nrx_model_destroy(model)
+    with pytest.raises(L.NrxError) as e:
+        L.nrx_model_create(8, 128, 6, 2, m, L.NRX_FP8, flags=4)
+    assert e.value.status == L.NRX_ERR_UNSUPPORTED
+
+
 def test_model_config_errors():
     with pytest.raises(L.NrxError) as e:
         L.nrx_model_create(8, 100, 6, 2, 4)          # state depth not a multiple of 8

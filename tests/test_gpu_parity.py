@@ -216,6 +216,9 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4, all_iters=False):
             [(f"mp{r}", f"mp{r}.b1", 1) for r in range(net.R)] + [("readout", "readout.b1", 1)]
     if getattr(net, "chest", False):
         units.append(("readout_ch", "readout_ch.b1", 1))
+    if getattr(net, "var_io", False):
+        units = [x for x in units if x[0] != "readout"] + [(f"readout_m{m}", f"readout.m{m}.b1", m)
+                                                           for m in net.mods()]
     margin = 0.0
     for it in range(iters + 1):
         W = cgnn.unflatten(w, net)
@@ -228,10 +231,15 @@ def _away_from_kinks(w, net, ref_slots, sigmas=5.0, iters=4, all_iters=False):
                     pre[k] += [rc[1].reshape(-1, net.d) for _, rc in cache["readouts"]]
                 elif k == "readout_ch":
                     pre[k] += [cc[1].reshape(-1, net.d) for cc in cache["chest"]]
+                elif k.startswith("readout_m"):   # Var-IO: the rows of this modulation's UEs
+                    us = [u for u, b in enumerate(r["desc"].bits_per_sym) if b == j]
+                    pre[k] += [rc[1][:, :, us].reshape(-1, net.d) for _, rc in cache["readouts"]]
                 else:
                     pre[k].append(cache[k][j].reshape(-1, net.d))
         margin = np.inf
         for k, bname, _ in units:
+            if not sum(len(x) for x in pre[k]):
+                continue                                 # a Var-IO modulation no UE of the batch uses
             x = np.concatenate(pre[k])
             b = w[offs[bname]:offs[bname] + net.d]
             x0 = x - b                                   # the pre-activation without its bias
@@ -302,6 +310,88 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1, multi=False):
 @pytest.mark.parametrize("variant", [1, 4, 5, 6, 7, 8])
 def test_nrx_backward_fp32_matches_oracle(variant):
     _grad_case(0, 1e-4, 0.9999999, variant=variant)
+
+
+VARIO_SHAPES = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
+                dict(n_prb=3, n_ant=4, n_ue=3, bits=[6, 4, 2], slot_number=2)]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
+def test_nrx_forward_var_io_matches_oracle(prec, tol):
+    """Var-IO output layers (Sec. III): one ReadoutLLRs per modulation (2, 4, 6, 8 bits), each UE read out by its
+    own; the batch mixes QPSK, 16-QAM and 64-QAM UEs, the 256-QAM readout is unused."""
+    net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
+    log(f"Var-IO forward: prec={prec}")
+    ref_slots = oracle_batch(VARIO_SHAPES, sim_cfg_oracle(SIMCFG), 61, 0, 8)
+    w = synth.he_weights(cgnn.layout(net), 61, perturb=True)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, 8, prec, flags=4)
+    try:
+        assert [(n, tuple(s)) for n, _, s in L.weight_layout(model)] == [(n, tuple(s)) for n, s in cgnn.layout(net)]
+        exp = oracle_nrx(w, net, ref_slots)
+        descs, sz = L.make_slots(VARIO_SHAPES, 8)
+        y = _upload_batch(VARIO_SHAPES, ref_slots)
+        llr = torch.full((sz["llr"],), float("nan"), dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        L.nrx_forward(model, dev(w), descs, y, llr, ws)
+        torch.cuda.synchronize()
+        got = llr.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got)), "LLR entries left unwritten"
+        e = rel_err(np.concatenate([x.reshape(-1) for x in split_llr(got, VARIO_SHAPES, 8)]),
+                    np.concatenate([x.reshape(-1) for x in exp]))
+        log(f"  LLR relative error {e:.2e}")
+        assert e <= tol
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_nrx_backward_var_io_fp32_matches_oracle():
+    """Var-IO gradient: each modulation's readout learns from its own UEs only; the unused one gets zero."""
+    net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
+    m_max = 8
+    log("Var-IO backward: fp32")
+    ref_slots = oracle_batch(VARIO_SHAPES, sim_cfg_oracle(SIMCFG), 67, 0, m_max)
+    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), 67, perturb=True), net, ref_slots)
+    log(f"  smallest |ReLU input| / layer RMS {margin:.2e}")
+    assert margin > 1e-4
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    rng = np.random.default_rng(67)
+    descs, sz = L.make_slots(VARIO_SHAPES, m_max)
+    dllr_np = rng.standard_normal(sz["llr"]).astype(np.float32)
+    dparts = split_llr(dllr_np.astype(np.float64), VARIO_SHAPES, m_max)
+    G = {k: np.zeros_like(v) for k, v in W.items()}
+    for i, r in enumerate(ref_slots):
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True)
+        for k, g in cgnn.backward(W, net, cache, dparts[i]).items():
+            G[k] += g
+    ref = cgnn.flatten(G, net)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, 0, flags=4)
+    try:
+        y = _upload_batch(VARIO_SHAPES, ref_slots)
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
+        dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
+        wt = dev(w)
+        L.set_all_conv_variants(model, 7)
+        L.nrx_forward(model, wt, descs, y, llr, ws, save_acts=True)
+        L.nrx_backward(model, wt, descs, dev(dllr_np), dw, ws)
+        torch.cuda.synchronize()
+        got = dw.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got)), "gradient entries left unwritten"
+        off = 0
+        for name, shape in cgnn.layout(net):
+            n = int(np.prod(shape))
+            if name.startswith("readout.m8."):
+                assert np.all(got[off:off + n] == 0), name
+            else:
+                et = rel_err(got[off:off + n], ref[off:off + n])
+                assert et <= 1e-4, f"{name}: relative error {et:.3e}"
+            off += n
+        e = rel_err(got, ref)
+        log(f"  gradient relative error (all weights) {e:.2e}")
+        assert e <= 1e-4
+    finally:
+        L.nrx_model_destroy(model)
 
 
 def test_nrx_backward_multi_loss_fp32_matches_oracle():
@@ -554,21 +644,24 @@ def test_double_readout_training_refines_channel_estimate():
     assert r["mse_nrx"] < 0.85 * r["mse_ls"]
 
 
-def test_mixed_mcs_training_learns_every_modulation():
-    """Mixed-MCS training with LLR masking (Sec. III, III-A; U_A drawn per batch, Sec. II-B): one network with six
-    LLR outputs, trained on batches of random U_A, iid per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR
-    offsets, detects every modulation (held-out BCE per coded bit at 10 dB after 2000 steps; measured after 1500
-    steps 0.056 / 0.242 / 0.396, after 3000 steps 0.023 / 0.164 / 0.331)."""
+@pytest.mark.parametrize("var_io", [False, True])
+def test_mixed_mcs_training_learns_every_modulation(var_io):
+    """Mixed-MCS training (Sec. III, III-A; U_A drawn per batch, Sec. II-B) of the two Var-MCS receivers: LLR masking
+    (one readout with six outputs) and Var-IO (one readout per modulation).  Trained on batches of random U_A, iid
+    per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR offsets, each detects every modulation (held-out BCE
+    per coded bit at 10 dB after 2000 steps; measured after 1500 steps 0.056 / 0.242 / 0.396 with masking and
+    0.052 / 0.241 / 0.394 with Var-IO)."""
     from paper_2409_02912_amd.train import Trainer, evaluate
     w = synth.WORKLOADS["tm"]
-    log("training: workload tm, mixed MCS (pool of 16 batch shapes), 2000 steps")
-    tr = Trainer(w, L.NRX_BF16, seed=5, lr=1e-3, mixed_pool=16)
+    log(f"training: workload tm, mixed MCS (pool of 16 batch shapes), Var-IO {var_io}, 2000 steps")
+    tr = Trainer(w, L.NRX_BF16, seed=5, lr=1e-3, mixed_pool=16, var_io=var_io)
     try:
         assert len({tuple(s["n_ue"] for s in e[0]) for e in tr.pool}) > 1   # U_A varies over the batches
         for _ in range(2000):
             tr.train_step()
         torch.cuda.synchronize()
-        bce = {b: evaluate(tr.params, w, seed=99, batches=2, snr_db=10.0, bits=b)["bce_nrx"] for b in w["mcs"]}
+        bce = {b: evaluate(tr.params, w, seed=99, batches=2, snr_db=10.0, bits=b, var_io=var_io)["bce_nrx"]
+               for b in w["mcs"]}
     finally:
         tr.close()
     log(f"  held-out BCE per modulation (bits: BCE) {bce}")
