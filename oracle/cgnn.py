@@ -12,7 +12,8 @@ and ReadoutLLRs, an MLP from the final state to m LLRs per UE and RE.  With the
 double readout (Sec. II-A, II-B) a second MLP, ReadoutChEst, maps the same state to
 a refined channel estimate per UE, RE and antenna, trained by a gamma-scaled MSE
 against the true channel added to the BCE.  Under Var-IO (Sec. III) every
-modulation has its own ReadoutLLRs with just its m outputs, the rest shared.  Unused
+modulation has its own StateInit and its own ReadoutLLRs with just its m outputs, the
+CGNN iterations shared.  Unused
 higher-order LLR outputs are masked for lower-order QAM (Sec. III).  Training
 minimises the BCE between LLRs and bit labels, averaged over the batch
 (Sec. II-B).
@@ -61,7 +62,12 @@ def layout(cfg):
     """Ordered list of (name, shape) of the flat weight vector."""
     d, B = cfg.d, cfg.B
     mpb = cfg.mp_blocks()
-    L = [("conv_in.w", (3, 3, 4 * B + 2, d)), ("conv_in.b", (d,))]
+    if cfg.var_io:
+        L = []
+        for m in cfg.mods():
+            L += [(f"conv_in.m{m}.w", (3, 3, 4 * B + 2, d)), (f"conv_in.m{m}.b", (d,))]
+    else:
+        L = [("conv_in.w", (3, 3, 4 * B + 2, d)), ("conv_in.b", (d,))]
     for i in range(cfg.C):
         cin = 2 * d + 2 if i in mpb else d
         L += [(f"blk{i}.conv_a.w", (3, 3, cin, d)), (f"blk{i}.conv_a.b", (d,)),
@@ -260,7 +266,14 @@ def forward_x(W, cfg, X, bits_per_sym, keep=False, n_iter=None, all_iters=False,
         mask[u, :bits_per_sym[u]] = 1.0
     pe = X[..., 4 * cfg.B:]
     cache = {"X": X, "mask": mask, "c_run": c_run, "readouts": [], "hests": [], "chest": []}
-    h = conv3x3(X, W["conv_in.w"], W["conv_in.b"])
+    if cfg.var_io:
+        # Var-IO input layers: every UE's state starts from its modulation's own StateInit
+        h = np.zeros(X.shape[:3] + (cfg.d,))
+        for m in sorted(set(bits_per_sym[:U])):
+            us = [u for u in range(U) if bits_per_sym[u] == m]
+            h[:, :, us] = conv3x3(X[:, :, us], W[f"conv_in.m{m}.w"], W[f"conv_in.m{m}.b"])
+    else:
+        h = conv3x3(X, W["conv_in.w"], W["conv_in.b"])
     cache["h0"] = h
     mpb = cfg.mp_blocks()
     llrs = []
@@ -373,7 +386,14 @@ def backward(W, cfg, cache, dllr, dhest=None):
             dh = dh + da1 @ W[f"mp{r}.w1"].T
         else:
             dh = dh + dxin
-    _, G["conv_in.w"], G["conv_in.b"] = conv3x3_backward(cache["X"], W["conv_in.w"], dh)
+    if cfg.var_io:
+        bps = [int(x) for x in cache["mask"].sum(axis=1)]
+        for m in sorted(set(bps)):
+            us = [u for u in range(len(bps)) if bps[u] == m]
+            _, G[f"conv_in.m{m}.w"], G[f"conv_in.m{m}.b"] = conv3x3_backward(
+                cache["X"][:, :, us], W[f"conv_in.m{m}.w"], dh[:, :, us])
+    else:
+        _, G["conv_in.w"], G["conv_in.b"] = conv3x3_backward(cache["X"], W["conv_in.w"], dh)
     return G
 
 

@@ -344,31 +344,36 @@ def test_chest_readout_closed_form_with_zero_second_layer():
     assert np.all(G["readout_ch.w1"] == 0) and np.all(G["readout_ch.b1"] == 0)
 
 
-def test_var_io_readout():
-    # Var-IO output layers (Sec. III): each UE is read out by its modulation's own ReadoutLLRs with m_u outputs.
-    # (i) with every modulation's layers equal to the shared readout cut to its first m outputs it is the masking
-    # scheme; (ii) central differences of the forward match the backward on a slot mixing two modulations, and the
-    # readout of the modulation nobody uses gets no gradient
+def test_var_io():
+    # Var-IO (Sec. III, Fig. 2): each UE starts from its modulation's own StateInit and is read out by its own
+    # ReadoutLLRs with m_u outputs.  (i) with every modulation's layers equal to the shared ones (readout cut to its
+    # first m outputs) it is the masking scheme; (ii) central differences of the forward match the backward on a
+    # slot mixing two modulations, and the layers of the modulation nobody uses get no gradient
     cfg = cgnn.NetConfig(2, 6, 2, 1, 6, var_io=True)
     plain = cgnn.NetConfig(2, 6, 2, 1, 6)
     Wp = _random_net(plain, 51)
     desc, r, h = _slot(U=3, m=4, seed=52)
     m_list = [4, 2, 4]
     X = cgnn.nrx_inputs(r["y"], h, cfg)
-    W = {k: v for k, v in Wp.items() if not k.startswith("readout.")}
+    W = {k: v for k, v in Wp.items() if not k.startswith("readout.") and not k.startswith("conv_in.")}
     for m in cfg.mods():
+        W[f"conv_in.m{m}.w"], W[f"conv_in.m{m}.b"] = Wp["conv_in.w"], Wp["conv_in.b"]
         W[f"readout.m{m}.w1"], W[f"readout.m{m}.b1"] = Wp["readout.w1"], Wp["readout.b1"]
         W[f"readout.m{m}.w2"], W[f"readout.m{m}.b2"] = Wp["readout.w2"][:, :m], Wp["readout.b2"][:m]
     assert set(W) == {n for n, _ in cgnn.layout(cfg)}
-    assert np.array_equal(cgnn.forward_x(W, cfg, X, m_list), cgnn.forward_x(Wp, plain, X, m_list))
+    # (the per-modulation convolutions over a subset of UEs sum in another order: equal to rounding)
+    assert np.allclose(cgnn.forward_x(W, cfg, X, m_list), cgnn.forward_x(Wp, plain, X, m_list), rtol=1e-12,
+                       atol=1e-12)
     W = _random_net(cfg, 53)
     llr, cache = cgnn.forward_x(W, cfg, X, m_list, keep=True)
     assert np.all(llr[1, :, :, 2:] == 0) and np.all(llr[0, :, :, 4:] == 0)
     rng = np.random.default_rng(54)
     dl = rng.standard_normal(llr.shape)
     G = cgnn.backward(W, cfg, cache, dl)
-    assert all(np.all(G[n] == 0) for n in ("readout.m6.w1", "readout.m6.b1", "readout.m6.w2", "readout.m6.b2"))
+    assert all(np.all(G[n] == 0) for n in ("readout.m6.w1", "readout.m6.b1", "readout.m6.w2", "readout.m6.b2",
+                                           "conv_in.m6.w", "conv_in.m6.b"))
     assert np.any(G["readout.m2.w2"] != 0) and np.any(G["readout.m4.w2"] != 0)
+    assert np.any(G["conv_in.m2.w"] != 0) and np.any(G["conv_in.m4.w"] != 0)
     eps = 1e-8
     v = {k: rng.standard_normal(w.shape) for k, w in W.items()}
     f = lambda Wx: np.sum(dl * cgnn.forward_x(Wx, cfg, X, m_list))  # noqa: E731
