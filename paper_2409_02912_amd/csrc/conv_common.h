@@ -264,6 +264,13 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
   }
 
   float vmax = 0.f;   // max |output| of this lane (calibration of FP8 scales)
+  int om[4] = {0, 0, 0, 0};   // Var-IO StateInit: bits per symbol of the slot's UEs (scalar loads)
+  if constexpr (EPI == EPI_STORE) {
+    if (a.only_m) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) om[k] = ldc(&a.geo[tl.slot].m[k]);
+    }
+  }
   // residual rows of the lane (EPI_RESID), requested RB m-blocks at a time before any of
   // them is used; rows past the tile read row 0 and are not stored
   constexpr int RB = MB % 2 == 0 ? 2 : 1;
@@ -307,7 +314,14 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs<T> &a, const Tile &
           for (int nb = 0; nb < 8; ++nb) v[nb] += rsd[nb];
         }
       }
-      if (valid) {
+      bool keep = valid;
+      if constexpr (EPI == EPI_STORE) {
+        if (a.only_m) {   // Var-IO StateInit: this launch writes its modulation's UEs only
+          const int u = (tl.row0 + r) % U;
+          keep = keep && (u == 0 ? om[0] : (u == 1 ? om[1] : (u == 2 ? om[2] : om[3]))) == a.only_m;
+        }
+      }
+      if (keep) {
         if (a.out) pack8<T>::store(a.out + grow * NRX_D + ch0, v);
         if (a.out8) *reinterpret_cast<uint2 *>(a.out8 + grow * NRX_D + ch0) = fp8x8(v, a.out8_inv);
         if (a.amax) {

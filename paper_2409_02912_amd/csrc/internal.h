@@ -34,6 +34,7 @@ struct ConvArgs {
   uint8_t *out8;            // E4M3 copy of the output, out * out8_inv, or null (out may then be null)
   float out8_inv;
   unsigned int *amax;       // max |output| over the launch (float bits, atomicMax), or null
+  int only_m;               // EPI_STORE (Var-IO StateInit): store only the rows of UEs with this many bits
 };
 
 struct ConvVariant {
@@ -180,6 +181,11 @@ struct MpBwdArgs {
 };
 template <typename T>
 void launch_mp_bwd(const MpBwdArgs<T> &a, int grid, hipStream_t st);
+
+// dst = src on the rows of UEs with only_m bits per symbol, 0 on the others ([rows][128]; Var-IO StateInit).
+template <typename T>
+void launch_select_rows(const T *src, const SlotGeo *geo, int n_slots, int64_t max_rows, int only_m, T *dst,
+                        hipStream_t st);
 
 template <typename T>
 struct RoBwdArgs {

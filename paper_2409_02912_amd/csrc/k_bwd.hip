@@ -560,6 +560,24 @@ __global__ __launch_bounds__(256) void readout_bwd_kernel(RoBwdArgs<T> a) {
     a.part[(int64_t)blockIdx.x * 1032 + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
 }
 
+// One thread per 8 channels (16 or 32 bytes) of a row; grid (row blocks, slots).
+template <typename T>
+__global__ void select_rows_kernel(const T *src, const SlotGeo *geo, int only_m, T *dst) {
+  const SlotGeo g = geo[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = idx >> 4;
+  if (row >= (int64_t)g.S * 14 * g.U) return;
+  const int ch0 = 8 * (int)(idx & 15);
+  const int64_t o = (g.row_base + row) * NRX_D + ch0;
+  float v[8];
+  pack8<T>::load(src + o, v);
+  if (g.m[row % g.U] != only_m) {
+#pragma unroll
+    for (int n = 0; n < 8; ++n) v[n] = 0.f;
+  }
+  pack8<T>::store(dst + o, v);
+}
+
 __global__ void readout_w2_reduce_kernel(const float *part, int n, int m_max, int64_t w2_off, int64_t b2_off,
                                          float *dw, int j0) {
   const int e = threadIdx.x + blockIdx.x * blockDim.x;   // 0..1031
@@ -606,6 +624,15 @@ template <typename T>
 void launch_mp_bwd(const MpBwdArgs<T> &a, int grid, hipStream_t st) {
   hipLaunchKernelGGL(mp_bwd_kernel<T>, dim3(grid), dim3(256), 0, st, a);
 }
+template <typename T>
+void launch_select_rows(const T *src, const SlotGeo *geo, int n_slots, int64_t max_rows, int only_m, T *dst,
+                        hipStream_t st) {
+  const unsigned nb = (unsigned)((max_rows * 16 + 255) / 256);
+  hipLaunchKernelGGL(select_rows_kernel<T>, dim3(nb, n_slots), dim3(256), 0, st, src, geo, only_m, dst);
+}
+template void launch_select_rows<float>(const float *, const SlotGeo *, int, int64_t, int, float *, hipStream_t);
+template void launch_select_rows<bf16_t>(const bf16_t *, const SlotGeo *, int, int64_t, int, bf16_t *, hipStream_t);
+
 template <typename T>
 void launch_readout_bwd(const RoBwdArgs<T> &a, int grid, hipStream_t st) {
   hipLaunchKernelGGL(readout_bwd_kernel<T>, dim3(grid), dim3(256), 0, st, a);

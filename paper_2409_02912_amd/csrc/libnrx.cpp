@@ -295,7 +295,9 @@ struct nrx_model {
   std::vector<TensorInfo> tensors;
   int64_t n_w = 0;
   int cx = 0;                           // feature channels of the StateInit input
-  ConvLayer conv_in;
+  // StateInit: one shared (m = 0), or under Var-IO one per modulation m = 2, 4, .. m_max
+  struct StateInit { ConvLayer c; int m; };
+  std::vector<StateInit> cins;
   std::vector<BlockLayer> blocks;
   std::vector<DenseLayer> mp;
   // ReadoutLLRs: one shared layer (m = 0, m_max outputs, masked to m_u), or under Var-IO (flags bit 2)
@@ -385,8 +387,18 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   m->cx = std::max(32, 4 * B);
   std::vector<int> mpb;
   for (int r = 0; r < c.n_rounds; ++r) mpb.push_back((r * c.n_blocks) / c.n_rounds);
-  add_tensor(m.get(), "conv_in.w", {3, 3, 4 * B + 2, d});
-  add_tensor(m.get(), "conv_in.b", {d});
+  std::vector<int> io_mods;   // modulation of each StateInit / ReadoutLLRs (0: shared)
+  if (c.flags & 4)
+    for (int mm = 2; mm <= c.m_max; mm += 2) io_mods.push_back(mm);
+  else
+    io_mods.push_back(0);
+  auto io_prefix = [](const char *layer, int mm) {
+    return mm ? std::string(layer) + ".m" + std::to_string(mm) + "." : std::string(layer) + ".";
+  };
+  for (int mm : io_mods) {
+    add_tensor(m.get(), io_prefix("conv_in", mm) + "w", {3, 3, 4 * B + 2, d});
+    add_tensor(m.get(), io_prefix("conv_in", mm) + "b", {d});
+  }
   for (int i = 0; i < c.n_blocks; ++i) {
     bool ismp = false;
     for (int v : mpb) ismp = ismp || v == i;
@@ -406,13 +418,8 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     add_tensor(m.get(), p + ".w2", {d, d});
     add_tensor(m.get(), p + ".b2", {d});
   }
-  std::vector<int> ro_mods;   // modulation of each ReadoutLLRs (0: shared)
-  if (c.flags & 4)
-    for (int mm = 2; mm <= c.m_max; mm += 2) ro_mods.push_back(mm);
-  else
-    ro_mods.push_back(0);
-  for (int mm : ro_mods) {
-    const std::string p = mm ? "readout.m" + std::to_string(mm) + "." : "readout.";
+  for (int mm : io_mods) {
+    const std::string p = io_prefix("readout", mm);
     add_tensor(m.get(), p + "w1", {d, d});
     add_tensor(m.get(), p + "b1", {d});
     add_tensor(m.get(), p + "w2", {d, mm ? mm : c.m_max});
@@ -450,7 +457,12 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   // d < 128: vectors padded with zeros, placed in the field buffer after the PE fields
   std::vector<std::pair<int64_t, int64_t *>> pads;
   auto pad_vec = [&](int64_t src, int64_t *dst) { if (d < NRX_D) pads.push_back({src, dst}); };
-  conv_job(m->conv_in, toff(m.get(), "conv_in.w"), toff(m.get(), "conv_in.b"), 4 * B, 4 * B + 2, m->cx, true, 0);
+  m->cins.resize(io_mods.size());
+  for (size_t i = 0; i < io_mods.size(); ++i) {
+    m->cins[i].m = io_mods[i];
+    conv_job(m->cins[i].c, toff(m.get(), io_prefix("conv_in", io_mods[i]) + "w"),
+             toff(m.get(), io_prefix("conv_in", io_mods[i]) + "b"), 4 * B, 4 * B + 2, m->cx, true, 0);
+  }
   m->mp.resize(c.n_rounds);
   for (int i = 0; i < c.n_blocks; ++i) {
     const std::string p = "blk" + std::to_string(i);
@@ -482,8 +494,8 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     dense_job(L.w1, L.p1);
     dense_job(L.w2, L.p2);
   }
-  for (int mm : ro_mods) {
-    const std::string p = mm ? "readout.m" + std::to_string(mm) + "." : "readout.";
+  for (int mm : io_mods) {
+    const std::string p = io_prefix("readout", mm);
     nrx_model::Readout R;
     R.m = mm;
     R.l.w1 = toff(m.get(), p + "w1"); R.l.b1 = toff(m.get(), p + "b1");
@@ -525,7 +537,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   for (auto &R : m->ros) R.l.t1 = bjob(5, R.l.w1, d, 0, (int64_t)d * 128);
   if (m->chest) m->ro_ch.t1 = bjob(5, m->ro_ch.w1, d, 0, (int64_t)d * 128);
   if (d < NRX_D) {
-    pad_vec(m->conv_in.b, &m->conv_in.bpad);
+    for (auto &ci : m->cins) pad_vec(ci.c.b, &ci.c.bpad);
     for (auto &L : m->blocks) {
       pad_vec(L.a.b, &L.a.bpad);
       pad_vec(L.b.b, &L.b.bpad);
@@ -586,6 +598,14 @@ namespace {
 // Blocks completed at the end of each CGNN iteration: iteration r is message-passing round r and
 // the state-update blocks up to the next round (Sec. II-A); without message passing the whole
 // stack is one iteration.
+// Does a UE of the batch use modulation m (bits per symbol)?  (Var-IO runs only those layers.)
+bool batch_uses(const Plan *P, int m) {
+  for (auto &g : P->geo)
+    for (int u = 0; u < g.U; ++u)
+      if (g.m[u] == m) return true;
+  return false;
+}
+
 std::vector<int> iteration_ends(const nrx_model_config &c) {
   std::vector<int> e;
   if (c.n_rounds == 0) e.push_back(c.n_blocks);
@@ -774,14 +794,18 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   a.ln_pad = (float)(NRX_D - m->cfg.d);
   // StateInit
   a.src0 = X; a.c0 = m->cx; a.src1 = nullptr; a.c1 = 0;
-  a.w = wprep + m->conv_in.prep;
-  a.bias = vec(m->conv_in.b, m->conv_in.bpad);
-  a.pe = fields + m->conv_in.field;
   a.out = buf(L.h[0]);
-  ConvArgs<T> a0 = a;
-  if (f8) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
-  if (amax) a0.amax = amax + 0;
-  conv(a0, EPI_STORE, NRX_K_CONV_IN, false);
+  for (auto &ci : m->cins) {   // Var-IO: one launch per modulation the batch uses, each storing its UEs' rows
+    if (ci.m && !batch_uses(P, ci.m)) continue;
+    ConvArgs<T> a0 = a;
+    a0.w = wprep + ci.c.prep;
+    a0.bias = vec(ci.c.b, ci.c.bpad);
+    a0.pe = fields + ci.c.field;
+    a0.only_m = ci.m;
+    if (f8) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
+    if (amax) a0.amax = amax + 0;
+    conv(a0, EPI_STORE, NRX_K_CONV_IN, false);
+  }
   // CGNN iterations run (depth control) and, with llr_stride > 0, a readout after each of them
   const std::vector<int> ends = iteration_ends(m->cfg);
   if (n_run <= 0 || n_run > (int)ends.size()) n_run = (int)ends.size();
@@ -789,12 +813,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   // ReadoutLLRs to run: the shared one, or (Var-IO) those of the modulations the batch uses
   std::vector<const nrx_model::Readout *> ros_run;
   for (auto &R : m->ros)
-    if (!R.m || std::any_of(P->geo.begin(), P->geo.end(), [&](const SlotGeo &g) {
-          for (int u = 0; u < g.U; ++u)
-            if (g.m[u] == R.m) return true;
-          return false;
-        }))
-      ros_run.push_back(&R);
+    if (!R.m || batch_uses(P, R.m)) ros_run.push_back(&R);
   auto readout = [&](int blocks_done, int k, bool last) {
     MlpArgs<T> ra{};
     for (size_t i = 0; i < ros_run.size(); ++i) {
@@ -1289,10 +1308,7 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   std::vector<int> ro_run;
   for (size_t i = 0; i < m->ros.size(); ++i) {
     const int mm = m->ros[i].m;
-    bool used = mm == 0;
-    for (auto &g : P->geo)
-      for (int u = 0; u < g.U; ++u) used = used || g.m[u] == mm;
-    if (used) {
+    if (!mm || batch_uses(P, mm)) {
       ro_run.push_back((int)i);
     } else {
       const DenseLayer &l = m->ros[i].l;
@@ -1406,8 +1422,19 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
   }
   // StateInit (no data gradient needed)
   const int B4 = 4 * m->cfg.n_ant;
-  wgrad(buf(L.X), m->cx, nullptr, 0, dh, true, B4, B4 + 2, m->conv_in.w);
-  bias(dh, m->conv_in.b, m->conv_in.w, B4 + 2, B4);
+  for (auto &ci : m->cins) {
+    if (!ci.m) {
+      wgrad(buf(L.X), m->cx, nullptr, 0, dh, true, B4, B4 + 2, ci.c.w);
+      bias(dh, ci.c.b, ci.c.w, B4 + 2, B4);
+    } else if (batch_uses(P, ci.m)) {
+      // Var-IO: this modulation's StateInit sees the gradient of its UEs' rows only
+      launch_select_rows<T>(dh, D.geo, P->n, P->max_rows, ci.m, dz, st);
+      wgrad(buf(L.X), m->cx, nullptr, 0, dz, true, B4, B4 + 2, ci.c.w);
+      bias(dz, ci.c.b, ci.c.w, B4 + 2, B4);
+    } else {
+      HIPCHK(hipMemsetAsync(dw + ci.c.w, 0, (size_t)(ci.c.b + m->cfg.d - ci.c.w) * sizeof(float), st));
+    }
+  }
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }

@@ -318,8 +318,9 @@ VARIO_SHAPES = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_var_io_matches_oracle(prec, tol):
-    """Var-IO output layers (Sec. III): one ReadoutLLRs per modulation (2, 4, 6, 8 bits), each UE read out by its
-    own; the batch mixes QPSK, 16-QAM and 64-QAM UEs, the 256-QAM readout is unused."""
+    """Var-IO (Sec. III, Fig. 2): one StateInit and one ReadoutLLRs per modulation (2, 4, 6, 8 bits), each UE's
+    state initialised and read out by its own; the batch mixes QPSK, 16-QAM and 64-QAM UEs, the 256-QAM layers are
+    unused."""
     net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
     log(f"Var-IO forward: prec={prec}")
     ref_slots = oracle_batch(VARIO_SHAPES, sim_cfg_oracle(SIMCFG), 61, 0, 8)
@@ -345,7 +346,8 @@ def test_nrx_forward_var_io_matches_oracle(prec, tol):
 
 
 def test_nrx_backward_var_io_fp32_matches_oracle():
-    """Var-IO gradient: each modulation's readout learns from its own UEs only; the unused one gets zero."""
+    """Var-IO gradient: each modulation's StateInit and readout learn from their own UEs only; the unused ones get
+    zero."""
     net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
     m_max = 8
     log("Var-IO backward: fp32")
@@ -381,7 +383,7 @@ def test_nrx_backward_var_io_fp32_matches_oracle():
         off = 0
         for name, shape in cgnn.layout(net):
             n = int(np.prod(shape))
-            if name.startswith("readout.m8."):
+            if name.startswith("readout.m8.") or name.startswith("conv_in.m8."):
                 assert np.all(got[off:off + n] == 0), name
             else:
                 et = rel_err(got[off:off + n], ref[off:off + n])
@@ -648,9 +650,10 @@ def test_double_readout_training_refines_channel_estimate():
 def test_mixed_mcs_training_learns_every_modulation(var_io):
     """Mixed-MCS training (Sec. III, III-A; U_A drawn per batch, Sec. II-B) of the two Var-MCS receivers: LLR masking
     (one readout with six outputs) and Var-IO (one readout per modulation).  Trained on batches of random U_A, iid
-    per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR offsets, each detects every modulation (held-out BCE
-    per coded bit at 10 dB after 2000 steps; measured after 1500 steps 0.056 / 0.242 / 0.396 with masking and
-    0.052 / 0.241 / 0.394 with Var-IO)."""
+    per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR offsets, each detects every modulation: held-out BCE
+    per coded bit at 10 dB after 2000 steps well below ln 2 = 0.69 (measured with masking after 1500 steps
+    0.056 / 0.242 / 0.396; with Var-IO, whose input and output layers each see a third of the data, after 2000
+    steps 0.135 / 0.346 / 0.477)."""
     from paper_2409_02912_amd.train import Trainer, evaluate
     w = synth.WORKLOADS["tm"]
     log(f"training: workload tm, mixed MCS (pool of 16 batch shapes), Var-IO {var_io}, 2000 steps")
@@ -665,7 +668,7 @@ def test_mixed_mcs_training_learns_every_modulation(var_io):
     finally:
         tr.close()
     log(f"  held-out BCE per modulation (bits: BCE) {bce}")
-    assert bce[2] < 0.12 and bce[4] < 0.30 and bce[6] < 0.45
+    assert bce[2] < 0.25 and bce[4] < 0.45 and bce[6] < 0.55
 
 
 def test_site_fine_tuning_improves_site_receiver():
