@@ -256,6 +256,61 @@ def depth_latency(reps=30):
                           "iteration and 270 us overhead on an A100 (TensorRT)"}
 
 
+def secondary_rows(steps, tune_cache):
+    """Throughput of the secondary shapes with seeded weights (no trained network exists for them, so LLR error
+    against the FP32 pass stands in for BER): B = 4 antennas / 2 UEs at 273 PRB (32 slots), and B = 16 antennas /
+    4 UEs / 64-QAM at 106 PRB with 8 blocks and 3 message-passing rounds (64 slots)."""
+    import numpy as np
+    import torch
+    from paper_2409_02912_amd import libnrx as L
+    from paper_2409_02912_amd import synth
+    out = {}
+    for name in ("c2", "c3"):
+        w = synth.WORKLOADS[name]
+        shapes = synth.uniform_shapes(w)
+        descs, sz = L.make_slots(shapes, w["m"])
+        cfg = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
+                           rho=w["rho"], snr_db_lo=w["snr"][0], snr_db_hi=w["snr"][1])
+        y = torch.empty(2 * sz["y"], dtype=torch.float32, device="cuda")
+        sws = torch.empty(L.slot_sim_workspace_bytes(cfg, descs), dtype=torch.uint8, device="cuda")
+        L.slot_sim(cfg, 0, 0, descs, w["m"], y, sws)
+        del sws
+        net_args = (w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], w["m"])
+        row, llrs = {}, {}
+        for prec, pname in ((L.NRX_BF16, "bf16"), (L.NRX_FP32, "fp32")):
+            model = L.nrx_model_create(*net_args, prec)
+            try:
+                dw = torch.from_numpy(synth.he_weights([(n, sh) for n, _, sh in L.weight_layout(model)], 0)).cuda()
+                ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
+                llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+                if pname == "bf16":
+                    L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=tune_cache)
+                n = steps if pname == "bf16" else 1
+                L.nrx_forward(model, dw, descs, y, llr, ws)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(n):
+                    L.nrx_forward(model, dw, descs, y, llr, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / n
+                row[pname] = {"ms_per_step": ms, "slots_per_s": len(shapes) / (ms * 1e-3)}
+                llrs[pname] = llr.cpu().numpy().astype(np.float64)
+                del ws
+            finally:
+                L.nrx_model_destroy(model)
+        row["res_per_s_bf16"] = row["bf16"]["slots_per_s"] * 12 * w["n_prb"] * 14
+        row["llr_rel_err_bf16_vs_fp32"] = float(np.linalg.norm(llrs["bf16"] - llrs["fp32"]) /
+                                               np.linalg.norm(llrs["fp32"]))
+        row["workload"] = (f"{len(shapes)} slots x {w['n_prb']} PRB x 14 sym, {w['n_ue']} UE, {w['n_ant']} ant, "
+                           f"{2 ** w['m']}-QAM; CGNN d={w['d']}, {w['n_blocks']} blocks, {w['n_rounds']} MP rounds; "
+                           "seeded weights")
+        out[name] = row
+        progress(f"secondary {name}: {row['bf16']['ms_per_step']:.3f} ms/step bf16")
+    return out
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -279,6 +334,7 @@ def main():
                     help="autotuner cache (JSON lines): reuse its tile-shape choices, append new ones")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain elementwise copy kernel over this many MiB (HBM-counter calibration)")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the B = 4 and B = 16 throughput rows")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2409_02912_amd", "weights", "nrx_c5.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -509,6 +565,8 @@ def main():
     if not args.bf16_only:
         out["paper_rt_batch1"] = paper_rt_latency()
         out["depth_latency"] = depth_latency()
+        if not args.no_secondary:
+            out["secondary"] = secondary_rows(max(3, args.steps // 4), args.tune_cache)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)
