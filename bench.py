@@ -311,6 +311,34 @@ def secondary_rows(steps, tune_cache):
     return out
 
 
+def training_row(steps):
+    """One training step (Sec. II-B) on the C5 training batch (64 slots x 106 PRB x 14 symbols, 4 UEs, 8 antennas,
+    16-QAM; CGNN d = 128, 6 blocks, 2 MP rounds), BF16: slot generation, forward keeping activations, BCE, the
+    hand-written backward and the Adam step, all on the GPU."""
+    import torch
+    from paper_2409_02912_amd import libnrx as L
+    from paper_2409_02912_amd import synth
+    from paper_2409_02912_amd.train import Trainer
+    w = synth.WORKLOADS["c5"]
+    tr = Trainer(w, L.NRX_BF16, seed=0)
+    try:
+        for _ in range(2):
+            tr.train_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            tr.train_step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    finally:
+        tr.close()
+    return {"workload": "64 slots x 106 PRB x 14 sym, 4 UE, 8 ant, 16-QAM; CGNN d=128, 6 blocks, 2 MP rounds; "
+                        "bf16; slot_sim + forward + BCE + backward + Adam",
+            "ms_per_step": ms, "slots_per_s": w["n_slots"] / (ms * 1e-3), "steps": steps}
+
+
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -567,6 +595,8 @@ def main():
         out["depth_latency"] = depth_latency()
         if not args.no_secondary:
             out["secondary"] = secondary_rows(max(3, args.steps // 4), args.tune_cache)
+            out["training"] = training_row(max(3, args.steps // 4))
+            progress(f"training: {out['training']['ms_per_step']:.2f} ms/step")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, weights, net_args, args.cpu_budget)
     print(json.dumps(out), flush=True)
