@@ -66,6 +66,8 @@ class Trainer:
             return max(f(e[1]) for e in self.pool)
         dev = "cuda"
         self.params = torch.from_numpy(synth.he_weights(weight_layout(self.model), seed)).to(dev)
+        # weights before the ReadoutChEst tensors (which close the vector)
+        self._n_no_chest = sum(int(np.prod(s)) for n, s in weight_layout(self.model) if not n.startswith("readout_ch"))
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros_like(self.params)
@@ -117,6 +119,8 @@ class Trainer:
         w0 = self.torch.as_tensor(np.asarray(w0, dtype=np.float32))
         if w0.numel() > self.params.numel():
             raise ValueError(f"{w0.numel()} weights for a model of {self.params.numel()}")
+        if self.var_io and w0.numel() < self._n_no_chest:
+            raise ValueError("a Var-IO model starts from Var-IO weights (the layouts differ)")
         self.params[:w0.numel()].copy_(w0)
 
     def train_step(self):
