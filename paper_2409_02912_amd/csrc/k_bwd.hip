@@ -29,6 +29,11 @@ template <typename T>
 struct WgStage {
   float x[4][8], d[4][8];
 };
+// BF16: the rows as loaded (8 channels = 4 packed words each), half the registers of floats
+template <>
+struct WgStage<bf16_t> {
+  uint32_t x[4][4], d[4][4];
+};
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
@@ -82,10 +87,7 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
     if (c.k0 >= c.nrows) set_tile(c, c.ti + 1);
   };
   auto load = [&](const Cur &c, WgStage<T> &stg) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) { stg.x[q][e] = 0.f; stg.d[q][e] = 0.f; }
+    stg = WgStage<T>{};
     if (c.ti >= t1) return;
     const int rps = 14 * c.U;
 #pragma unroll
@@ -95,20 +97,52 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
         const int R = c.row0 + r;
         const int s = R / rps, t = (R - s * rps) / c.U;
         const int64_t grow = c.base + R;
-        pack8<T>::load(a.dy + grow * NRX_D + 8 * cg, stg.d[q]);
         const int sn = s + di, tn = t + dj;
-        if (sn >= 0 && sn < c.S && tn >= 0 && tn < 14 && 8 * cg < cwidth)
-          pack8<T>::load(src + (grow + di * rps + dj * c.U) * cs + coff + 8 * cg, stg.x[q]);
+        const bool xin = sn >= 0 && sn < c.S && tn >= 0 && tn < 14 && 8 * cg < cwidth;
+        const T *xs = src + (grow + di * rps + dj * c.U) * cs + coff + 8 * cg;
+        if constexpr (sizeof(T) == 2) {
+          const v16 dv = ld16(a.dy + grow * NRX_D + 8 * cg);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) stg.d[q][w] = dv.w[w];
+          if (xin) {
+            const v16 xv = ld16(xs);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) stg.x[q][w] = xv.w[w];
+          }
+        } else {
+          pack8<T>::load(a.dy + grow * NRX_D + 8 * cg, stg.d[q]);
+          if (xin) pack8<T>::load(xs, stg.x[q]);
+        }
       }
     }
   };
   auto store = [&](int b, const WgStage<T> &stg) {
+    if constexpr (sizeof(T) == 2) {
+      // channel 2w / 2w + 1 of rows (q, q + 1) from the low / high halves of word w: the 4 rows of a channel
+      // are contiguous in the transposed tile, one 8-byte store per channel and array
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      T *xp = &xt[b][(8 * cg + e) * TP + 4 * rg];
-      T *dp = &dt[b][(8 * cg + e) * TP + 4 * rg];
+      for (int w = 0; w < 4; ++w) {
+        uint32_t xl[2], xh[2], dl[2], dh[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) { xp[q] = elem<T>::from_f(stg.x[q][e]); dp[q] = elem<T>::from_f(stg.d[q][e]); }
+        for (int p = 0; p < 2; ++p) {
+          xl[p] = (stg.x[2 * p][w] & 0xFFFFu) | (stg.x[2 * p + 1][w] << 16);
+          xh[p] = (stg.x[2 * p][w] >> 16) | (stg.x[2 * p + 1][w] & 0xFFFF0000u);
+          dl[p] = (stg.d[2 * p][w] & 0xFFFFu) | (stg.d[2 * p + 1][w] << 16);
+          dh[p] = (stg.d[2 * p][w] >> 16) | (stg.d[2 * p + 1][w] & 0xFFFF0000u);
+        }
+        *reinterpret_cast<uint2 *>(&xt[b][(8 * cg + 2 * w) * TP + 4 * rg]) = make_uint2(xl[0], xl[1]);
+        *reinterpret_cast<uint2 *>(&xt[b][(8 * cg + 2 * w + 1) * TP + 4 * rg]) = make_uint2(xh[0], xh[1]);
+        *reinterpret_cast<uint2 *>(&dt[b][(8 * cg + 2 * w) * TP + 4 * rg]) = make_uint2(dl[0], dl[1]);
+        *reinterpret_cast<uint2 *>(&dt[b][(8 * cg + 2 * w + 1) * TP + 4 * rg]) = make_uint2(dh[0], dh[1]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        T *xp = &xt[b][(8 * cg + e) * TP + 4 * rg];
+        T *dp = &dt[b][(8 * cg + e) * TP + 4 * rg];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { xp[q] = elem<T>::from_f(stg.x[q][e]); dp[q] = elem<T>::from_f(stg.d[q][e]); }
+      }
     }
   };
 
@@ -147,11 +181,7 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
       c0 = c1;
       c1 = c2;
       if (c2.ti < t1) next(c2);
-      // rotate register stages: s1 <- s0 (step k+2 becomes k+1)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) { s1.x[q][e] = s0.x[q][e]; s1.d[q][e] = s0.d[q][e]; }
+      s1 = s0;   // rotate register stages: step k+2 becomes k+1
     }
   }
   // partial [part][job][c 128][o 128]; D layout: lane holds c = 4*lk + i, o = lr (per block)
