@@ -1280,8 +1280,9 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.save_stats = const_cast<float *>(stats);
     a.ln_part = lpart;
     a.geo = D.geo;
-    // the LayerNorm-backward epilogue spills in the large-tile variants: keep it on variant 1
-    int v = epi == EPI_LN_BWD ? 1 : m->conv_variant[cls];
+    // the LayerNorm-backward epilogue spills in the 8-wave and 2-waves-per-SIMD variants; the one-wave-per-SIMD
+    // LDS-operand variant (384-row tiles) holds it in registers
+    int v = epi == EPI_LN_BWD ? 4 : m->conv_variant[cls];
     if (kConvVariants[v].pref == 2 && ((a.c0 + a.c1) / (64 / (int)sizeof(T))) % 2) v = 1;
     const ConvVariant &cv = kConvVariants[v];
     const int ti = tile_size_index(cv.mb);
