@@ -420,7 +420,8 @@ def main():
     if not args.bf16_only:
         passes.append((L.NRX_FP32, "fp32"))
     for prec, name in passes:
-        model = L.nrx_model_create(*net_args, prec)
+        # flags bit 0: the timed pass is the captured launch sequence replayed as a hipGraph
+        model = L.nrx_model_create(*net_args, prec, flags=1)
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         if name == "fp8":
@@ -451,9 +452,6 @@ def main():
         for _ in range(warm):
             L.nrx_forward(model, dw, descs, y, llr, ws)
         torch.cuda.synchronize()
-        L.nrx_profile_enable(model, True)
-        for c in range(len(L.KERNEL_CLASSES)):
-            L.nrx_profile_read(model, c, reset=True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
@@ -461,10 +459,19 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        # per-kernel durations: the same passes launched one by one, each kernel between two HIP events on the
+        # stream it runs on (profiling replaces the graph replay by the eager launch sequence)
+        L.nrx_profile_enable(model, True)
+        for c in range(len(L.KERNEL_CLASSES)):
+            L.nrx_profile_read(model, c, reset=True)
+        psteps = min(steps, 5)
+        for _ in range(psteps):
+            L.nrx_forward(model, dw, descs, y, llr, ws)
+        torch.cuda.synchronize()
         kern = {}
         for c, cname in enumerate(L.KERNEL_CLASSES):
             t, n = L.nrx_profile_read(model, c)
-            kern[cname] = {"ms_per_launch": t / max(n, 1), "launches_per_step": n / steps}
+            kern[cname] = {"ms_per_launch": t / max(n, 1), "launches_per_step": n / psteps}
         L.nrx_profile_enable(model, False)
         results[name] = {"ms_per_step": ms, "kernels": kern}
         progress(f"{name}: {ms:.3f} ms/step")
