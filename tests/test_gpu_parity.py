@@ -396,6 +396,63 @@ def test_nrx_backward_var_io_fp32_matches_oracle():
         L.nrx_model_destroy(model)
 
 
+def test_nrx_backward_var_io_chest_multi_loss_fp32_matches_oracle():
+    """The training extensions together: Var-IO layers, the double readout and the multi-loss (readouts after both
+    CGNN iterations), one gradient against the oracle's."""
+    net = cgnn.NetConfig(4, 128, 4, 2, 8, chest=True, var_io=True)
+    m_max = 8
+    log("Var-IO + double readout + multi-loss backward: fp32")
+    ref_slots = oracle_batch(VARIO_SHAPES, sim_cfg_oracle(SIMCFG), 71, 0, m_max)
+    w, margin = _away_from_kinks(synth.he_weights(cgnn.layout(net), 71, perturb=True), net, ref_slots,
+                                 all_iters=True)
+    log(f"  smallest |ReLU input| / layer RMS {margin:.2e}")
+    assert margin > 1e-4
+    W = cgnn.unflatten(w.astype(np.float64), net)
+    rng = np.random.default_rng(71)
+    descs, sz = L.make_slots(VARIO_SHAPES, m_max)
+    ls_, hs_ = sz["llr"], 2 * sz["h"]
+    dllr_np = rng.standard_normal(2 * ls_).astype(np.float32)
+    dh_np = rng.standard_normal(2 * hs_).astype(np.float32)
+    dl = [split_llr(dllr_np[k * ls_:(k + 1) * ls_].astype(np.float64), VARIO_SHAPES, m_max) for k in range(2)]
+    dhc = [split_h(dh_np[k * hs_:(k + 1) * hs_].astype(np.float64).view(np.complex128), VARIO_SHAPES)
+           for k in range(2)]
+    G = {k: np.zeros_like(v) for k, v in W.items()}
+    for i, r in enumerate(ref_slots):
+        h = receiver.ls_estimate(r["y32"], r["desc"])
+        _, cache = cgnn.forward(W, net, r["y32"], h, r["desc"].bits_per_sym, keep=True, all_iters=True)
+        for k, g in cgnn.backward(W, net, cache, [dl[j][i] for j in range(2)], [dhc[j][i] for j in range(2)]).items():
+            G[k] += g
+    ref = cgnn.flatten(G, net)
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, 0, flags=6)
+    try:
+        y = _upload_batch(VARIO_SHAPES, ref_slots)
+        llr = torch.zeros(2 * ls_, dtype=torch.float32, device="cuda")
+        hest = torch.zeros(2 * hs_, dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs, save_acts=True))
+        dw = torch.full((len(w),), float("nan"), dtype=torch.float32, device="cuda")
+        wt = dev(w)
+        L.set_all_conv_variants(model, 7)
+        L.nrx_forward_chest(model, wt, descs, y, llr, hest, ws, llr_stride=ls_, h_stride=hs_, save_acts=True)
+        L.nrx_backward_chest(model, wt, descs, dev(dllr_np), dev(dh_np), dw, ws, llr_stride=ls_, h_stride=hs_)
+        torch.cuda.synchronize()
+        got = dw.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(got)), "gradient entries left unwritten"
+        off = 0
+        for name, shape in cgnn.layout(net):
+            n = int(np.prod(shape))
+            if ".m8." in name:
+                assert np.all(got[off:off + n] == 0), name
+            else:
+                et = rel_err(got[off:off + n], ref[off:off + n])
+                assert et <= 1e-4, f"{name}: relative error {et:.3e}"
+            off += n
+        e = rel_err(got, ref)
+        log(f"  gradient relative error (all weights) {e:.2e}")
+        assert e <= 1e-4
+    finally:
+        L.nrx_model_destroy(model)
+
+
 def test_nrx_backward_multi_loss_fp32_matches_oracle():
     # the multi-loss gradient (Sec. II-B): readouts after both CGNN iterations, one dllr each
     _grad_case(0, 1e-4, 0.9999999, variant=7, multi=True)
