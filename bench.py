@@ -44,6 +44,12 @@ def cpu_baseline(w, weights, net_args, budget_s):
         cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu_model)
+    except OSError:  # pragma: no cover
+        pass
     net = cgnn.NetConfig(*net_args)
     W = cgnn.unflatten(weights.astype(np.float64), net)
     cfg = slot_sim.SimConfig(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"],
@@ -58,6 +64,7 @@ def cpu_baseline(w, weights, net_args, budget_s):
         t_total += time.perf_counter() - t0
         n += 1
     out = {"value": n / t_total, "unit": "slots/s", "cores": int(cores), "kind": "oracle",
+           "cpu_model": cpu_model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
            "sample": f"{n} slot(s) of {w['n_prb']} PRB x 14 x {w['n_ue']} UE x {w['n_ant']} ant, "
                      f"fp64 numpy LS + CGNN forward, {t_total:.1f} s"}
     # the LS + LMMSE + max-log oracle on one slot of the same workload
@@ -112,6 +119,7 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         if not no_autotune:
             L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=tune_cache)
+        variants = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}
         lat = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
         for _ in range(2):
             L.nrx_forward(model, dw, descs, y, llr, ws)      # first call captures the graph
@@ -130,14 +138,26 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
         ms = total / steps
         v = np.concatenate(lats)
         res = sum(12 * s["n_prb"] * 14 for s in shapes)
-        return {"workload": f"{len(shapes)} uneven slots: PRB 4-273, 1-4 UE, 4/8/16 ant, QPSK..256-QAM, bf16, "
-                            f"hipGraph replay",
-                "slots_per_s": len(shapes) / (ms * 1e-3), "res_per_s": res / (ms * 1e-3), "ms_per_step": ms,
-                "steps": steps, "latency_us_p50": float(np.percentile(v, 50)),
-                "latency_us_p99": float(np.percentile(v, 99)),
-                "conv_variants": {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}}
+        llr_bf16 = llr.clone()
     finally:
         L.nrx_model_destroy(model)
+    # the same batch once through the FP32 pass: LLR error of the timed BF16 pass against it
+    m32 = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, L.NRX_FP32)
+    try:
+        del ws
+        ws = torch.empty(L.nrx_workspace_bytes(m32, descs), dtype=torch.uint8, device="cuda")
+        llr32 = torch.zeros_like(llr)
+        L.nrx_forward(m32, dw, descs, y, llr32, ws)
+        torch.cuda.synchronize()
+        rel = (torch.linalg.vector_norm(llr_bf16 - llr32) / torch.linalg.vector_norm(llr32)).item()
+    finally:
+        L.nrx_model_destroy(m32)
+    return {"workload": f"{len(shapes)} uneven slots: PRB 4-273, 1-4 UE, 4/8/16 ant, QPSK..256-QAM, bf16, "
+                        f"hipGraph replay",
+            "slots_per_s": len(shapes) / (ms * 1e-3), "res_per_s": res / (ms * 1e-3), "ms_per_step": ms,
+            "steps": steps, "latency_us_p50": float(np.percentile(v, 50)),
+            "latency_us_p99": float(np.percentile(v, 99)),
+            "llr_rel_err_bf16_vs_fp32": rel, "conv_variants": variants}
 
 
 # kernel templates behind the conv variant indices of the library (kConvVariants), for reporting
@@ -375,7 +395,6 @@ def main():
 
     from paper_2409_02912_amd import libnrx as L
     from paper_2409_02912_amd import synth
-    from oracle import cgnn  # layout names only (weights are drawn by synth)
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib << 18
@@ -392,7 +411,9 @@ def main():
     descs, sz = L.make_slots(shapes, m_max)
     n_slots = len(shapes)
     net_args = (w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max)
-    layout = cgnn.layout(cgnn.NetConfig(*net_args))
+    m0 = L.nrx_model_create(*net_args)           # host-only: the weight layout the library uses
+    layout = [(n, sh) for n, _, sh in L.weight_layout(m0)]
+    L.nrx_model_destroy(m0)
     trained = os.path.exists(args.weights)
     weights = np.load(args.weights) if trained else synth.he_weights(layout, 0)
     dw = torch.from_numpy(weights).cuda()
@@ -414,6 +435,7 @@ def main():
 
     results = {}
     llrs = {}
+    flag_words = {}    # per-slot health words of each pass (non-finite input or LLRs)
     passes = [(L.NRX_BF16, "bf16")]
     if not args.no_fp8:
         passes.append((L.NRX_FP8, "fp8"))
@@ -476,6 +498,8 @@ def main():
         results[name] = {"ms_per_step": ms, "kernels": kern}
         progress(f"{name}: {ms:.3f} ms/step")
         llrs[name] = llr
+        flag_words[name] = torch.zeros(n_slots, dtype=torch.int32, device="cuda")
+        L.nrx_slot_flags(model, descs, ws, flag_words[name])
         if args.bf16_only:
             results[name]["batch1_ms"] = None
             L.nrx_model_destroy(model)
@@ -503,11 +527,16 @@ def main():
     nerr = torch.zeros(1, dtype=torch.int64, device="cuda")
     n_bits = sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in shapes)
     ber = {}
+    # fallback policy (Sec. III-B baseline beside the NRX): slots flagged by the pass get the LS + LMMSE LLRs
+    lws = torch.empty(L.lmmse_workspace_bytes(descs), dtype=torch.uint8, device="cuda")
+    flagged = {}
+    for name, l in llrs.items():
+        flagged[name] = int((flag_words[name] != 0).sum().item())
+        L.nrx_fallback_lmmse(descs, m_max, y, flag_words[name], l, lws, n0=n0)
     for name, l in llrs.items():
         L.nrx_bce(descs, m_max, l, bits, None, loss, nerr, bws)
         torch.cuda.synchronize()
         ber[name] = nerr.item() / n_bits
-    lws = torch.empty(L.lmmse_workspace_bytes(descs), dtype=torch.uint8, device="cuda")
     llm = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -531,6 +560,7 @@ def main():
     else:
         rel_llr = rel_llr8 = None
     ber["n_bits"] = n_bits
+    ber["slots_on_lmmse_fallback"] = flagged
 
     S = 12 * w["n_prb"]
     ms = results["bf16"]["ms_per_step"]

@@ -5,6 +5,11 @@ runs the hand-written backward kernels (nrx_backward) on the gradient of the LLR
 returns the gradient of the flat fp32 weight vector (Sec. II-B: the receiver is trained
 end to end on the BCE of the coded bits).  The received grid is an input, not a
 parameter, so it gets no gradient.
+
+All calls of one Nrx share its workspace, which holds the activations of the last
+forward only: each forward records the library's sequence token and its backward
+checks it (nrx_check_token), so a backward whose activations were overwritten by a
+later forward raises instead of returning a wrong gradient.
 """
 import torch
 
@@ -17,12 +22,14 @@ class NrxFunction(torch.autograd.Function):
         llr = torch.empty(n_llr, dtype=torch.float32, device=w.device)
         L.nrx_forward(model, w, slots, y, llr, ws, save_acts=True)
         ctx.model, ctx.slots, ctx.ws = model, slots, ws
+        ctx.token = L.nrx_saved_token(model)
         ctx.save_for_backward(w)
         return llr
 
     @staticmethod
     def backward(ctx, dllr):
         (w,) = ctx.saved_tensors
+        L.nrx_check_token(ctx.model, ctx.ws, ctx.token)
         dw = torch.empty_like(w)
         L.nrx_backward(ctx.model, w, ctx.slots, dllr.contiguous(), dw, ctx.ws)
         return dw, None, None, None, None, None

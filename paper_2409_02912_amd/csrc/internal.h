@@ -88,14 +88,17 @@ void launch_prep(const float *w, const PrepJob *jobs, int n_jobs, int64_t total,
                  float *fields, hipStream_t st);
 
 // Front end: DMRS generation, LS pair estimates, interpolation + feature rows.
-void launch_dmrs(const SlotGeo *geo, int n_slots, float2 *dmrs, hipStream_t st);
+// slot_mask (nullable, device, one word per slot): when given, slots whose word is 0 are skipped.
+void launch_dmrs(const SlotGeo *geo, int n_slots, float2 *dmrs, hipStream_t st,
+                 const unsigned int *slot_mask = nullptr);
 void launch_ls_pairs(const SlotGeo *geo, int n_slots, int max_pairs_total, const float2 *y,
                      const float2 *dmrs, float2 *pairs, const int64_t *pair_off, int max_u_b_pairs,
-                     hipStream_t st);
+                     hipStream_t st, const unsigned int *slot_mask = nullptr);
 template <typename T>
 void launch_features(const SlotGeo *geo, const int64_t *re_base, int n_slots, int64_t n_re,
                      const float2 *y, const float2 *pairs, const int64_t *pair_off, int model_B,
-                     int cx, T *X, float2 *h_out, hipStream_t st);
+                     int cx, T *X, float2 *h_out, hipStream_t st, const unsigned int *slot_mask = nullptr,
+                     unsigned int *slot_flags = nullptr);   // OR-ed with 4 for a slot whose y is not all finite
 
 // Message passing and readout.
 template <typename T>
@@ -115,6 +118,8 @@ struct MlpArgs {
   unsigned int *amax;             // MP: max |aggregate| (float bits, atomicMax) or null
   unsigned int *slot_done;        // readout: finished tiles per slot (zeroed by launch_stamp_start)
   unsigned long long *stamps;     // readout: wall-clock time at which each slot's last tile finished
+  unsigned int *slot_flags;       // readout: per-slot health word, OR-ed with bit 0 (LLR readout) or bit 1
+                                  // (ReadoutChEst) when a value the launch stores for the slot is not finite
   int chest;                      // readout: ReadoutChEst -- llr is a channel estimate in the h layout
                                   // ([s][t][u][b] complex at geo.h_off), outputs j < 2B of the slot
   int n_out;                      // readout: columns of w2 / b2 (0: m_max)
@@ -122,8 +127,12 @@ struct MlpArgs {
 };
 template <typename T>
 void launch_mp(const MlpArgs<T> &a, int grid, hipStream_t st);
-// Zeroes the per-slot tile counters and records the start time in stamps[n_slots].
-void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, int n_slots, hipStream_t st);
+// Zeroes the per-slot tile counters and health words (flags, nullable) and records the start time in
+// stamps[n_slots].
+void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, unsigned int *flags, int n_slots,
+                        hipStream_t st);
+// dst[i] = src[i], i < n (device words)
+void launch_copy_words(const unsigned int *src, unsigned int *dst, int n, hipStream_t st);
 // latency_us[i] = (stamps[i] - stamps[n]) / rate
 void launch_stamp_latency(const unsigned long long *stamps, int n_slots, double ticks_per_us, float *latency_us,
                           hipStream_t st);
@@ -131,8 +140,11 @@ template <typename T>
 void launch_readout(const MlpArgs<T> &a, int grid, hipStream_t st);
 
 // LMMSE + max-log judge.
+// slot_mask (nullable): only slots with a non-zero word are demapped, and their LLRs that are not finite
+// are written as 0 (the fallback of a flagged NRX slot).
 void launch_lmmse(const SlotGeo *geo, const int64_t *re_base, int n_slots, int64_t n_re, int m_max,
-                  const float2 *y, const float2 *h, const float *n0dev, float *llr, hipStream_t st);
+                  const float2 *y, const float2 *h, const float *n0dev, float *llr, hipStream_t st,
+                  const unsigned int *slot_mask = nullptr);
 
 // Slot simulator.
 struct SimParams {

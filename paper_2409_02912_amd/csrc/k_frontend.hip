@@ -38,9 +38,10 @@ __device__ void gold_bits(uint32_t c_init, int n, uint8_t *out) {
   }
 }
 
-__global__ void dmrs_kernel(const SlotGeo *geo, float2 *dmrs) {
+__global__ void dmrs_kernel(const SlotGeo *geo, float2 *dmrs, const unsigned int *slot_mask) {
   __shared__ uint8_t bits[2 * 275 * 12];
   const int slot = blockIdx.x, li = blockIdx.y;
+  if (slot_mask && !slot_mask[slot]) return;
   const SlotGeo g = geo[slot];
   const int l = li ? NRX_DMRS1 : NRX_DMRS0;
   if (threadIdx.x == 0) {
@@ -57,8 +58,9 @@ __global__ void dmrs_kernel(const SlotGeo *geo, float2 *dmrs) {
 
 // pairs layout per slot: [l(2)][u][n][b]
 __global__ void ls_pairs_kernel(const SlotGeo *geo, const float2 *y, const float2 *dmrs, float2 *pairs,
-                                const int64_t *pair_off) {
+                                const int64_t *pair_off, const unsigned int *slot_mask) {
   const int slot = blockIdx.y;
+  if (slot_mask && !slot_mask[slot]) return;
   const SlotGeo g = geo[slot];
   const int np = g.S / 4, B = g.B, U = g.U;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,16 +85,18 @@ __global__ void ls_pairs_kernel(const SlotGeo *geo, const float2 *y, const float
 
 template <typename T>
 __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float2 *pairs, const int64_t *pair_off,
-                                int model_B, int cx, T *X, float2 *h_out) {
+                                int model_B, int cx, T *X, float2 *h_out, const unsigned int *slot_mask,
+                                unsigned int *slot_flags) {
   // one thread per (row, group of 8 input channels): the threads of a row write
   // its cx channels as adjacent 16/32-byte vectors, a wave a contiguous block
   const int slot = blockIdx.y;
+  if (slot_mask && !slot_mask[slot]) return;
   const SlotGeo g = geo[slot];
   const int S = g.S, U = g.U, B = g.B;
   const int ngrp = X ? cx / 8 : 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = (int)(e / ngrp), grp = (int)(e - (int64_t)r * ngrp);   // row within the slot, channel group
-  if (r >= S * 14 * U) return;
+  if (r >= S * 14 * U) return;   // e grows with the lane: a wave's lane 0 is in range if any lane is
   const int s = r / (14 * U);
   const int rem = r - s * 14 * U;
   const int t = rem / U, u = rem - t * U;
@@ -123,6 +127,14 @@ __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float
   if (h_out && grp == 0) {
     for (int b = 0; b < B; ++b) h_out[g.h_off + (((int64_t)s * 14 + t) * U + u) * B + b] = hval(b);
   }
+  if (slot_flags) {
+    // health word of the slot: bit 2 when a received sample is not finite (every sample is a
+    // feature of the rows of its RE; the UE-0, group-0 thread of each RE checks its B antennas)
+    bool bad = false;
+    if (u == 0 && grp == 0)
+      for (int b = 0; b < B; ++b) bad |= !__builtin_isfinite(yr[b].x) || !__builtin_isfinite(yr[b].y);
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&slot_flags[slot], 4u);
+  }
   if (X) {
     // channel order [Re y | Im y | Re h | Im h], each block model_B wide, zero padded to cx
     float f[8];
@@ -142,25 +154,28 @@ __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float
 
 }  // namespace
 
-void launch_dmrs(const SlotGeo *geo, int n_slots, float2 *dmrs, hipStream_t st) {
-  hipLaunchKernelGGL(dmrs_kernel, dim3(n_slots, 2), dim3(256), 0, st, geo, dmrs);
+void launch_dmrs(const SlotGeo *geo, int n_slots, float2 *dmrs, hipStream_t st, const unsigned int *slot_mask) {
+  hipLaunchKernelGGL(dmrs_kernel, dim3(n_slots, 2), dim3(256), 0, st, geo, dmrs, slot_mask);
 }
 
 void launch_ls_pairs(const SlotGeo *geo, int n_slots, int max_pairs_total, const float2 *y, const float2 *dmrs,
-                     float2 *pairs, const int64_t *pair_off, int, hipStream_t st) {
+                     float2 *pairs, const int64_t *pair_off, int, hipStream_t st, const unsigned int *slot_mask) {
   dim3 grid((max_pairs_total + 255) / 256, n_slots);
-  hipLaunchKernelGGL(ls_pairs_kernel, grid, dim3(256), 0, st, geo, y, dmrs, pairs, pair_off);
+  hipLaunchKernelGGL(ls_pairs_kernel, grid, dim3(256), 0, st, geo, y, dmrs, pairs, pair_off, slot_mask);
 }
 
 template <typename T>
 void launch_features(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_rows, const float2 *y,
                      const float2 *pairs, const int64_t *pair_off, int model_B, int cx, T *X, float2 *h_out,
-                     hipStream_t st) {
+                     hipStream_t st, const unsigned int *slot_mask, unsigned int *slot_flags) {
   const int64_t threads = max_rows * (X ? cx / 8 : 1);   // one per (row, 8-channel group)
   dim3 grid((unsigned)((threads + 255) / 256), n_slots);
-  hipLaunchKernelGGL(features_kernel<T>, grid, dim3(256), 0, st, geo, y, pairs, pair_off, model_B, cx, X, h_out);
+  hipLaunchKernelGGL(features_kernel<T>, grid, dim3(256), 0, st, geo, y, pairs, pair_off, model_B, cx, X, h_out,
+                     slot_mask, slot_flags);
 }
 template void launch_features<float>(const SlotGeo *, const int64_t *, int, int64_t, const float2 *, const float2 *,
-                                     const int64_t *, int, int, float *, float2 *, hipStream_t);
+                                     const int64_t *, int, int, float *, float2 *, hipStream_t,
+                                     const unsigned int *, unsigned int *);
 template void launch_features<bf16_t>(const SlotGeo *, const int64_t *, int, int64_t, const float2 *,
-                                      const float2 *, const int64_t *, int, int, bf16_t *, float2 *, hipStream_t);
+                                      const float2 *, const int64_t *, int, int, bf16_t *, float2 *, hipStream_t,
+                                      const unsigned int *, unsigned int *);

@@ -39,8 +39,9 @@ __device__ void axis_llr(float z, float inv_var, int K, float scale, float *out 
 }
 
 __global__ void lmmse_kernel(const SlotGeo *geo, int m_max, const float2 *y, const float2 *h, const float *n0dev,
-                             float *llr) {
+                             float *llr, const unsigned int *slot_mask) {
   const int slot = blockIdx.y;
+  if (slot_mask && !slot_mask[slot]) return;
   const SlotGeo g = geo[slot];
   const int S = g.S, U = g.U, B = g.B;
   const int re = blockIdx.x * blockDim.x + threadIdx.x;
@@ -131,6 +132,8 @@ __global__ void lmmse_kernel(const SlotGeo *geo, int m_max, const float2 *y, con
     for (int j = 0; j < m_max; ++j) {
       float v = 0.f;
       if (j < m) v = (j & 1) ? li[j >> 1] : lr[j >> 1];
+      // fallback of a flagged slot: what LMMSE cannot produce either is an erasure
+      if (slot_mask && !isfinite(v)) v = 0.f;
       dst[j] = v;
     }
   }
@@ -139,7 +142,7 @@ __global__ void lmmse_kernel(const SlotGeo *geo, int m_max, const float2 *y, con
 }  // namespace
 
 void launch_lmmse(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_re, int m_max, const float2 *y,
-                  const float2 *h, const float *n0dev, float *llr, hipStream_t st) {
+                  const float2 *h, const float *n0dev, float *llr, hipStream_t st, const unsigned int *slot_mask) {
   dim3 grid((unsigned)((max_re + 127) / 128), n_slots);
-  hipLaunchKernelGGL(lmmse_kernel, grid, dim3(128), 0, st, geo, m_max, y, h, n0dev, llr);
+  hipLaunchKernelGGL(lmmse_kernel, grid, dim3(128), 0, st, geo, m_max, y, h, n0dev, llr, slot_mask);
 }

@@ -437,6 +437,7 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
       for (int mb = 0; mb < MBW; ++mb)
         o[mb] = mfma_bf16(ld16(t + apos(rbase + mb * 16 + lr, 4 * c + lk)), bf, o[mb]);
     }
+    bool bad = false;   // a stored value that is not finite (per-slot health word)
     if (a.chest) {
       // ReadoutChEst: row R = (s * 14 + t) * U + u is entry R of the slot's h layout
       const int Bs = ldc(&a.geo[tl.slot].B);
@@ -447,7 +448,11 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int r = rbase + mb * 16 + 4 * lk + i;
-            if (r < tl.nrows) a.llr[(h_off + (int64_t)(tl.row0 + r) * Bs) * 2 + lr] = o[mb][i] + b2;
+            const float v = o[mb][i] + b2;
+            if (r < tl.nrows) {
+              a.llr[(h_off + (int64_t)(tl.row0 + r) * Bs) * 2 + lr] = v;
+              bad |= !__builtin_isfinite(v);
+            }
           }
       }
     } else if (lr < M) {
@@ -466,11 +471,15 @@ __global__ __launch_bounds__(64 * NW, 1) void readout_lds_kernel(MlpArgs<bf16_t>
             const int rem = R - s * 14 * U;
             const int tt = rem / U, u = rem - tt * U;
             const int mu = u == 0 ? mu0 : (u == 1 ? mu1 : (u == 2 ? mu2 : mu3));
-            if (!a.only_m || mu == a.only_m)
-              a.llr[llr_off + (((int64_t)u * 14 + tt) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
+            if (!a.only_m || mu == a.only_m) {
+              const float v = lr < mu ? o[mb][i] + b2 : 0.f;
+              a.llr[llr_off + (((int64_t)u * 14 + tt) * S + s) * M + lr] = v;
+              bad |= !__builtin_isfinite(v);
+            }
           }
         }
     }
+    if (a.slot_flags && __ballot(bad) != 0ull && lane == 0) atomicOr(&a.slot_flags[tl.slot], a.chest ? 2u : 1u);
     if (a.slot_done) {
       dma_barrier();   // every wave of the tile has issued its stores
       if (tid == 0) {
@@ -537,6 +546,7 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
         o[mb] = mma<T>::run(OpTile<T>::frag(lds, wave * 16 * MLP_MB + mb * 16 + lr, c, lk), bf, o[mb]);
     }
     const int U = g.U, S = g.S;
+    bool bad = false;   // a stored value that is not finite (per-slot health word)
     if (a.chest) {
       // ReadoutChEst: row R = (s * 14 + t) * U + u is entry R of the slot's h layout
       if (lr < 2 * g.B) {
@@ -545,7 +555,11 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int r = wave * 16 * MLP_MB + mb * 16 + 4 * lk + i;
-            if (r < tl.nrows) a.llr[(g.h_off + (int64_t)(tl.row0 + r) * g.B) * 2 + lr] = o[mb][i] + b2;
+            const float v = o[mb][i] + b2;
+            if (r < tl.nrows) {
+              a.llr[(g.h_off + (int64_t)(tl.row0 + r) * g.B) * 2 + lr] = v;
+              bad |= !__builtin_isfinite(v);
+            }
           }
       }
     } else if (lr < M) {
@@ -560,11 +574,15 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
             const int rem = R - s * 14 * U;
             const int t = rem / U, u = rem - t * U;
             const int mu = a.geo[tl.slot].m[u];
-            if (!a.only_m || mu == a.only_m)
-              a.llr[g.llr_off + (((int64_t)u * 14 + t) * S + s) * M + lr] = lr < mu ? o[mb][i] + b2 : 0.f;
+            if (!a.only_m || mu == a.only_m) {
+              const float v = lr < mu ? o[mb][i] + b2 : 0.f;
+              a.llr[g.llr_off + (((int64_t)u * 14 + t) * S + s) * M + lr] = v;
+              bad |= !__builtin_isfinite(v);
+            }
           }
         }
     }
+    if (a.slot_flags && __ballot(bad) != 0ull && lane == 0) atomicOr(&a.slot_flags[tl.slot], a.chest ? 2u : 1u);
     __syncthreads();   // LDS reads done before the next tile overwrites it
     if (a.slot_done && tid == 0) {
       // the workgroup that finishes a slot's last readout tile stamps the time (its LLR
@@ -575,9 +593,17 @@ __global__ __launch_bounds__(256) void readout_kernel(MlpArgs<T> a) {
   }
 }
 
-__global__ void stamp_start_kernel(unsigned int *slot_done, unsigned long long *stamps, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) slot_done[i] = 0u;
+__global__ void stamp_start_kernel(unsigned int *slot_done, unsigned long long *stamps, unsigned int *flags, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    slot_done[i] = 0u;
+    if (flags) flags[i] = 0u;
+  }
   if (threadIdx.x == 0) stamps[n] = wall_clock64();
+}
+
+__global__ void copy_words_kernel(const unsigned int *src, unsigned int *dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 __global__ void stamp_latency_kernel(const unsigned long long *stamps, int n, double ticks_per_us, float *lat) {
@@ -587,8 +613,12 @@ __global__ void stamp_latency_kernel(const unsigned long long *stamps, int n, do
 
 }  // namespace
 
-void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, int n, hipStream_t st) {
-  hipLaunchKernelGGL(stamp_start_kernel, dim3(1), dim3(256), 0, st, slot_done, stamps, n);
+void launch_stamp_start(unsigned int *slot_done, unsigned long long *stamps, unsigned int *flags, int n,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(stamp_start_kernel, dim3(1), dim3(256), 0, st, slot_done, stamps, flags, n);
+}
+void launch_copy_words(const unsigned int *src, unsigned int *dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_words_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
 }
 void launch_stamp_latency(const unsigned long long *stamps, int n, double ticks_per_us, float *lat, hipStream_t st) {
   hipLaunchKernelGGL(stamp_latency_kernel, dim3((n + 255) / 256), dim3(256), 0, st, stamps, n, ticks_per_us, lat);

@@ -100,26 +100,50 @@ struct Plan {
   size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0, 0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
+  void *packed_geo = nullptr;    // lmmse_demap: pinned geometry copy with h offsets into its workspace
   ~Plan() {
+    // an asynchronous copy (or a graph replay) may still read the pinned tables
+    if (pinned || packed_geo) (void)hipDeviceSynchronize();
     if (pinned) (void)hipHostFree(pinned);
+    if (packed_geo) (void)hipHostFree(packed_geo);
   }
 };
+using PlanRef = std::shared_ptr<Plan>;
 
-uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
-  const unsigned char *c = (const unsigned char *)p;
-  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
-  return h;
-}
-
+// Plans are keyed on every descriptor field (compared in full on a hit) and kept for the
+// PLAN_CACHE_MAX most recently used batches; a model's graph or saved forward holds its plan alive
+// after eviction.
+constexpr size_t PLAN_CACHE_MAX = 256;
 struct PlanCache {
   std::mutex mu;
-  std::map<uint64_t, std::unique_ptr<Plan>> plans;
+  struct Entry { PlanRef plan; uint64_t used; };
+  std::map<std::vector<int64_t>, Entry> plans;
+  uint64_t tick = 0;
 };
 
 PlanCache g_plans;  // shared by model-free calls and models
 
+std::vector<int64_t> plan_key(const nrx_slot_desc *d, int n, int sim_taps) {
+  std::vector<int64_t> k;
+  k.reserve(2 + (size_t)n * 18);
+  k.push_back(n);
+  k.push_back(sim_taps);
+  for (int i = 0; i < n; ++i) {
+    const nrx_slot_desc &s = d[i];
+    int32_t n0b, offb;
+    memcpy(&n0b, &s.n0, 4);
+    memcpy(&offb, &s.snr_offset_db, 4);
+    const int64_t f[] = {s.n_prb, s.n_ant, s.n_ue, s.bits_per_sym[0], s.bits_per_sym[1], s.bits_per_sym[2],
+                         s.bits_per_sym[3], s.slot_number, s.n_id, s.n_scid, n0b, offb,
+                         s.y_offset, s.h_offset, s.llr_offset, s.bits_offset};
+    // UEs beyond n_ue do not take part: their bits_per_sym entries are not part of the key
+    for (int j = 0; j < 16; ++j) k.push_back((j >= 3 + s.n_ue && j < 7) ? 0 : f[j]);
+  }
+  return k;
+}
+
 // Validates descriptors and builds (or fetches) the plan.  max_ant bounds n_ant.
-nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int sim_taps, Plan **out) {
+nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int sim_taps, PlanRef *out) {
   if (!d || n <= 0) return fail(NRX_ERR_INVALID, "no slot descriptors");
   for (int i = 0; i < n; ++i) {
     const nrx_slot_desc &s = d[i];
@@ -137,15 +161,27 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
     if (s.y_offset < 0 || s.h_offset < 0 || s.llr_offset < 0 || s.bits_offset < 0)
       return fail(NRX_ERR_INVALID, "slot %d: negative offset", i);
     if (!(std::fabs(s.snr_offset_db) <= 60.f)) return fail(NRX_ERR_SHAPE, "slot %d: snr_offset_db outside -60..60", i);
+    if (s.dmrs_sym_mask != 0 && s.dmrs_sym_mask != ((1u << NRX_DMRS0) | (1u << NRX_DMRS1)))
+      return fail(NRX_ERR_UNSUPPORTED, "slot %d: dmrs_sym_mask 0x%x: only DMRS on symbols 2 and 11 is implemented", i,
+                  s.dmrs_sym_mask);
   }
-  uint64_t key = fnv(d, sizeof(nrx_slot_desc) * (size_t)n);
-  key = fnv(&n, sizeof n, key);
-  key = fnv(&sim_taps, sizeof sim_taps, key);
+  std::vector<int64_t> key = plan_key(d, n, sim_taps);
+  PlanRef evicted;   // released after the lock (its destructor synchronises the device)
   std::lock_guard<std::mutex> lk(g_plans.mu);
   auto it = g_plans.plans.find(key);
-  if (it != g_plans.plans.end()) { *out = it->second.get(); return NRX_OK; }
-  if (g_plans.plans.size() >= 4096) return fail(NRX_ERR_UNSUPPORTED, "too many distinct batch shapes cached");
-  auto P = std::make_unique<Plan>();
+  if (it != g_plans.plans.end()) {
+    it->second.used = ++g_plans.tick;
+    *out = it->second.plan;
+    return NRX_OK;
+  }
+  if (g_plans.plans.size() >= PLAN_CACHE_MAX) {
+    auto lru = g_plans.plans.begin();
+    for (auto e = g_plans.plans.begin(); e != g_plans.plans.end(); ++e)
+      if (e->second.used < lru->second.used) lru = e;
+    evicted = std::move(lru->second.plan);
+    g_plans.plans.erase(lru);
+  }
+  auto P = std::make_shared<Plan>();
   P->n = n;
   int64_t row = 0, dm = 0, pr = 0, tp = 0;
   for (int i = 0; i < n; ++i) {
@@ -217,8 +253,8 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   memcpy(b + P->off_rt, P->rt.data(), sizeof(Tile) * P->rt.size());
   memcpy(b + P->off_pair, P->pair_off.data(), sizeof(int64_t) * P->pair_off.size());
   memcpy(b + P->off_tap, P->tap_off.data(), sizeof(int64_t) * P->tap_off.size());
-  *out = P.get();
-  g_plans.plans[key] = std::move(P);
+  *out = P;
+  g_plans.plans[std::move(key)] = PlanCache::Entry{std::move(P), ++g_plans.tick};
   return NRX_OK;
 }
 
@@ -281,9 +317,12 @@ struct GraphKey {
   }
 };
 
+constexpr size_t GRAPH_CACHE_MAX = 64;   // captured forward graphs kept per model (least recently used evicted)
 struct Graphs {
   hipStream_t cap = nullptr;
-  std::map<GraphKey, hipGraphExec_t> execs;
+  struct Entry { hipGraphExec_t exec; PlanRef plan; uint64_t used; };   // the plan's pinned tables feed the graph
+  std::map<GraphKey, Entry> execs;
+  uint64_t tick = 0;
 };
 
 }  // namespace
@@ -339,7 +378,8 @@ struct nrx_model {
   int n_iter = 0;
   // last save_acts forward (for nrx_backward): its workspace, batch, depth and readouts kept
   const void *saved_ws = nullptr;
-  const Plan *saved_plan = nullptr;
+  PlanRef saved_plan;                   // held: an evicted plan's address is not reused while it is saved
+  int64_t save_seq = 0;                 // save_acts forwards run so far (the token of the last one)
   int saved_iters = 0;
   bool saved_multi = false;
   bool saved_chest = false;
@@ -563,7 +603,8 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
 extern "C" nrx_status nrx_model_destroy(nrx_model *m) {
   if (!m) return fail(NRX_ERR_INVALID, "null model");
   if (m->graphs) {
-    for (auto &kv : m->graphs->execs) (void)hipGraphExecDestroy(kv.second);
+    if (!m->graphs->execs.empty()) (void)hipDeviceSynchronize();   // no replay may still run
+    for (auto &kv : m->graphs->execs) (void)hipGraphExecDestroy(kv.second.exec);
     if (m->graphs->cap) (void)hipStreamDestroy(m->graphs->cap);
     delete m->graphs;
   }
@@ -614,7 +655,7 @@ std::vector<int> iteration_ends(const nrx_model_config &c) {
 }
 
 struct FwdLayout {
-  size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps;
+  size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps, flags;   // the same for save and inference
   size_t h8 = 0, a8 = 0, agg8 = 0, w8 = 0, wsc = 0, f8jobs = 0, amax = 0;   // FP8 models
   std::vector<size_t> h;      // h_0 .. h_C (inference: one buffer)
   std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
@@ -645,6 +686,7 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   L.X = o; o = align256(o + (size_t)P->rows * m->cx * ts);
   L.done = o; o = align256(o + (size_t)P->n * 4);
   L.stamps = o; o = align256(o + (size_t)(P->n + 1) * 8);
+  L.flags = o; o = align256(o + (size_t)P->n * 4);
   const int C = m->cfg.n_blocks, R = m->cfg.n_rounds;
   if (m->fp8) {
     const size_t act8 = align256((size_t)P->rows * NRX_D);
@@ -738,14 +780,15 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   float2 *dmrs = (float2 *)(ws + L.dmrs);
   float2 *pairs = (float2 *)(ws + L.pairs);
   T *X = (T *)(ws + L.X);
-  launch_stamp_start((unsigned int *)(ws + L.done), (unsigned long long *)(ws + L.stamps), P->n, st);
+  unsigned int *slot_flags = (unsigned int *)(ws + L.flags);
+  launch_stamp_start((unsigned int *)(ws + L.done), (unsigned long long *)(ws + L.stamps), slot_flags, P->n, st);
   {
     ProfMark pm(m, NRX_K_FRONTEND, st);
     launch_prep<T>(w, (const PrepJob *)(ws + L.jobs), (int)m->jobs.size(), m->prep_total, wprep, fields, st);
     launch_dmrs(D.geo, P->n, dmrs, st);
     launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
     launch_features<T>(D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, m->cfg.n_ant, m->cx,
-                       X, (float2 *)h_ls, st);
+                       X, (float2 *)h_ls, st, nullptr, slot_flags);
   }
   // FP8 models: E4M3 block-conv operands (or, while calibrating, BF16 convs that record max |activation|)
   const bool f8 = m->fp8 && !m->calibrating && !save;
@@ -836,6 +879,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       const bool fin = last && i + 1 == ros_run.size();
       ra.slot_done = fin ? (unsigned int *)(ws + L.done) : nullptr;
       ra.stamps = fin ? (unsigned long long *)(ws + L.stamps) : nullptr;
+      ra.slot_flags = slot_flags;
       ProfMark pm(m, NRX_K_READOUT, st);
       launch_readout<T>(ra, grid_mlp, st);
     }
@@ -933,13 +977,14 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
 
 namespace {
 template <typename F>
-nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipStream_t st);
+nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F run, hipStream_t st);
 }  // namespace
 
 extern "C" size_t nrx_workspace_bytes(nrx_model *m, const nrx_slot_desc *slots, int32_t n, int32_t save_acts) {
   if (!m) return 0;
-  Plan *P;
-  if (get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P) != NRX_OK) return 0;
+  PlanRef PR;
+  if (get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR) != NRX_OK) return 0;
+  Plan *P = PR.get();
   return fwd_layout(m, P, save_acts != 0).total;
 }
 
@@ -948,8 +993,9 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
                          float *h_ls, float *llr, int64_t llr_stride, int32_t save_acts, void *ws, size_t ws_bytes,
                          hipStream_t st, float *hest = nullptr, int64_t h_stride = 0) {
   if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   if (m->fp8 && save_acts) return fail(NRX_ERR_UNSUPPORTED, "FP8 models are inference-only (train in BF16)");
   if (m->cfg.d != NRX_D && save_acts) return fail(NRX_ERR_UNSUPPORTED, "training needs d = 128 in this build");
@@ -967,7 +1013,7 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
     uint64_t vs = 0;
     for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (4 * c);
-    s = graph_forward(m, P,
+    s = graph_forward(m, PR,
                       GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride, hest,
                                h_stride},
                       run, st);
@@ -977,7 +1023,8 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
   if (s == NRX_OK && save_acts) {
     std::lock_guard<std::mutex> lk(m->mu);
     m->saved_ws = ws;
-    m->saved_plan = P;
+    m->saved_plan = PR;
+    ++m->save_seq;
     m->saved_iters = iters;
     m->saved_multi = llr_stride > 0;
     m->saved_chest = hest != nullptr;
@@ -1024,13 +1071,17 @@ extern "C" int32_t nrx_num_iterations(const nrx_model *m) {
 
 namespace {
 template <typename F>
-nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipStream_t st) {
+nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F run, hipStream_t st) {
+  Plan *P = PR.get();
   hipGraphExec_t exec = nullptr;
   {
     std::lock_guard<std::mutex> lk(m->mu);
     if (!m->graphs) m->graphs = new Graphs();
     auto it = m->graphs->execs.find(key);
-    if (it != m->graphs->execs.end()) exec = it->second;
+    if (it != m->graphs->execs.end()) {
+      exec = it->second.exec;
+      it->second.used = ++m->graphs->tick;
+    }
   }
   if (!exec) {
     // host-side allocations happen before the capture
@@ -1055,7 +1106,15 @@ nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipS
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(NRX_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     std::lock_guard<std::mutex> lk(m->mu);
-    m->graphs->execs[key] = exec;
+    if (m->graphs->execs.size() >= GRAPH_CACHE_MAX) {
+      auto lru = m->graphs->execs.begin();
+      for (auto e = m->graphs->execs.begin(); e != m->graphs->execs.end(); ++e)
+        if (e->second.used < lru->second.used) lru = e;
+      (void)hipDeviceSynchronize();   // no replay of the evicted graph may still run
+      (void)hipGraphExecDestroy(lru->second.exec);
+      m->graphs->execs.erase(lru);
+    }
+    m->graphs->execs[key] = Graphs::Entry{exec, PR, ++m->graphs->tick};
   }
   HIPCHK(hipGraphLaunch(exec, st));
   return NRX_OK;
@@ -1065,8 +1124,9 @@ nrx_status graph_forward(nrx_model *m, Plan *P, const GraphKey &key, F run, hipS
 extern "C" nrx_status nrx_slot_latency(nrx_model *m, const nrx_slot_desc *slots, int32_t n, const void *ws,
                                        float *latency_us, hipStream_t st) {
   if (!m || !ws || !latency_us) return fail(NRX_ERR_INVALID, "null argument");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const FwdLayout L = fwd_layout(m, P, false);
   int dev = 0, khz = 0;
@@ -1075,6 +1135,37 @@ extern "C" nrx_status nrx_slot_latency(nrx_model *m, const nrx_slot_desc *slots,
   if (khz <= 0) return fail(NRX_ERR_HIP, "wall clock rate unavailable");
   launch_stamp_latency((const unsigned long long *)((const char *)ws + L.stamps), P->n, khz / 1000.0, latency_us, st);
   HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" nrx_status nrx_slot_flags(nrx_model *m, const nrx_slot_desc *slots, int32_t n, const void *ws,
+                                     size_t ws_bytes, uint32_t *flags, hipStream_t st) {
+  if (!m || !ws || !flags) return fail(NRX_ERR_INVALID, "null argument");
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
+  if (s != NRX_OK) return s;
+  const FwdLayout L = fwd_layout(m, P, false);   // the flags sit at the same offset in the training layout
+  if (ws_bytes < L.flags + (size_t)P->n * 4)
+    return fail(NRX_ERR_WORKSPACE, "workspace %zu bytes is not a forward workspace of this batch", ws_bytes);
+  launch_copy_words((const unsigned int *)((const char *)ws + L.flags), (unsigned int *)flags, P->n, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
+}
+
+extern "C" int64_t nrx_saved_token(const nrx_model *m) {
+  if (!m) return 0;
+  std::lock_guard<std::mutex> lk(const_cast<nrx_model *>(m)->mu);
+  return m->saved_ws ? m->save_seq : 0;
+}
+
+extern "C" nrx_status nrx_check_token(const nrx_model *m, const void *ws, int64_t token) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  std::lock_guard<std::mutex> lk(const_cast<nrx_model *>(m)->mu);
+  if (!m->saved_ws || m->save_seq == 0) return fail(NRX_ERR_INVALID, "no save_acts forward has run on this model");
+  if (token != m->save_seq || ws != m->saved_ws)
+    return fail(NRX_ERR_INVALID, "stale activations: the backward belongs to forward %lld, the workspace holds forward "
+                "%lld", (long long)token, (long long)m->save_seq);
   return NRX_OK;
 }
 
@@ -1141,8 +1232,9 @@ extern "C" nrx_status nrx_autotune(nrx_model *m, const float *w, const nrx_slot_
                                    const float *y, float *llr, void *ws, size_t ws_bytes, const char *cache_path,
                                    hipStream_t st) {
   if (!m) return fail(NRX_ERR_INVALID, "null model");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const int classes[4] = {NRX_K_CONV_IN, NRX_K_CONV_A, NRX_K_CONV_A_MP, NRX_K_CONV_B};
   // cached choices
@@ -1447,13 +1539,14 @@ nrx_status backward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slo
                           int64_t llr_stride, float *dw, void *ws, size_t ws_bytes, hipStream_t st,
                           const float *dhest = nullptr, int64_t h_stride = 0) {
   if (!m || !w || !dllr || !dw || !ws) return fail(NRX_ERR_INVALID, "null argument");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   int iters;
   {
     std::lock_guard<std::mutex> lk(m->mu);
-    if (m->saved_ws != ws || m->saved_plan != P)
+    if (m->saved_ws != ws || m->saved_plan.get() != P)
       return fail(NRX_ERR_INVALID, "no save_acts forward of this batch on this workspace");
     if (m->saved_multi != (llr_stride > 0))
       return fail(NRX_ERR_INVALID, "the saved forward %s per-iteration readouts",
@@ -1513,20 +1606,21 @@ FrontLayout front_layout(const Plan *P, bool need_h) {
 }  // namespace
 
 extern "C" size_t lmmse_workspace_bytes(const nrx_slot_desc *slots, int32_t n) {
-  Plan *P;
-  if (get_plan(slots, n, 16, 8, 0, &P) != NRX_OK) return 0;
+  PlanRef PR;
+  if (get_plan(slots, n, 16, 8, 0, &PR) != NRX_OK) return 0;
+  Plan *P = PR.get();
   return front_layout(P, true).total + align256(sizeof(SlotGeo) * (size_t)n);
 }
 
 static nrx_status ls_into(const Plan *P, const FrontLayout &L, const float *y, float *h, const SlotGeo *geo_h,
-                          char *ws, hipStream_t st) {
+                          char *ws, hipStream_t st, const unsigned int *slot_mask = nullptr) {
   const Dev D = dev_tables(P, ws + L.meta);
   float2 *dmrs = (float2 *)(ws + L.dmrs);
   float2 *pairs = (float2 *)(ws + L.pairs);
-  launch_dmrs(D.geo, P->n, dmrs, st);
-  launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st);
+  launch_dmrs(D.geo, P->n, dmrs, st, slot_mask);
+  launch_ls_pairs(D.geo, P->n, (int)P->max_pairs, (const float2 *)y, dmrs, pairs, D.pair_off, 0, st, slot_mask);
   launch_features<float>(geo_h ? geo_h : D.geo, nullptr, P->n, P->max_rows, (const float2 *)y, pairs, D.pair_off, 16,
-                         0, (float *)nullptr, (float2 *)h, st);
+                         0, (float *)nullptr, (float2 *)h, st, slot_mask);
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }
@@ -1534,8 +1628,9 @@ static nrx_status ls_into(const Plan *P, const FrontLayout &L, const float *y, f
 extern "C" nrx_status nrx_ls_estimate(const nrx_slot_desc *slots, int32_t n, const float *y, float *h, void *ws,
                                       size_t ws_bytes, hipStream_t st) {
   if (!y || !h || !ws) return fail(NRX_ERR_INVALID, "null argument");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, 16, 8, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, 16, 8, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const FrontLayout L = front_layout(P, false);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
@@ -1543,21 +1638,17 @@ extern "C" nrx_status nrx_ls_estimate(const nrx_slot_desc *slots, int32_t n, con
   return ls_into(P, L, y, h, nullptr, (char *)ws, st);
 }
 
-namespace {
-// geometry copy whose h offsets point into a packed internal buffer
-struct PackedGeo {
-  std::mutex mu;
-  std::map<const Plan *, void *> pinned;
-};
-PackedGeo g_packed;
-}  // namespace
 
-extern "C" nrx_status lmmse_demap(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y, const float *h,
-                                  const float *n0dev, float *llr, void *ws, size_t ws_bytes, hipStream_t st) {
+namespace {
+// LS (when h is null) + LMMSE + max-log over the batch, or with slot_mask only over its flagged slots
+nrx_status lmmse_impl(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y, const float *h,
+                      const float *n0dev, const unsigned int *slot_mask, float *llr, void *ws, size_t ws_bytes,
+                      hipStream_t st) {
   if (!y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
   if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
-  Plan *P;
-  nrx_status s = get_plan(slots, n, 16, m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, 16, m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const FrontLayout L = front_layout(P, h == nullptr);
   const size_t need = L.total + align256(sizeof(SlotGeo) * (size_t)n);
@@ -1571,9 +1662,8 @@ extern "C" nrx_status lmmse_demap(const nrx_slot_desc *slots, int32_t n, int32_t
     // packed internal estimate: a geometry copy with h offsets into the workspace buffer
     void *pg;
     {
-      std::lock_guard<std::mutex> lk(g_packed.mu);
-      auto it = g_packed.pinned.find(P);
-      if (it == g_packed.pinned.end()) {
+      std::lock_guard<std::mutex> lk(g_plans.mu);
+      if (!P->packed_geo) {
         if (hipHostMalloc(&pg, sizeof(SlotGeo) * n, hipHostMallocDefault) != hipSuccess)
           return fail(NRX_ERR_HIP, "hipHostMalloc failed");
         SlotGeo *gp = (SlotGeo *)pg;
@@ -1583,26 +1673,40 @@ extern "C" nrx_status lmmse_demap(const nrx_slot_desc *slots, int32_t n, int32_t
           gp[i].h_off = off;
           off += (int64_t)gp[i].S * 14 * gp[i].U * gp[i].B;
         }
-        g_packed.pinned[P] = pg;
-      } else {
-        pg = it->second;
+        P->packed_geo = pg;
       }
+      pg = P->packed_geo;
     }
     SlotGeo *gdev = (SlotGeo *)(w + L.total);
     HIPCHK(hipMemcpyAsync(gdev, pg, sizeof(SlotGeo) * n, hipMemcpyHostToDevice, st));
-    s = ls_into(P, L, y, (float *)(w + L.h), gdev, w, st);
+    s = ls_into(P, L, y, (float *)(w + L.h), gdev, w, st, slot_mask);
     if (s != NRX_OK) return s;
     geo = gdev;
     hh = (const float *)(w + L.h);
   }
-  launch_lmmse(geo, nullptr, P->n, P->max_re, m_max, (const float2 *)y, (const float2 *)hh, n0dev, llr, st);
+  launch_lmmse(geo, nullptr, P->n, P->max_re, m_max, (const float2 *)y, (const float2 *)hh, n0dev, llr, st,
+               slot_mask);
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }
+}  // namespace
+
+extern "C" nrx_status lmmse_demap(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y, const float *h,
+                                  const float *n0dev, float *llr, void *ws, size_t ws_bytes, hipStream_t st) {
+  return lmmse_impl(slots, n, m_max, y, h, n0dev, nullptr, llr, ws, ws_bytes, st);
+}
+
+extern "C" nrx_status nrx_fallback_lmmse(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y,
+                                         const float *h, const float *n0dev, const uint32_t *flags, float *llr,
+                                         void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!flags) return fail(NRX_ERR_INVALID, "null flags");
+  return lmmse_impl(slots, n, m_max, y, h, n0dev, (const unsigned int *)flags, llr, ws, ws_bytes, st);
+}
 
 extern "C" size_t nrx_bce_workspace_bytes(const nrx_slot_desc *slots, int32_t n, int32_t m_max) {
-  Plan *P;
-  if (get_plan(slots, n, 16, m_max, 0, &P) != NRX_OK) return 0;
+  PlanRef PR;
+  if (get_plan(slots, n, 16, m_max, 0, &PR) != NRX_OK) return 0;
+  Plan *P = PR.get();
   const int64_t nb = (P->max_ute + 255) / 256;
   return align256(P->meta_bytes) + align256((size_t)n * nb * 16);
 }
@@ -1612,8 +1716,9 @@ extern "C" nrx_status nrx_bce(const nrx_slot_desc *slots, int32_t n, int32_t m_m
                               size_t ws_bytes, hipStream_t st) {
   if (!llr || !bits || !ws) return fail(NRX_ERR_INVALID, "null argument");
   if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
-  Plan *P;
-  nrx_status s = get_plan(slots, n, 16, m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, 16, m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const int64_t nb = (P->max_ute + 255) / 256;
   const size_t need = align256(P->meta_bytes) + align256((size_t)n * nb * 16);
@@ -1629,8 +1734,9 @@ extern "C" nrx_status nrx_bce(const nrx_slot_desc *slots, int32_t n, int32_t m_m
 }
 
 extern "C" size_t nrx_mse_workspace_bytes(const nrx_slot_desc *slots, int32_t n) {
-  Plan *P;
-  if (get_plan(slots, n, 16, 8, 0, &P) != NRX_OK) return 0;
+  PlanRef PR;
+  if (get_plan(slots, n, 16, 8, 0, &PR) != NRX_OK) return 0;
+  Plan *P = PR.get();
   const int64_t nb = (P->max_ute + 255) / 256;
   return align256(P->meta_bytes) + align256((size_t)n * nb * 16);
 }
@@ -1638,8 +1744,9 @@ extern "C" size_t nrx_mse_workspace_bytes(const nrx_slot_desc *slots, int32_t n)
 extern "C" nrx_status nrx_mse(const nrx_slot_desc *slots, int32_t n, const float *h_est, const float *h_true,
                               float gamma, float *dh_est, double *loss, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!h_est || !h_true || !ws) return fail(NRX_ERR_INVALID, "null argument");
-  Plan *P;
-  nrx_status s = get_plan(slots, n, 16, 8, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, 16, 8, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const int64_t nb = (P->max_ute + 255) / 256;
   const size_t need = align256(P->meta_bytes) + align256((size_t)n * nb * 16);
@@ -1694,8 +1801,9 @@ nrx_status sim_check(const nrx_sim_config *c) {
 
 extern "C" size_t slot_sim_workspace_bytes(const nrx_sim_config *cfg, const nrx_slot_desc *slots, int32_t n) {
   if (sim_check(cfg) != NRX_OK) return 0;
-  Plan *P;
-  if (get_plan(slots, n, 16, 8, cfg->n_taps, &P) != NRX_OK) return 0;
+  PlanRef PR;
+  if (get_plan(slots, n, 16, 8, cfg->n_taps, &PR) != NRX_OK) return 0;
+  Plan *P = PR.get();
   return sim_layout(P).total;
 }
 
@@ -1706,8 +1814,9 @@ extern "C" nrx_status slot_sim(const nrx_sim_config *cfg, uint64_t seed, uint32_
   if (s != NRX_OK) return s;
   if (!y || !ws) return fail(NRX_ERR_INVALID, "null argument");
   if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
-  Plan *P;
-  s = get_plan(slots, n, 16, m_max, cfg->n_taps, &P);
+  PlanRef PR;
+  s = get_plan(slots, n, 16, m_max, cfg->n_taps, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const SimLayout L = sim_layout(P);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
@@ -1787,8 +1896,9 @@ extern "C" nrx_status nrx_calibrate(nrx_model *m, const float *w, const nrx_slot
   if (!m || !w || !y || !llr || !ws) return fail(NRX_ERR_INVALID, "null argument");
   if (!m->fp8) return fail(NRX_ERR_INVALID, "not an FP8 model");
   if (!(headroom >= 1.0f)) return fail(NRX_ERR_INVALID, "headroom %g < 1", headroom);
-  Plan *P;
-  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &P);
+  PlanRef PR;
+  nrx_status s = get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR);
+  Plan *P = PR.get();
   if (s != NRX_OK) return s;
   const FwdLayout L = fwd_layout(m, P, false);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);

@@ -33,7 +33,8 @@ class SlotDesc(ctypes.Structure):
     _fields_ = [("n_prb", ctypes.c_int32), ("n_ant", ctypes.c_int32), ("n_ue", ctypes.c_int32),
                 ("bits_per_sym", ctypes.c_int32 * 4), ("slot_number", ctypes.c_int32),
                 ("n_id", ctypes.c_int32), ("n_scid", ctypes.c_int32), ("n0", ctypes.c_float),
-                ("snr_offset_db", ctypes.c_float), ("y_offset", ctypes.c_int64), ("h_offset", ctypes.c_int64),
+                ("snr_offset_db", ctypes.c_float), ("dmrs_sym_mask", ctypes.c_uint32),
+                ("y_offset", ctypes.c_int64), ("h_offset", ctypes.c_int64),
                 ("llr_offset", ctypes.c_int64), ("bits_offset", ctypes.c_int64)]
 
 
@@ -90,6 +91,10 @@ _SIGS = {
     "nrx_act_scale_count": (_i32, [_vp]),
     "nrx_act_scales": (_i32, [_vp, _vp, _vp, _i32]),
     "nrx_calibrate": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp]),
+    "nrx_slot_flags": (_i32, [_vp, _DESC, _i32, _vp, _sz, _vp, _vp]),
+    "nrx_fallback_lmmse": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nrx_saved_token": (_i64, [_vp]),
+    "nrx_check_token": (_i32, [_vp, _vp, _i64]),
     "nrx_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -142,6 +147,7 @@ def make_slots(shapes, m_max, model_b=None):
         d.n_scid = sh.get("n_scid", 0)
         d.n0 = sh.get("n0", 0.0)
         d.snr_offset_db = sh.get("snr_offset_db", 0.0)
+        d.dmrs_sym_mask = sh.get("dmrs_sym_mask", 0)
         d.y_offset, d.h_offset, d.llr_offset, d.bits_offset = yo, ho, lo, bo
         yo += S * 14 * B
         ho += S * 14 * U * B
@@ -284,6 +290,28 @@ def lmmse_demap(slots, m_max, y, llr, ws, h=None, n0=None, stream=None):
     arr, n = _descs(slots)
     _check(_lib.lmmse_demap(arr, n, m_max, _ptr(y), _ptr(h), _ptr(n0), _ptr(llr), _ptr(ws),
                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_slot_flags(model, slots, ws, flags, stream=None):
+    """flags: int32/uint32 device tensor of one word per slot (bit 0: an LLR is not finite, bit 1: a channel
+    estimate is not finite) for the last forward on ws."""
+    arr, n = _descs(slots)
+    _check(_lib.nrx_slot_flags(model, arr, n, _ptr(ws), ws.numel() * ws.element_size(), _ptr(flags),
+                               _stream(stream)))
+
+
+def nrx_fallback_lmmse(slots, m_max, y, flags, llr, ws, h=None, n0=None, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.nrx_fallback_lmmse(arr, n, m_max, _ptr(y), _ptr(h), _ptr(n0), _ptr(flags), _ptr(llr), _ptr(ws),
+                                   ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_saved_token(model):
+    return int(_lib.nrx_saved_token(model))
+
+
+def nrx_check_token(model, ws, token):
+    _check(_lib.nrx_check_token(model, _ptr(ws), int(token)))
 
 
 # ------------------------------------------------------------- data model ---

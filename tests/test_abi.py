@@ -192,3 +192,78 @@ def test_fp8_model_host_checks():
     finally:
         L.nrx_model_destroy(model)
         L.nrx_model_destroy(plain)
+
+
+def test_dmrs_symbol_mask_only_type_a_with_one_additional_position():
+    # the descriptor names the DMRS symbols; this build implements symbols 2 and 11 (Sec. III-B) and
+    # rejects any other pattern explicitly rather than silently using 2 and 11
+    model = L.nrx_model_create(4, 128, 2, 0, 2)
+    try:
+        base = dict(n_prb=4, n_ant=4, n_ue=1, bits=[2])
+        for mask in (0, (1 << 2) | (1 << 11)):
+            sl, _ = L.make_slots([dict(base, dmrs_sym_mask=mask)], 2)
+            assert L.nrx_workspace_bytes(model, sl) > 0
+            assert L.lmmse_workspace_bytes(sl) > 0
+        bad, _ = L.make_slots([dict(base, dmrs_sym_mask=(1 << 3) | (1 << 10))], 2)
+        assert L.nrx_workspace_bytes(model, bad) == 0
+        import torch
+        t = torch.zeros(16)
+        st = type("S", (), {"cuda_stream": 0})()
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_forward(model, t, bad, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_UNSUPPORTED
+        with pytest.raises(L.NrxError) as e:
+            L.lmmse_demap(bad, 2, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_UNSUPPORTED
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_fallback_and_token_host_checks():
+    import torch
+    model = L.nrx_model_create(4, 128, 2, 0, 2)
+    try:
+        t = torch.zeros(16)
+        st = type("S", (), {"cuda_stream": 0})()
+        ok, _ = L.make_slots([dict(n_prb=4, n_ant=4, n_ue=1, bits=[2])] * 3, 2)
+        # no save_acts forward yet: no token, and any token is stale
+        assert L.nrx_saved_token(model) == 0
+        for tok in (0, 1):
+            with pytest.raises(L.NrxError) as e:
+                L.nrx_check_token(model, t, tok)
+            assert e.value.status == L.NRX_ERR_INVALID
+        # flags of a forward need that forward's workspace
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_slot_flags(model, ok, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_WORKSPACE
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_slot_flags(model, ok, t, None, stream=st)
+        assert e.value.status == L.NRX_ERR_INVALID
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_fallback_lmmse(ok, 2, t, None, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_INVALID
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_fallback_lmmse(ok, 3, t, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_SHAPE
+        with pytest.raises(L.NrxError) as e:
+            L.nrx_fallback_lmmse(ok, 2, t, t, t, t, stream=st)
+        assert e.value.status == L.NRX_ERR_WORKSPACE
+    finally:
+        L.nrx_model_destroy(model)
+
+
+def test_plan_cache_evicts_instead_of_failing():
+    # a receiver that passes a per-slot N0 in the descriptor makes a new batch key every call: the
+    # plan cache keeps the most recent ones and never runs full
+    model = L.nrx_model_create(4, 128, 2, 0, 2)
+    try:
+        first = None
+        for k in range(600):
+            sl, _ = L.make_slots([dict(n_prb=4, n_ant=4, n_ue=1, bits=[2], n0=1e-3 * (k + 1))] * 2, 2)
+            n = L.nrx_workspace_bytes(model, sl)
+            assert n > 0, L.nrx_last_error()
+            first = first or n
+            assert n == first
+            assert L.lmmse_workspace_bytes(sl) > 0
+    finally:
+        L.nrx_model_destroy(model)

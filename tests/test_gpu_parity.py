@@ -706,18 +706,19 @@ def test_double_readout_training_refines_channel_estimate():
 @pytest.mark.parametrize("var_io", [False, True])
 def test_mixed_mcs_training_learns_every_modulation(var_io):
     """Mixed-MCS training (Sec. III, III-A; U_A drawn per batch, Sec. II-B) of the two Var-MCS receivers: LLR masking
-    (one readout with six outputs) and Var-IO (one readout per modulation).  Trained on batches of random U_A, iid
-    per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR offsets, each detects every modulation: held-out BCE
-    per coded bit at 10 dB after 2000 steps well below ln 2 = 0.69 (measured with masking after 1500 steps
-    0.056 / 0.242 / 0.396; with Var-IO, whose input and output layers each see a third of the data, after 2000
-    steps 0.135 / 0.346 / 0.477)."""
+    (one readout with six outputs) and Var-IO (one StateInit and readout per modulation).  Trained on batches of
+    random U_A, iid per-UE QPSK / 16-QAM / 64-QAM and modulation-dependent SNR offsets, each detects every
+    modulation: held-out BCE per coded bit at 10 dB below 0.12 / 0.30 / 0.45 for both (measured with masking after
+    1500 steps 0.056 / 0.242 / 0.396).  The Var-IO input and output layers each see a third of the data, so that
+    network trains three times as many steps to the same bound."""
     from paper_2409_02912_amd.train import Trainer, evaluate
     w = synth.WORKLOADS["tm"]
-    log(f"training: workload tm, mixed MCS (pool of 16 batch shapes), Var-IO {var_io}, 2000 steps")
+    steps = 6000 if var_io else 2000
+    log(f"training: workload tm, mixed MCS (pool of 16 batch shapes), Var-IO {var_io}, {steps} steps")
     tr = Trainer(w, L.NRX_BF16, seed=5, lr=1e-3, mixed_pool=16, var_io=var_io)
     try:
         assert len({tuple(s["n_ue"] for s in e[0]) for e in tr.pool}) > 1   # U_A varies over the batches
-        for _ in range(2000):
+        for _ in range(steps):
             tr.train_step()
         torch.cuda.synchronize()
         bce = {b: evaluate(tr.params, w, seed=99, batches=2, snr_db=10.0, bits=b, var_io=var_io)["bce_nrx"]
@@ -725,7 +726,7 @@ def test_mixed_mcs_training_learns_every_modulation(var_io):
     finally:
         tr.close()
     log(f"  held-out BCE per modulation (bits: BCE) {bce}")
-    assert bce[2] < 0.25 and bce[4] < 0.45 and bce[6] < 0.55
+    assert bce[2] < 0.12 and bce[4] < 0.30 and bce[6] < 0.45
 
 
 def test_site_fine_tuning_improves_site_receiver():

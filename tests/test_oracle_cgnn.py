@@ -201,6 +201,27 @@ def test_bce_and_adam():
     assert np.allclose(w1, -1e-3 * np.sign(g), rtol=1e-4)
 
 
+def test_adam_third_step_against_hand_values():
+    """Three Adam steps (Kingma & Ba, Algorithm 1) with gradients 1, 0, 0.  At step 1 the bias
+    correction cancels both decay rates, so only a later step sees them.  After step 3:
+    m3 = (1 - b1) b1^2 = 0.1 * 0.81 = 0.081, bias-corrected 0.081 / (1 - 0.729) = 0.298893...;
+    v3 = (1 - b2) b2^2 = 0.001 * 0.998001 = 9.98001e-4, bias-corrected 9.98001e-4 / (1 - 0.997002999)
+    = 0.333000...; the third step moves the weight by -lr * 0.298893 / (0.577062 + eps) = -0.517957 lr.
+    Swapped decay rates would give -0.609 lr; a missing bias correction -0.0810 / 0.0316 lr."""
+    w = np.array([0.0])
+    m = np.zeros(1)
+    v = np.zeros(1)
+    steps = []
+    for t, g in enumerate([1.0, 0.0, 0.0], start=1):
+        w_new, m, v = cgnn.adam_step(w, np.array([g]), m, v, t, lr=1e-3)
+        steps.append(float(w_new[0] - w[0]))
+        w = w_new
+    assert abs(m[0] - 0.081) < 1e-15 and abs(v[0] - 9.98001e-4) < 1e-15
+    # step 2: m2 = 0.09, mhat = 0.09/0.19; v2 = 9.99e-4, vhat = 9.99e-4/1.999e-3
+    assert abs(steps[1] - (-1e-3 * (0.09 / 0.19) / (np.sqrt(9.99e-4 / 1.999e-3) + 1e-8))) < 1e-15
+    assert abs(steps[2] / 1e-3 - (-0.5179570)) < 1e-6, steps[2]
+
+
 def test_window_reproduces_full_grid():
     """The 1 + 2C stacked 3x3 convolutions see C' = 1 + 2C subcarriers either way; with message
     passing and the readout acting per RE, a window of +-16 subcarriers starting on an even

@@ -44,6 +44,34 @@ def test_ls_affine_channel_reproduced_in_interior():
     assert np.allclose(est[lo:hi + 1, 2:12, 0], H[lo:hi + 1, 2:12, 0], atol=1e-12)
 
 
+@pytest.mark.parametrize("port", [0, 1, 2, 3])
+def test_ls_edge_rules_on_affine_channel(port):
+    """Flat extrapolation: on a noiseless channel affine in s and t, seen by one port (the others
+    silent, so the OCC sees no co-group leakage), the estimate at (s, t) equals the channel at
+    (clamp(s, first pair centre, last pair centre), clamp(t, 2, 11)) everywhere on the grid --
+    symbols 0, 1 repeat symbol 2, symbols 12, 13 repeat symbol 11, and subcarriers below the
+    first / above the last pair centre of the port's CDM group repeat that centre."""
+    rng = np.random.default_rng(11 + port)
+    U = port + 1
+    desc = slot_sim.SlotDesc(3, 2, U, [2] * U, slot_number=7)
+    S = desc.n_sc
+    a, b, c = (rng.standard_normal(2) + 1j * rng.standard_normal(2) for _ in range(3))
+    s = np.arange(S)[:, None, None]
+    t = np.arange(14)[None, :, None]
+    H = np.zeros((S, 14, U, 2), dtype=np.complex128)
+    H[:, :, port, :] = a + 0.03 * s * b + 0.05 * t * c
+    y, _, _ = _grid_from_h(H, desc)
+    est = receiver.ls_estimate(y, desc)[:, :, port]
+    delta = port // 2
+    first, last = 1 + delta, 4 * (S // 4 - 1) + 1 + delta
+    sc = np.clip(np.arange(S), first, last)
+    tc = np.clip(np.arange(14), 2, 11)
+    want = (a + 0.03 * sc[:, None, None] * b + 0.05 * tc[None, :, None] * c)
+    assert np.allclose(est, want, atol=1e-12)
+    # the rule really extrapolates: the grid's edges differ from the channel there
+    assert not np.allclose(est[0, 0], H[0, 0, port]) and not np.allclose(est[S - 1, 13], H[S - 1, 13, port])
+
+
 def test_lmmse_noiseless_recovers_symbols():
     rng = np.random.default_rng(2)
     desc = slot_sim.SlotDesc(2, 8, 4, [4, 4, 4, 4])
