@@ -142,8 +142,8 @@ std::vector<int64_t> plan_key(const nrx_slot_desc *d, int n, int sim_taps) {
   return k;
 }
 
-// Validates descriptors and builds (or fetches) the plan.  max_ant bounds n_ant.
-nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int sim_taps, PlanRef *out) {
+// Validates the descriptors of a batch.  max_ant bounds n_ant, m_max the bits per symbol.
+nrx_status validate_slots(const nrx_slot_desc *d, int n, int max_ant, int m_max) {
   if (!d || n <= 0) return fail(NRX_ERR_INVALID, "no slot descriptors");
   for (int i = 0; i < n; ++i) {
     const nrx_slot_desc &s = d[i];
@@ -165,6 +165,12 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
       return fail(NRX_ERR_UNSUPPORTED, "slot %d: dmrs_sym_mask 0x%x: only DMRS on symbols 2 and 11 is implemented", i,
                   s.dmrs_sym_mask);
   }
+  return NRX_OK;
+}
+
+// Validates descriptors and builds (or fetches) the plan.  max_ant bounds n_ant.
+nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int sim_taps, PlanRef *out) {
+  if (nrx_status v = validate_slots(d, n, max_ant, m_max)) return v;
   std::vector<int64_t> key = plan_key(d, n, sim_taps);
   PlanRef evicted;   // released after the lock (its destructor synchronises the device)
   std::lock_guard<std::mutex> lk(g_plans.mu);
@@ -1701,6 +1707,135 @@ extern "C" nrx_status nrx_fallback_lmmse(const nrx_slot_desc *slots, int32_t n, 
                                          void *ws, size_t ws_bytes, hipStream_t st) {
   if (!flags) return fail(NRX_ERR_INVALID, "null flags");
   return lmmse_impl(slots, n, m_max, y, h, n0dev, (const unsigned int *)flags, llr, ws, ws_bytes, st);
+}
+
+// ------------------------------------------------ allocation-free judge --
+//
+// lmmse_demap_noalloc runs the kernels of lmmse_demap with every buffer they need beyond y, h and llr
+// (the per-slot tables, the DMRS sequences, the LS pair estimates and the interpolated LS estimate)
+// carved out of one file-scope device array, so the call allocates nothing: no hipMalloc, no pinned
+// host staging, no plan-cache entry.  Each device holds its own copy of the array; its address is
+// taken once per device with hipGetSymbolAddress, and only that address reaches kernels and copies.
+
+static __device__ __align__(256) unsigned char scratch[NRX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up on the first call per device).
+nrx_status scratch_of_current_device(char **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(NRX_ERR_UNSUPPORTED, "device index %d >= %d", dev,
+                                                         NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(NRX_ERR_HIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char *)g_scratch_ptr[dev];
+  return NRX_OK;
+}
+
+// Scratch layout of one call: [SlotGeo n][pair offsets n+1][DMRS][LS pairs][interpolated LS estimate].
+struct NoAllocLayout {
+  size_t geo, pair_off, dmrs, pairs, h, total;
+  int64_t max_re, max_pairs, max_rows;
+};
+NoAllocLayout noalloc_layout(const nrx_slot_desc *d, int n, bool need_h) {
+  NoAllocLayout L{};
+  int64_t dmrs = 0, pairs = 0, hel = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t S = 12LL * d[i].n_prb, U = d[i].n_ue, B = d[i].n_ant;
+    dmrs += S;
+    pairs += 2 * U * (S / 4) * B;
+    hel += S * 14 * U * B;
+    L.max_re = std::max(L.max_re, S * 14);
+    L.max_pairs = std::max(L.max_pairs, 2 * U * (S / 4) * B);
+    L.max_rows = std::max(L.max_rows, S * 14 * U);
+  }
+  size_t o = 0;
+  L.geo = o; o = align256(o + sizeof(SlotGeo) * (size_t)n);
+  L.pair_off = o; o = align256(o + sizeof(int64_t) * (size_t)(n + 1));
+  L.dmrs = o; o = align256(o + (size_t)dmrs * 8);
+  L.pairs = o; o = align256(o + (size_t)pairs * 8);
+  L.h = o; o = align256(o + (need_h ? (size_t)hel * 8 : 0));
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t lmmse_noalloc_scratch_bytes(const nrx_slot_desc *slots, int32_t n, int32_t internal_ls) {
+  if (validate_slots(slots, n, 16, 8) != NRX_OK) return 0;
+  return noalloc_layout(slots, n, internal_ls != 0).total;
+}
+
+extern "C" nrx_status lmmse_demap_noalloc(const nrx_slot_desc *slots, int32_t n, int32_t m_max, const float *y,
+                                          const float *h, const float *n0dev, float *llr, hipStream_t st) {
+  if (!y || !llr) return fail(NRX_ERR_INVALID, "null argument");
+  if (m_max != 2 && m_max != 4 && m_max != 6 && m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", m_max);
+  if (nrx_status v = validate_slots(slots, n, 16, m_max)) return v;
+  const NoAllocLayout L = noalloc_layout(slots, n, h == nullptr);
+  if (L.total > (size_t)NRX_NOALLOC_SCRATCH_BYTES)
+    return fail(NRX_ERR_WORKSPACE, "batch needs %zu bytes of scratch, above the fixed %zu-byte array of the "
+                "allocation-free call: split the batch or use lmmse_demap", L.total,
+                (size_t)NRX_NOALLOC_SCRATCH_BYTES);
+  char *w = nullptr;
+  if (nrx_status v = scratch_of_current_device(&w)) return v;
+  // host image of the tables; the internal estimate is packed slot after slot in the scratch
+  const size_t tbytes = L.dmrs;
+  thread_local std::vector<char> img;
+  if (img.size() < tbytes) img.resize(tbytes);
+  std::fill(img.begin(), img.begin() + tbytes, 0);
+  SlotGeo *geo = (SlotGeo *)(img.data() + L.geo);
+  int64_t *poff = (int64_t *)(img.data() + L.pair_off);
+  int64_t dm = 0, pr = 0, ho = 0;
+  for (int i = 0; i < n; ++i) {
+    const nrx_slot_desc &s = slots[i];
+    SlotGeo g{};
+    g.S = 12 * s.n_prb;
+    g.U = s.n_ue;
+    g.B = s.n_ant;
+    for (int u = 0; u < 4; ++u) g.m[u] = u < s.n_ue ? s.bits_per_sym[u] : 0;
+    g.slot_number = s.slot_number;
+    g.n_id = s.n_id;
+    g.n_scid = s.n_scid;
+    g.n0 = s.n0;
+    g.snr_off = s.snr_offset_db;
+    g.y_off = s.y_offset;
+    g.h_off = h ? s.h_offset : ho;
+    g.llr_off = s.llr_offset;
+    g.bits_off = s.bits_offset;
+    g.dmrs_off = dm;
+    geo[i] = g;
+    poff[i] = pr;
+    dm += g.S;
+    pr += 2LL * g.U * (g.S / 4) * g.B;
+    ho += (int64_t)g.S * 14 * g.U * g.B;
+  }
+  poff[n] = pr;
+  // pageable source: the copy has read the host image when hipMemcpyAsync returns
+  HIPCHK(hipMemcpyAsync(w, img.data(), tbytes, hipMemcpyHostToDevice, st));
+  const SlotGeo *dgeo = (const SlotGeo *)(w + L.geo);
+  const int64_t *dpoff = (const int64_t *)(w + L.pair_off);
+  const float *hh = h;
+  if (!h) {
+    float2 *dmrs = (float2 *)(w + L.dmrs);
+    float2 *pairs = (float2 *)(w + L.pairs);
+    launch_dmrs(dgeo, n, dmrs, st);
+    launch_ls_pairs(dgeo, n, (int)L.max_pairs, (const float2 *)y, dmrs, pairs, dpoff, 0, st);
+    launch_features<float>(dgeo, nullptr, n, L.max_rows, (const float2 *)y, pairs, dpoff, 16, 0, (float *)nullptr,
+                           (float2 *)(w + L.h), st);
+    HIPCHK(hipGetLastError());
+    hh = (const float *)(w + L.h);
+  }
+  launch_lmmse(dgeo, nullptr, n, L.max_re, m_max, (const float2 *)y, (const float2 *)hh, n0dev, llr, st);
+  HIPCHK(hipGetLastError());
+  return NRX_OK;
 }
 
 extern "C" size_t nrx_bce_workspace_bytes(const nrx_slot_desc *slots, int32_t n, int32_t m_max) {

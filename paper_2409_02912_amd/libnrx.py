@@ -80,6 +80,8 @@ _SIGS = {
     "nrx_ls_estimate": (_i32, [_DESC, _i32, _vp, _vp, _vp, _sz, _vp]),
     "lmmse_workspace_bytes": (_sz, [_DESC, _i32]),
     "lmmse_demap": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "lmmse_noalloc_scratch_bytes": (_sz, [_DESC, _i32, _i32]),
+    "lmmse_demap_noalloc": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "slot_sim_workspace_bytes": (_sz, [ctypes.POINTER(SimConfig), _DESC, _i32]),
     "slot_sim": (_i32, [ctypes.POINTER(SimConfig), _u64, _u32, _DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                         _sz, _vp]),
@@ -290,6 +292,19 @@ def lmmse_demap(slots, m_max, y, llr, ws, h=None, n0=None, stream=None):
     arr, n = _descs(slots)
     _check(_lib.lmmse_demap(arr, n, m_max, _ptr(y), _ptr(h), _ptr(n0), _ptr(llr), _ptr(ws),
                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
+NRX_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def lmmse_noalloc_scratch_bytes(slots, internal_ls=True):
+    arr, n = _descs(slots)
+    return int(_lib.lmmse_noalloc_scratch_bytes(arr, n, 1 if internal_ls else 0))
+
+
+def lmmse_demap_noalloc(slots, m_max, y, llr, h=None, n0=None, stream=None):
+    arr, n = _descs(slots)
+    _check(_lib.lmmse_demap_noalloc(arr, n, m_max, _ptr(y), _ptr(h), _ptr(n0), _ptr(llr), _stream(stream)))
 
 
 def nrx_slot_flags(model, slots, ws, flags, stream=None):

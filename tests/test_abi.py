@@ -267,3 +267,26 @@ def test_plan_cache_evicts_instead_of_failing():
             assert L.lmmse_workspace_bytes(sl) > 0
     finally:
         L.nrx_model_destroy(model)
+
+
+def test_noalloc_lmmse_host_checks():
+    # the allocation-free judge refuses, before touching the device, a batch beyond its fixed array
+    t = type("T", (), {"data_ptr": lambda self: 256})()
+    st = type("S", (), {"cuda_stream": 0})()
+    big, _ = L.make_slots([dict(n_prb=273, n_ant=16, n_ue=4, bits=[4] * 4)] * 6, 4)
+    need = L.lmmse_noalloc_scratch_bytes(big, True)
+    assert need > L.NRX_NOALLOC_SCRATCH_BYTES
+    # a caller-given estimate needs no room for the internal one
+    assert L.lmmse_noalloc_scratch_bytes(big, False) < need
+    with pytest.raises(L.NrxError) as e:
+        L.lmmse_demap_noalloc(big, 4, t, t, stream=st)
+    assert e.value.status == L.NRX_ERR_WORKSPACE
+    one, _ = L.make_slots([dict(n_prb=273, n_ant=8, n_ue=4, bits=[4] * 4)], 4)
+    assert 0 < L.lmmse_noalloc_scratch_bytes(one, True) <= L.NRX_NOALLOC_SCRATCH_BYTES
+    for m_max, err in ((3, L.NRX_ERR_SHAPE), (2, L.NRX_ERR_SHAPE)):   # 16-QAM UEs do not fit m_max = 2
+        with pytest.raises(L.NrxError) as e:
+            L.lmmse_demap_noalloc(one, m_max, t, t, stream=st)
+        assert e.value.status == err
+    with pytest.raises(L.NrxError) as e:
+        L.lmmse_demap_noalloc(one, 4, None, t, stream=st)
+    assert e.value.status == L.NRX_ERR_INVALID
