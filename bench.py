@@ -93,10 +93,11 @@ def cpu_baseline(w, weights, net_args, budget_s):
     return out
 
 
-def ragged_batch(steps, no_autotune, tune_cache=None):
+def ragged_batch(steps, no_autotune, tune_cache=None, persistent=False):
     """Uneven batch of 256 slots (PRBs 4..273, 1..4 UEs, 4/8/16 antennas, QPSK..256-QAM) in BF16,
     replayed from a captured hipGraph; per-slot latency = start of the pass to the end of the
-    slot's last readout tile, from the device wall clock."""
+    slot's last readout tile, from the device wall clock.  persistent: the CGNN runs as one
+    persistent launch over slot groups (model flags bit 3) instead of one launch per layer."""
     import numpy as np
     import torch
     from paper_2409_02912_amd import libnrx as L
@@ -105,7 +106,8 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
     shapes = synth.uniform_shapes(w)
     m_max = w["m"]
     descs, sz = L.make_slots(shapes, m_max)
-    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, L.NRX_BF16, flags=1)
+    model = L.nrx_model_create(w["n_ant"], w["d"], w["n_blocks"], w["n_rounds"], m_max, L.NRX_BF16,
+                               flags=1 | (8 if persistent else 0))
     try:
         layout = [(n, s) for n, _, s in L.weight_layout(model)]
         dw = torch.from_numpy(synth.he_weights(layout, 0)).cuda()
@@ -117,9 +119,11 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
         del sws
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
-        if not no_autotune:
+        if not no_autotune and not persistent:
             L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=tune_cache)
-        variants = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}
+        variants = ({L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}
+                    if not persistent else "persistent kernel (ring conv shape of variant 7)")
+        flags = torch.full((len(shapes),), -1, dtype=torch.int32, device="cuda")
         lat = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
         for _ in range(2):
             L.nrx_forward(model, dw, descs, y, llr, ws)      # first call captures the graph
@@ -136,6 +140,8 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
             total += e0.elapsed_time(e1)
             lats.append(lat.cpu().numpy().copy())
         ms = total / steps
+        L.nrx_slot_flags(model, descs, ws, flags)
+        n_flagged = int((flags != 0).sum().item())
         v = np.concatenate(lats)
         res = sum(12 * s["n_prb"] * 14 for s in shapes)
         llr_bf16 = llr.clone()
@@ -153,7 +159,8 @@ def ragged_batch(steps, no_autotune, tune_cache=None):
     finally:
         L.nrx_model_destroy(m32)
     return {"workload": f"{len(shapes)} uneven slots: PRB 4-273, 1-4 UE, 4/8/16 ant, QPSK..256-QAM, bf16, "
-                        f"hipGraph replay",
+                        f"hipGraph replay" + (", one persistent launch" if persistent else ", one launch per layer"),
+            "slots_flagged": n_flagged,
             "slots_per_s": len(shapes) / (ms * 1e-3), "res_per_s": res / (ms * 1e-3), "ms_per_step": ms,
             "steps": steps, "latency_us_p50": float(np.percentile(v, 50)),
             "latency_us_p99": float(np.percentile(v, 99)),
@@ -169,6 +176,9 @@ CONV_VARIANT_KERNELS = [
     "conv3x3_ring_kernel<MB 4, NW 8, G 1, OCC 1, NBUF 6>",
     "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, compiler-scheduled>",
     "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, raised wave priority>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, staggered start>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 2, raised wave priority, staggered start>",
+    "conv3x3_ring_kernel<MB 4, NW 8, G 3, OCC 1, NBUF 3, 504-row subcarrier-aligned tiles>",
 ]
 
 
@@ -375,6 +385,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 pass")
+    ap.add_argument("--no-persistent", action="store_true", help="skip the persistent-launch BF16 pass")
     ap.add_argument("--variant-sweep", action="store_true", help="time every conv variant per layer class")
     ap.add_argument("--ragged-steps", type=int, default=5,
                     help="timed replays of the uneven 256-slot batch under a hipGraph (0: skip)")
@@ -437,13 +448,15 @@ def main():
     llrs = {}
     flag_words = {}    # per-slot health words of each pass (non-finite input or LLRs)
     passes = [(L.NRX_BF16, "bf16")]
+    if not args.no_persistent:
+        passes.append((L.NRX_BF16, "bf16_persistent"))
     if not args.no_fp8:
         passes.append((L.NRX_FP8, "fp8"))
     if not args.bf16_only:
         passes.append((L.NRX_FP32, "fp32"))
     for prec, name in passes:
         # flags bit 0: the timed pass is the captured launch sequence replayed as a hipGraph
-        model = L.nrx_model_create(*net_args, prec, flags=1)
+        model = L.nrx_model_create(*net_args, prec, flags=1 | (8 if name == "bf16_persistent" else 0))
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
         if name == "fp8":
@@ -467,7 +480,7 @@ def main():
                             for c in L.CONV_CLASSES}
                 L.nrx_profile_enable(model, False)
             results.setdefault("sweep", {})[name] = sweep
-        if not args.no_autotune:
+        if not args.no_autotune and name != "bf16_persistent":
             L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=args.tune_cache)
         results.setdefault("variants", {})[name] = {L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0]
                                                     for c in L.CONV_CLASSES}
@@ -619,6 +632,12 @@ def main():
                                           "peak": 8000.0, "unit": "GB/s",
                                           "frac": rows * 768 / (cb8 * 1e-3) / 8e12,
                                           "mfma_frac": conv_flops / (cb8 * 1e-3) / PEAKS["fp8"]}}
+    if "bf16_persistent" in results:
+        msp = results["bf16_persistent"]["ms_per_step"]
+        out["bf16_persistent"] = {"slots_per_s": n_slots / (msp * 1e-3), "ms_per_step": msp,
+                                  "batch1_ms": results["bf16_persistent"]["batch1_ms"],
+                                  "llr_identical_to_layer_path": bool(torch.equal(llrs["bf16_persistent"],
+                                                                                  llrs["bf16"]))}
     if "fp32" in results:
         out["fp32"] = {"slots_per_s": n_slots / (results["fp32"]["ms_per_step"] * 1e-3),
                        "ms_per_step": results["fp32"]["ms_per_step"], "kernels": results["fp32"]["kernels"]}
@@ -626,6 +645,8 @@ def main():
     progress("ber done")
     if args.ragged_steps > 0:
         out["ragged"] = ragged_batch(args.ragged_steps, args.no_autotune, args.tune_cache)
+        progress("uneven batch (per-layer launches) done")
+        out["ragged_persistent"] = ragged_batch(args.ragged_steps, args.no_autotune, args.tune_cache, persistent=True)
     progress("uneven batch done")
     if not args.bf16_only:
         out["paper_rt_batch1"] = paper_rt_latency()

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnrx-gfx950.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["k_conv.hip", "k_conv8.hip", "k_mlp.hip", "k_frontend.hip", "k_lmmse.hip", "k_sim.hip", "k_train.hip",
-           "k_bwd.hip", "libnrx.cpp"]
+           "k_bwd.hip", "k_persist.hip", "libnrx.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

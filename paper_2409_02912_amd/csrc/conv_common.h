@@ -44,6 +44,23 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p) {
   return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const lds_void *)p);
 }
 
+// LDS bytes addressed in the local address space: bodies that receive their LDS region as a pointer
+// use these, so no generic-to-local pointer conversion is left for the compiler to check at run time.
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+__device__ __forceinline__ uint32_t lds_addr(const lds_u8 *p) {
+  return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)p);
+}
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v16 ld16(const lds_u8 *p) {
+  const u32x4_t x = *(const __attribute__((address_space(3))) u32x4_t *)p;
+  return v16{{x.x, x.y, x.z, x.w}};
+}
+__device__ __forceinline__ void st16(lds_u8 *p, v16 v) {
+  *(__attribute__((address_space(3))) u32x4_t *)p = u32x4_t{v.w[0], v.w[1], v.w[2], v.w[3]};
+}
+using ::ld16;   // the generic-pointer forms stay visible beside these
+using ::st16;
+
 // Global -> LDS copy of 16 bytes per lane (lane i writes lds + 16 i) through the
 // buffer unit.  Written as inline assembly so that the compiler's wait-count pass
 // does not tie later LDS reads of other buffers to it; the kernels order it

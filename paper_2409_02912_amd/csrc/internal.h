@@ -42,10 +42,12 @@ struct ConvVariant {
   int occ;    // waves per SIMD the kernel is built for
   int pref;   // 1: weights prefetched one tap ahead; 2: weights and halo through LDS (K loop unrolled
               // over two chunks: even chunk counts only); 3: the same, rolled (ring kernel)
+  int aligned = 0;   // 1: tiles of CONV_ALIGNED_TILE rows starting on subcarrier boundaries
 };
-#define NRX_CONV_VARIANTS 11
+constexpr int CONV_ALIGNED_TILE = 504;   // whole subcarriers for U = 1..4 (14 U rows each)
+#define NRX_CONV_VARIANTS 14
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
-#define NRX_CONV8_VARIANTS 3
+#define NRX_CONV8_VARIANTS 4
 extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64
 
 // FP8 convolution (EPI_LN_RELU or EPI_RESID) on E4M3 operands a.src8_*, a.w8, a.wscale.
@@ -146,6 +148,71 @@ void launch_lmmse(const SlotGeo *geo, const int64_t *re_base, int n_slots, int64
                   const float2 *y, const float2 *h, const float *n0dev, float *llr, hipStream_t st,
                   const unsigned int *slot_mask = nullptr);
 
+// Persistent forward (BF16 inference): one launch runs every layer of the CGNN over every slot.
+// A work item is (stage, slot, run of up to item_tiles consecutive tiles of the slot).  Slots form groups
+// of consecutive slots; the items of a group come after those of the groups before it, and inside a
+// group they are ordered by stage, then slot, then tile, so every item comes after the items it reads.
+// Workgroups claim items in that order from a counter.  A conv item on tiles ta .. tb - 1 waits for the
+// previous stage's tiles ta - 1 .. tb of its slot (the 3x3 halo), an MLP item for tiles ta .. tb - 1.
+enum { PK_CONV_STORE = 0, PK_CONV_LN = 1, PK_CONV_RESID = 2, PK_MP = 3, PK_READOUT = 4 };
+struct PersistStage {
+  int32_t kind;                 // PK_*
+  int32_t pad;
+  ConvArgs<bf16_t> c;           // conv stages (tiles/n_tiles unused)
+  MlpArgs<bf16_t> m;            // MLP stages (tiles/n_tiles unused)
+};
+struct PersistArgs {
+  const PersistStage *stages;
+  int32_t n_stages;
+  int32_t n_groups;
+  const SlotGeo *geo;
+  const int32_t *tile_base;     // per slot (n + 1 entries): index of its first tile in the batch
+  const int32_t *item_base;     // per slot (n + 1 entries): index of its first item in a stage
+  const int32_t *tile_rows;     // per slot: rows per tile (whole REs, at most PERSIST_TILE)
+  const int32_t *group_slot;    // per group (n_groups + 1 entries): its first slot
+  int32_t item_tiles;           // consecutive tiles of one slot per work item
+  unsigned int *ctl;            // [0] next item to claim, [1] abort (a wait ran out); zeroed before the launch
+  unsigned int *done;           // [stage][tile of the batch]: finished flags (zeroed before the launch)
+  unsigned int *slot_done;      // per slot: readout tiles finished (zeroed before the launch)
+  unsigned long long *stamps;   // per slot: wall clock when its last readout item finished
+  unsigned int *slot_flags;     // per-slot health word; bit 3 when a wait of one of its items ran out
+  int32_t spin_limit;           // polls of a dependency flag before the wait gives up
+};
+constexpr int PERSIST_TILE = 512;       // rows per persistent tile (before rounding down to whole REs)
+constexpr int PERSIST_ITEM_TILES = 4;   // tiles per work item
+
+// Item it of the persistent order -> (stage, slot, item of the slot).  IB(i) reads item_base[i], GS(i)
+// group_slot[i]; the same code runs in the kernel (scalar loads) and on the host.
+struct PersistIdx {
+  int stage, slot, item;
+};
+template <typename IB, typename GS>
+__host__ __device__ inline PersistIdx persist_decode(int it, int n_stages, int n_groups, IB ib, GS gs) {
+  auto last_at_most = [](int lo, int hi, int x, auto key) {   // largest i in [lo, hi] with key(i) <= x
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (key(mid) <= x) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  };
+  const int g = last_at_most(0, n_groups - 1, it, [&](int i) { return n_stages * ib(gs(i)); });
+  const int gs0 = gs(g), gs1 = gs(g + 1);
+  const int i0 = ib(gs0), ig = ib(gs1) - i0;
+  const int k = it - n_stages * i0;
+  PersistIdx r;
+  r.stage = k / ig;
+  const int gi = i0 + (k - r.stage * ig);
+  r.slot = last_at_most(gs0, gs1 - 1, gi, [&](int i) { return ib(i); });
+  r.item = gi - ib(r.slot);
+  return r;
+}
+// Workgroups of the persistent kernel that fit on the device at once (0 if it cannot run).
+int persist_max_grid();
+void launch_persist(const PersistArgs &a, int grid, hipStream_t st);
+// Clears n words (a fill kernel: no memset node in a captured graph).
+void launch_zero_words(unsigned int *p, int64_t n, hipStream_t st);
+
 // Slot simulator.
 struct SimParams {
   int n_taps, tap_spacing_ns, scs_khz;
@@ -171,6 +238,8 @@ struct WgradArgs {
 };
 template <typename T>
 void launch_wgrad(const WgradArgs<T> &a, hipStream_t st);
+// workgroups launch_wgrad runs per row partition (BF16 3x3 convolutions take three taps per workgroup)
+int wgrad_jobs_per_partition(int n_taps, int n_slices, bool bf16);
 void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
                          int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st,
                          bool acc = false);

@@ -14,6 +14,8 @@
 // (symbol t, subcarrier parity relative to the UE's CDM group, edge class):
 // the PE bias field has exactly that structure, so its weight gradient is the
 // same small table contracted with those sums.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -193,6 +195,174 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         dst[((4 * wm + m) * 16 + 4 * lk + i) * 128 + (4 * wn + n) * 16 + lr] = acc[m][n][i];
+}
+
+// BF16 weight gradient of a 3x3 convolution, three taps per workgroup.  A workgroup owns one (row
+// partition, tap row di, 128-channel input slice) and the three taps dj = -1, 0, 1 of that row: per
+// 64-row step it stages dY once (transposed) and the three dj-shifted input windows (transposed, rows
+// whose neighbour lies outside the grid zero), so every staged dY row feeds three 128x128 blocks.  Eight
+// waves: 4 (32 input channels) x 2 (64 output channels), each holding 3 x 2 x 4 MFMA blocks.  The
+// partials go to the same [partition][tap][slice] layout as wgrad_kernel, summed by the same reduce.
+constexpr int W3_WAVES = 8;
+
+__global__ __launch_bounds__(64 * W3_WAVES, 1) void wgrad3_kernel(WgradArgs<bf16_t> a) {
+  __shared__ __align__(16) bf16_t xt[2][3][128 * TP];
+  __shared__ __align__(16) bf16_t dt[2][128 * TP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int wm = wave >> 1, wn = wave & 1;   // 32 input channels x 64 output channels per wave
+  constexpr int KF = mma<bf16_t>::KF;
+  const int njob = 3 * a.n_slices;
+  const int part = blockIdx.x / njob, job = blockIdx.x % njob;
+  const int dg = job / a.n_slices, slice = job % a.n_slices;
+  const int di = dg - 1;
+  const bf16_t *src;
+  int cs, coff;
+  if (slice * 128 < a.c0) { src = a.src0; cs = a.c0; coff = slice * 128; }
+  else { src = a.src1; cs = a.c1; coff = slice * 128 - a.c0; }
+  const int cwidth = cs - coff < 128 ? cs - coff : 128;
+
+  f32x4_t acc[3][2][4];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[t][m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = (int)((int64_t)a.n_tiles * part / a.n_part);
+  const int t1 = (int)((int64_t)a.n_tiles * (part + 1) / a.n_part);
+  struct Cur {
+    int ti, k0, nrows, row0, U, S;
+    int64_t base;
+  };
+  auto set_tile = [&](Cur &c, int ti) {
+    c.ti = ti;
+    c.k0 = 0;
+    if (ti < t1) {
+      const Tile tl = a.tiles[ti];
+      const SlotGeo &g = a.geo[tl.slot];
+      c.nrows = tl.nrows;
+      c.row0 = tl.row0;
+      c.U = g.U;
+      c.S = g.S;
+      c.base = g.row_base;
+    }
+  };
+  auto next = [&](Cur &c) {
+    c.k0 += RS;
+    if (c.k0 >= c.nrows) set_tile(c, c.ti + 1);
+  };
+  // staging pairs of a thread: p = tid + 512 j; which = p / 256 (0..2: input window of tap dj = which - 1,
+  // 3: dY); 4 consecutive rows (4 rg ..) x 8 consecutive channels (8 cg ..) of the step
+  struct Stage {
+    uint32_t v[2][4][4];
+  };
+  auto load = [&](const Cur &c, Stage &stg) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int p = tid + 512 * j, which = p >> 8, q = p & 255, rg = q & 15, cg = q >> 4;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) stg.v[j][r4][w] = 0u;
+      if (c.ti >= t1) continue;
+      const int rps = 14 * c.U;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int r = c.k0 + 4 * rg + r4;
+        if (r >= c.nrows) continue;
+        const int R = c.row0 + r;
+        const int64_t grow = c.base + R;
+        if (which == 3) {
+          const v16 dv = ld16(a.dy + grow * NRX_D + 8 * cg);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) stg.v[j][r4][w] = dv.w[w];
+        } else {
+          const int dj = which - 1;
+          const int s = R / rps, t = (R - s * rps) / c.U;
+          const int sn = s + di, tn = t + dj;
+          if (sn >= 0 && sn < c.S && tn >= 0 && tn < 14 && 8 * cg < cwidth) {
+            const v16 xv = ld16(src + (grow + di * rps + dj * c.U) * cs + coff + 8 * cg);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) stg.v[j][r4][w] = xv.w[w];
+          }
+        }
+      }
+    }
+  };
+  auto store = [&](int b, const Stage &stg) {
+    // channel 2w / 2w + 1 of rows (q, q + 1) from the low / high halves of word w: the 4 rows of a channel are
+    // contiguous in the transposed tile, one 8-byte store per channel
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int p = tid + 512 * j, which = p >> 8, q = p & 255, rg = q & 15, cg = q >> 4;
+      bf16_t *dst = which == 3 ? dt[b] : xt[b][which];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        uint32_t lo[2], hi[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          lo[h] = (stg.v[j][2 * h][w] & 0xFFFFu) | (stg.v[j][2 * h + 1][w] << 16);
+          hi[h] = (stg.v[j][2 * h][w] >> 16) | (stg.v[j][2 * h + 1][w] & 0xFFFF0000u);
+        }
+        *reinterpret_cast<uint2 *>(&dst[(8 * cg + 2 * w) * TP + 4 * rg]) = make_uint2(lo[0], lo[1]);
+        *reinterpret_cast<uint2 *>(&dst[(8 * cg + 2 * w + 1) * TP + 4 * rg]) = make_uint2(hi[0], hi[1]);
+      }
+    }
+  };
+
+  // pipeline: LDS buffer b holds step k; registers hold steps k+1 (s1) and k+2 (being loaded into s0)
+  Cur c0, c1, c2;
+  set_tile(c0, t0);
+  if (c0.ti < t1) {
+    c1 = c0;
+    next(c1);
+    c2 = c1;
+    if (c2.ti < t1) next(c2);
+    Stage s0, s1;
+    load(c0, s0);
+    store(0, s0);
+    load(c1, s1);
+    __syncthreads();
+    int b = 0;
+    while (c0.ti < t1) {
+      load(c2, s0);
+#pragma unroll
+      for (int f = 0; f < RS / KF; ++f) {
+        v16 bfr[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) bfr[n] = ld16(&dt[b][((4 * wn + n) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const v16 af = ld16(&xt[b][t][((2 * wm + m) * 16 + lr) * TP + f * KF + lk * (KF / 4)]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[t][m][n] = mfma_bf16(af, bfr[n], acc[t][m][n]);
+          }
+      }
+      if (c1.ti < t1) store(b ^ 1, s1);
+      __syncthreads();
+      b ^= 1;
+      c0 = c1;
+      c1 = c2;
+      if (c2.ti < t1) next(c2);
+      s1 = s0;
+    }
+  }
+  // partials [part][tap][slice][c 128][o 128], tap = 3 (di + 1) + (dj + 1)
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    float *dst = a.partials + ((int64_t)part * 9 * a.n_slices + (3 * dg + t) * a.n_slices + slice) * 128 * 128;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dst[((2 * wm + m) * 16 + 4 * lk + i) * 128 + (4 * wn + n) * 16 + lr] = acc[t][m][n][i];
+  }
 }
 
 // dw[layout] = sum over partitions, fixed order (added to dw when acc)
@@ -626,8 +796,17 @@ __global__ void readout_w2_reduce_kernel(const float *part, int n, int m_max, in
 
 template <typename T>
 void launch_wgrad(const WgradArgs<T> &a, hipStream_t st) {
+  if constexpr (std::is_same<T, bf16_t>::value) {
+    if (a.n_taps == 9) {   // 3x3 convolutions: three taps per workgroup
+      hipLaunchKernelGGL(wgrad3_kernel, dim3(a.n_part * 3 * a.n_slices), dim3(64 * W3_WAVES), 0, st, a);
+      return;
+    }
+  }
   const int grid = a.n_part * a.n_taps * a.n_slices;
   hipLaunchKernelGGL(wgrad_kernel<T>, dim3(grid), dim3(256), 0, st, a);
+}
+int wgrad_jobs_per_partition(int n_taps, int n_slices, bool bf16) {
+  return (bf16 && n_taps == 9) ? 3 * n_slices : n_taps * n_slices;
 }
 void launch_wgrad_reduce(const float *partials, int n_part, int n_taps, int tap0, int n_slices, int cin_real,
                          int cin_total, int conv, int64_t dst_off, float *dw, hipStream_t st, bool acc) {

@@ -28,6 +28,7 @@
 #include "common.h"
 #include "internal.h"
 #include "conv_common.h"
+#include "conv_ring.h"
 
 #ifndef NRX_LDS_MB
 #define NRX_LDS_MB 6
@@ -366,199 +367,22 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_lds_kernel(ConvArgs<T> a) 
   conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(lds_b0), a.ln_part, tid, wave, lr, lk);
 }
 
-// Ring variant: the same operands-in-LDS scheme with the K loop rolled and the
-// global -> LDS copies issued as inline assembly (dma16), so buffer slots are
-// chosen at run time without the compiler draining the DMA queue before LDS
-// reads.  G taps of weights per ring slot and NBUF slots: the weights of group
-// k + NBUF - 1 are requested while group k computes (weights are the same for
-// every tile, so the ring runs on across tiles), which hides NBUF - 1 groups of
-// DMA latency.  The next chunk's halo (or the next tile's first chunk) is
-// requested at the first group of a chunk.  G = 1 with small slots also lets two
-// 256-row workgroups share a CU, so one workgroup's epilogue overlaps the other's
-// MFMAs.
-//
-// DMA accounting (per wave, in issue order): every group issues BPW weight
-// copies, and a chunk's first group APW halo copies after them.  At the end of
-// group k the weights of group k + 1 must have landed; they were requested NBUF - 2
-// groups earlier, and at least (NBUF - 2) BPW weight copies (plus APW halo copies
-// if a halo was requested since) were issued after them, so s_waitcnt vmcnt of that
-// count suffices.  A halo requested at a chunk's first group is covered by the
-// wait at the chunk's last group (NG - 1 > NBUF - 2 groups later).
-// SCHED: 0 scheduling barriers between pipeline steps, 1 none (compiler interleaves),
-// 2 scheduling barriers and raised wave priority around the MFMA steps
-template <typename T, int EPI, int MB, int NW, int G, int OCC, int NBUF, int SCHED>
+// Ring variant: the same operands-in-LDS scheme with the K loop rolled and the global -> LDS
+// copies issued as inline assembly (dma16), so buffer slots are chosen at run time without the
+// compiler draining the DMA queue before LDS reads (conv_ring.h).  G = 1 with small slots also lets
+// two 256-row workgroups share a CU, so one workgroup's epilogue overlaps the other's MFMAs.
+template <typename T, int EPI, int MB, int NW, int G, int OCC, int NBUF, int SCHED, int STAG, int ALIGNED>
 __global__ __launch_bounds__(64 * NW, OCC) void conv3x3_ring_kernel(ConvArgs<T> a) {
-  constexpr int TILE = 16 * MB * NW;
-  constexpr int HMAX = halo_rows_max(TILE);
-  constexpr int NINS = HMAX / 16;
-  constexpr int APW = (NINS + NW - 1) / NW;
-  constexpr int AROWS = APW * NW * 16;
-  constexpr int ZROW = AROWS;
-  constexpr int KC = 64 / (int)sizeof(T);
-  constexpr int NG = 9 / G;                        // weight groups per chunk
-  constexpr int BROWS = G * 8 * 16;                // 64-byte weight rows per group
-  constexpr int BINS = BROWS / 16;                 // weight DMA instructions per group
-  constexpr int BPW = BINS / NW;
-  static_assert(9 % G == 0 && BINS % NW == 0, "shape");
-  static_assert(NBUF >= 2 && NG - 1 > NBUF - 2, "ring depth");
-  constexpr int NB_ = (NBUF - 2) * BPW;
-  static_assert(NB_ + APW < 16, "vmcnt immediate below");
-  constexpr int WAIT_B = (0xF << 8) | (7 << 4) | NB_;            // weights of the next group landed
-  constexpr int WAIT_BA = (0xF << 8) | (7 << 4) | (NB_ + APW);   // the same with a halo issued since
-  __shared__ __align__(16) unsigned char lds_a[2][(AROWS + 1) * ROWB];
-  __shared__ __align__(16) unsigned char lds_b[NBUF][BROWS * ROWB];
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int lr = lane & 15, lk = lane >> 4;
-  if (tid < 4) {
-    v16 z = {{0, 0, 0, 0}};
-    st16(&lds_a[0][ZROW * ROWB + tid * 16], z);
-    st16(&lds_a[1][ZROW * ROWB + tid * 16], z);
-  }
-  const int nch = (a.c0 + a.c1) / KC;
+  using Sh = RingShape<MB, NW, G, NBUF, ALIGNED>;
+  __shared__ __align__(16) unsigned char lds[Sh::LDS_BYTES];
   float lnp[EPI == EPI_LN_BWD ? 16 : 1];
 #pragma unroll
   for (int k = 0; k < (EPI == EPI_LN_BWD ? 16 : 1); ++k) lnp[k] = 0.f;
-
-  const int Gd = gridDim.x;
-  const int lb = (blockIdx.x & 7) * (Gd >> 3) + (blockIdx.x >> 3);
-  const i32x4_t wrs = rsrc_words(a.w, 0x7FFFFFFF);
-  // weights of group k (chunk k / NG, taps G * (k % NG) ..) into ring slot b
-  auto stage_b = [&](int k, int b) {
-    const int c = k / NG, grp = k - NG * c;
-    const uint32_t base = (uint32_t)((c * 9 + G * grp) * 8 * 16) * ROWB;
-#pragma unroll
-    for (int j = 0; j < BPW; ++j) {
-      const int ins = wave + NW * j;
-      const int row = ins * 16 + (lane >> 2);
-      const int piece = (lane & 3) ^ swz(row);
-      dma16(wrs, lds_addr(&lds_b[b][ins * 16 * ROWB]), base + row * ROWB + piece * 16);
-    }
-  };
-  struct Geo {
-    int64_t row_base;
-    int rel0, halo, S, rps, U;
-  };
-  auto geo_of = [&](const Tile &tl) {
-    const SlotGeo g = ldc_geo(a.geo + tl.slot);
-    Geo q;
-    q.U = g.U;
-    q.S = g.S;
-    q.rps = 14 * g.U;
-    const int s_first = tl.row0 / q.rps;
-    const int s_last = (tl.row0 + tl.nrows - 1) / q.rps;
-    q.halo = (s_last - s_first + 3) * q.rps;
-    q.rel0 = (s_first - 1) * q.rps;
-    q.row_base = g.row_base;
-    return q;
-  };
-  auto stage_a = [&](const Geo &q, int c, int b) {
-    const T *src;
-    int cs, coff;
-    if (c * KC < a.c0) { src = a.src0; cs = a.c0; coff = c * KC; }
-    else { src = a.src1; cs = a.c1; coff = c * KC - a.c0; }
-    const i32x4_t rs = rsrc_words(src + q.row_base * cs + coff, q.S * q.rps * cs * (int)sizeof(T));
-#pragma unroll
-    for (int j = 0; j < APW; ++j) {
-      const int ins = wave + NW * j;
-      const int h = ins * 16 + (lane >> 2);
-      const int piece = (lane & 3) ^ swz(h);
-      // rows past the halo read out of range (zeros); the instruction count per wave stays fixed
-      const uint32_t voff = h < q.halo ? (uint32_t)((q.rel0 + h) * cs * (int)sizeof(T) + piece * 16) : 0x80000000u;
-      dma16(rs, lds_addr(&lds_a[b][ins * 16 * ROWB]), voff);
-    }
-  };
-
-  int ka = 0, kb = 0, gsa = 1 << 20;   // halo buffer, weight-slot counter, groups since a halo request
-  int tile = lb;
-  if (tile < a.n_tiles) {
-    const int ngrp0 = NG * nch;
-#pragma unroll 1
-    for (int j = 0; j < NBUF - 1; ++j) stage_b(j % ngrp0, j);
-    stage_a(geo_of(ldc(a.tiles + tile)), 0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    dma_barrier();
-  }
-  for (; tile < a.n_tiles; tile += Gd) {
-    const Tile tl = ldc(a.tiles + tile);
-    const Geo q = geo_of(tl);
-    int hc[MB], tt[MB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const int r = wave * 16 * MB + mb * 16 + lr;
-      const int R = tl.row0 + r;
-      const int s = R / q.rps;
-      tt[mb] = r < tl.nrows ? (R - s * q.rps) / q.U : -1;
-      hc[mb] = R - q.rel0;
-    }
-    f32x4_t acc[MB][8];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb) acc[mb][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    const int ngrp = NG * nch;
-    const int next_tile = tile + Gd;
-#pragma unroll 1
-    for (int k = 0; k < ngrp; ++k) {
-      const int c = k / NG, grp = k - NG * c;
-      // weights NBUF - 1 groups ahead (wrapping into the next tile's groups), then the next halo
-      stage_b((k + NBUF - 1) % ngrp, (kb + NBUF - 1) % NBUF);
-      ++gsa;
-      if (grp == 0) {
-        if (c + 1 < nch) { stage_a(q, c + 1, (ka + 1) & 1); gsa = 0; }
-        else if (next_tile < a.n_tiles) { stage_a(geo_of(ldc(a.tiles + next_tile)), 0, (ka + 1) & 1); gsa = 0; }
-      }
-      const unsigned char *la = &lds_a[ka & 1][0];
-      const unsigned char *lbr = &lds_b[kb % NBUF][0];
-      // the G taps x 8 n-blocks of the group as one software pipeline: weight
-      // fragments two steps ahead, the next tap's activation fragments half a tap ahead
-      auto load_a = [&](int tg, v16 *af) {
-        const int tap = G * grp + tg;
-        const int di = tap / 3 - 1, dj = tap % 3 - 1;
-        const int off = di * q.rps + dj * q.U;
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-          const bool ok = tt[mb] >= 0 && (dj >= 0 || tt[mb] > 0) && (dj <= 0 || tt[mb] < 13);
-          const int row = ok ? hc[mb] + off : ZROW;
-          af[mb] = ld16(la + row * ROWB + ((lk ^ swz(row)) << 4));
-        }
-      };
-      auto load_bf = [&](int i) {
-        const int brow = i * 16 + lr;   // step i = tg * 8 + nb
-        return ld16(lbr + brow * ROWB + ((lk ^ swz(brow)) << 4));
-      };
-      v16 afc[MB], afn[MB];
-      load_a(0, afc);
-      v16 b0 = load_bf(0), b1 = load_bf(1);
-      if constexpr (SCHED == 2) __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-      for (int i = 0; i < 8 * G; ++i) {
-        const int nb = i & 7;
-        const v16 b2 = i + 2 < 8 * G ? load_bf(i + 2) : b1;
-        if (nb == 4 && i / 8 + 1 < G) load_a(i / 8 + 1, afn);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mma<T>::run(afc[mb], b0, acc[mb][nb]);
-        if (nb == 7 && i / 8 + 1 < G) {
-#pragma unroll
-          for (int mb = 0; mb < MB; ++mb) afc[mb] = afn[mb];
-        }
-        b0 = b1;
-        b1 = b2;
-        if constexpr (SCHED != 1) __builtin_amdgcn_sched_barrier(0);
-      }
-      if constexpr (SCHED == 2) __builtin_amdgcn_s_setprio(0);
-      if (gsa <= NBUF - 2) __builtin_amdgcn_s_waitcnt(WAIT_BA);
-      else __builtin_amdgcn_s_waitcnt(WAIT_B);
-      dma_barrier();
-      kb += 1;
-      if (grp == NG - 1) ka += 1;
-    }
-    conv_epilogue<T, MB, EPI>(a, tl, ldc_geo(a.geo + tl.slot), acc, wave, lr, lk, lnp);
-  }
-  __builtin_amdgcn_s_waitcnt(0);   // no copy into LDS outlives the workgroup
-  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(&lds_b[0][0]), a.ln_part, tid, wave, lr, lk);
+  conv_ring_body<T, EPI, MB, NW, G, NBUF, SCHED, GridTiles, STAG, ALIGNED>(a, GridTiles(a.tiles, a.n_tiles),
+                                                                           (lds_u8 *)lds, lnp);
+  const int tid = threadIdx.x, lane = tid & 63;
+  conv_ln_reduce<EPI, NW>(lnp, reinterpret_cast<float *>(lds + 2 * Sh::ABYTES), a.ln_part, tid, tid >> 6, lane & 15,
+                          lane >> 4);
 }
 
 }  // namespace
@@ -577,6 +401,9 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {8, 1, 3},            // ring kernel: 512-row tiles of 8 waves, six 1-tap slots (weights 5 taps ahead)
     {8, 1, 3},            // as 7, scheduling left to the compiler
     {8, 1, 3},            // as 7, raised wave priority over the MFMA steps
+    {8, 1, 3},            // as 7, workgroups started at staggered times
+    {8, 1, 3},            // as 10, workgroups started at staggered times
+    {8, 1, 3, 1},         // as 7 on 504-row tiles of whole subcarriers, three 3-tap weight slots
 };
 
 template <typename T>
@@ -617,26 +444,29 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_LDS_CASE(4, NRX_LDS_MB, 4)
   NRX_LDS_CASE(5, 4, 8)
 #undef NRX_LDS_CASE
-#define NRX_RING_CASE(V, M, NWV, GV, OCCV, NBV, SCH)                                                              \
+#define NRX_RING_CASE(V, M, NWV, GV, OCCV, NBV, SCH, STG, ALG)                                            \
   if (variant == V) {                                                                                   \
     dim3 b2(64 * NWV);                                                                                  \
     if (epi == EPI_STORE)                                                                               \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_STORE, M, NWV, GV, OCCV, NBV, SCH, STG, ALG>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_LN_RELU)                                                                        \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU, M, NWV, GV, OCCV, NBV, SCH, STG, ALG>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_RESID)                                                                          \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_RESID, M, NWV, GV, OCCV, NBV, SCH, STG, ALG>), dim3(grid), b2, 0, st, a); \
     else if (epi == EPI_LN_RELU_SAVE)                                                                   \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU_SAVE, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_RELU_SAVE, M, NWV, GV, OCCV, NBV, SCH, STG, ALG>), dim3(grid), b2, 0, st, a); \
     else                                                                                                \
-      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV, SCH>), dim3(grid), b2, 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_ring_kernel<T, EPI_LN_BWD, M, NWV, GV, OCCV, NBV, SCH, STG, ALG>), dim3(grid), b2, 0, st, a); \
     return;                                                                                             \
   }
-  NRX_RING_CASE(6, 4, 4, 1, 2, 2, 0)
-  NRX_RING_CASE(7, 4, 8, 3, 1, 2, 0)
-  NRX_RING_CASE(8, 4, 8, 1, 1, 6, 0)
-  NRX_RING_CASE(9, 4, 8, 3, 1, 2, 1)
-  NRX_RING_CASE(10, 4, 8, 3, 1, 2, 2)
+  NRX_RING_CASE(6, 4, 4, 1, 2, 2, 0, 0, 0)
+  NRX_RING_CASE(7, 4, 8, 3, 1, 2, 0, 0, 0)
+  NRX_RING_CASE(8, 4, 8, 1, 1, 6, 0, 0, 0)
+  NRX_RING_CASE(9, 4, 8, 3, 1, 2, 1, 0, 0)
+  NRX_RING_CASE(10, 4, 8, 3, 1, 2, 2, 0, 0)
+  NRX_RING_CASE(11, 4, 8, 3, 1, 2, 0, 1, 0)
+  NRX_RING_CASE(12, 4, 8, 3, 1, 2, 2, 1, 0)
+  NRX_RING_CASE(13, 4, 8, 3, 1, 3, 0, 0, 1)
 #undef NRX_RING_CASE
 }
 

@@ -32,7 +32,7 @@ constexpr int BSLOT = 8 * 16 * BROWB;
 
 __device__ __forceinline__ int bswz(int row) { return row & 7; }
 
-template <int EPI, int MB, int NW>
+template <int EPI, int MB, int NW, int STAG>
 __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t> a) {
   constexpr int TILE = 16 * MB * NW;
   constexpr int HMAX = halo_rows_max(TILE);
@@ -57,6 +57,11 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
   }
   const int nch = (a.c0 + a.c1) / KC;   // even (checked by the host)
   float lnp[1];
+  if constexpr (STAG) {   // staggered start (see conv_ring_body): tile epilogues spread over time
+    const uint64_t t0 = wall_clock64();
+    const uint64_t wait = (uint64_t)((blockIdx.x >> 3) & 15) * 225;
+    while (wall_clock64() - t0 < wait) __builtin_amdgcn_s_sleep(8);
+  }
 
   const int G = gridDim.x;
   const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
@@ -254,20 +259,22 @@ const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS] = {
     {8, 2, 2},   // 512-row tiles of 8 waves (4 m-blocks each), 2 waves/SIMD
     {6, 1, 2},   // 384-row tiles of 4 waves (6 m-blocks each)
     {4, 1, 2},   // 256-row tiles of 4 waves (4 m-blocks each)
+    {8, 2, 2},   // as 0, workgroups started at staggered times
 };
 
 void launch_conv8(const ConvArgs<bf16_t> &a, int epi, int variant, int grid, hipStream_t st) {
-#define NRX_FP8_CASE(V, M, NWV)                                                                        \
+#define NRX_FP8_CASE(V, M, NWV, STG)                                                                   \
   if (variant == V) {                                                                                  \
     if (epi == EPI_LN_RELU)                                                                            \
-      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_LN_RELU, M, NWV>), dim3(grid), dim3(64 * NWV), 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_LN_RELU, M, NWV, STG>), dim3(grid), dim3(64 * NWV), 0, st, a); \
     else                                                                                               \
-      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_RESID, M, NWV>), dim3(grid), dim3(64 * NWV), 0, st, a);   \
+      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_RESID, M, NWV, STG>), dim3(grid), dim3(64 * NWV), 0, st, a);   \
     return;                                                                                            \
   }
-  NRX_FP8_CASE(0, 4, 8)
-  NRX_FP8_CASE(1, 6, 4)
-  NRX_FP8_CASE(2, 4, 4)
+  NRX_FP8_CASE(0, 4, 8, 0)
+  NRX_FP8_CASE(1, 6, 4, 0)
+  NRX_FP8_CASE(2, 4, 4, 0)
+  NRX_FP8_CASE(3, 4, 8, 1)
 #undef NRX_FP8_CASE
 }
 

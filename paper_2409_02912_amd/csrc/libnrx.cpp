@@ -52,9 +52,14 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 namespace {
 
 constexpr int MLP_TILE = 128;
-constexpr int N_TILE_SIZES = 4;            // conv tiles of 128, 256, 384 and 512 rows (mb = 2, 4, 6, 8)
+constexpr int PERSIST_GROUP = 1024;        // tiles per slot group of the persistent forward (one item per CU)
+// conv tiles of 128, 256, 384 and 512 rows (mb = 2, 4, 6, 8), and of 504 rows: whole subcarriers for
+// every UE count (504 = 36, 18, 12, 9 subcarriers of 14, 28, 42, 56 rows)
+constexpr int N_TILE_SIZES = 5;
+constexpr int ALIGNED_TILES = 4;
 inline int tile_size_index(int mb) { return mb / 2 - 1; }
-inline int tile_rows_of_index(int i) { return 128 * (i + 1); }
+inline int tile_rows_of_index(int i) { return i == ALIGNED_TILES ? CONV_ALIGNED_TILE : 128 * (i + 1); }
+inline int variant_tiles(const ConvVariant &v) { return v.aligned ? ALIGNED_TILES : tile_size_index(v.mb); }
 
 struct TensorInfo {
   std::string name;
@@ -93,11 +98,16 @@ struct Plan {
   std::vector<SlotGeo> geo;
   std::vector<Tile> ct[N_TILE_SIZES], mt, rt;
   std::vector<int64_t> pair_off, tap_off;
+  // persistent forward: per slot the first tile and the first item of a stage (n + 1 entries each) and rows
+  // per tile (whole REs, at most PERSIST_TILE); slot groups (first slot of each, n_groups + 1 entries) of at
+  // least PERSIST_GROUP tiles
+  std::vector<int32_t> ptile_base, pitem_base, ptile_rows, pgroup;
   int64_t rows = 0, max_rows = 0, max_re = 0, max_pairs = 0, max_ute = 0, max_bits = 0;
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
   // device table blob
-  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {0, 0, 0, 0}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0, meta_bytes = 0;
+  size_t off_geo = 0, off_ct[N_TILE_SIZES] = {}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0;
+  size_t off_ptb = 0, off_pib = 0, off_ptr = 0, off_pg = 0, meta_bytes = 0;
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
   void *packed_geo = nullptr;    // lmmse_demap: pinned geometry copy with h offsets into its workspace
@@ -109,6 +119,18 @@ struct Plan {
   }
 };
 using PlanRef = std::shared_ptr<Plan>;
+
+// A pinned host buffer; freed after the device has drained (an asynchronous copy may still read it).
+struct PinnedBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  ~PinnedBuf() {
+    if (ptr) {
+      (void)hipDeviceSynchronize();
+      (void)hipHostFree(ptr);
+    }
+  }
+};
 
 // Plans are keyed on every descriptor field (compared in full on a hit) and kept for the
 // PLAN_CACHE_MAX most recently used batches; a model's graph or saved forward holds its plan alive
@@ -240,6 +262,26 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   }
   P->pair_off.push_back(pr);
   P->tap_off.push_back(tp);
+  {
+    int32_t tb = 0, ib = 0, in_group = 0;
+    P->pgroup.push_back(0);
+    for (int i = 0; i < n; ++i) {
+      const int U = P->geo[i].U;
+      const int tr = (PERSIST_TILE / U) * U;
+      const int64_t rows_i = (int64_t)P->geo[i].S * 14 * U;
+      const int32_t cnt = (int32_t)((rows_i + tr - 1) / tr);
+      P->ptile_base.push_back(tb);
+      P->pitem_base.push_back(ib);
+      P->ptile_rows.push_back(tr);
+      tb += cnt;
+      ib += (cnt + PERSIST_ITEM_TILES - 1) / PERSIST_ITEM_TILES;
+      in_group += cnt;
+      if (in_group >= PERSIST_GROUP && i + 1 < n) { P->pgroup.push_back(i + 1); in_group = 0; }
+    }
+    P->ptile_base.push_back(tb);
+    P->pitem_base.push_back(ib);
+    P->pgroup.push_back(n);
+  }
   P->rows = row;
   P->dmrs_total = dm;
   P->pairs_total = pr;
@@ -250,6 +292,10 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->off_rt = o; o = align256(o + sizeof(Tile) * P->rt.size());
   P->off_pair = o; o = align256(o + sizeof(int64_t) * P->pair_off.size());
   P->off_tap = o; o = align256(o + sizeof(int64_t) * P->tap_off.size());
+  P->off_ptb = o; o = align256(o + sizeof(int32_t) * P->ptile_base.size());
+  P->off_pib = o; o = align256(o + sizeof(int32_t) * P->pitem_base.size());
+  P->off_ptr = o; o = align256(o + sizeof(int32_t) * P->ptile_rows.size());
+  P->off_pg = o; o = align256(o + sizeof(int32_t) * P->pgroup.size());
   P->meta_bytes = o;
   P->blob.assign(o, 0);
   char *b = P->blob.data();
@@ -259,6 +305,10 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   memcpy(b + P->off_rt, P->rt.data(), sizeof(Tile) * P->rt.size());
   memcpy(b + P->off_pair, P->pair_off.data(), sizeof(int64_t) * P->pair_off.size());
   memcpy(b + P->off_tap, P->tap_off.data(), sizeof(int64_t) * P->tap_off.size());
+  memcpy(b + P->off_ptb, P->ptile_base.data(), sizeof(int32_t) * P->ptile_base.size());
+  memcpy(b + P->off_pib, P->pitem_base.data(), sizeof(int32_t) * P->pitem_base.size());
+  memcpy(b + P->off_ptr, P->ptile_rows.data(), sizeof(int32_t) * P->ptile_rows.size());
+  memcpy(b + P->off_pg, P->pgroup.data(), sizeof(int32_t) * P->pgroup.size());
   *out = P;
   g_plans.plans[std::move(key)] = PlanCache::Entry{std::move(P), ++g_plans.tick};
   return NRX_OK;
@@ -282,6 +332,7 @@ struct Dev {
   const SlotGeo *geo;
   const Tile *ct[N_TILE_SIZES], *mt, *rt;
   const int64_t *pair_off, *tap_off;
+  const int32_t *ptile_base, *pitem_base, *ptile_rows, *pgroup;
 };
 
 Dev dev_tables(const Plan *P, char *ws) {
@@ -292,6 +343,10 @@ Dev dev_tables(const Plan *P, char *ws) {
   d.rt = (const Tile *)(ws + P->off_rt);
   d.pair_off = (const int64_t *)(ws + P->off_pair);
   d.tap_off = (const int64_t *)(ws + P->off_tap);
+  d.ptile_base = (const int32_t *)(ws + P->off_ptb);
+  d.pitem_base = (const int32_t *)(ws + P->off_pib);
+  d.ptile_rows = (const int32_t *)(ws + P->off_ptr);
+  d.pgroup = (const int32_t *)(ws + P->off_pg);
   return d;
 }
 
@@ -326,7 +381,8 @@ struct GraphKey {
 constexpr size_t GRAPH_CACHE_MAX = 64;   // captured forward graphs kept per model (least recently used evicted)
 struct Graphs {
   hipStream_t cap = nullptr;
-  struct Entry { hipGraphExec_t exec; PlanRef plan; uint64_t used; };   // the plan's pinned tables feed the graph
+  // the plan's pinned tables (and a persistent forward's stage table) feed the graph
+  struct Entry { hipGraphExec_t exec; PlanRef plan; uint64_t used; std::shared_ptr<PinnedBuf> ptable; };
   std::map<GraphKey, Entry> execs;
   uint64_t tick = 0;
 };
@@ -389,6 +445,11 @@ struct nrx_model {
   int saved_iters = 0;
   bool saved_multi = false;
   bool saved_chest = false;
+  // persistent forward (flags bit 3): stage tables by contents, and the one the last forward used
+  struct PTable { std::shared_ptr<PinnedBuf> buf; uint64_t used; };
+  std::map<std::string, PTable> ptables;
+  uint64_t ptable_tick = 0;
+  std::shared_ptr<PinnedBuf> last_ptable;
   std::mutex mu;
 };
 
@@ -422,6 +483,9 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
   if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
   if ((c.flags & 4) && c.precision == NRX_FP8) return fail(NRX_ERR_UNSUPPORTED, "Var-IO needs FP32 or BF16");
+  if ((c.flags & 8) && (c.precision != NRX_BF16 || (c.flags & 4)))
+    return fail(NRX_ERR_UNSUPPORTED, "the persistent forward (flags bit 3) runs BF16 models with shared input and output layers");
+  if (c.flags & ~15) return fail(NRX_ERR_INVALID, "unknown model flags 0x%x", c.flags);
   if ((c.flags & 2) && c.n_ant > 8)
     return fail(NRX_ERR_SHAPE, "ReadoutChEst has 2 n_ant outputs, at most 16: n_ant %d > 8", c.n_ant);
   auto m = std::make_unique<nrx_model>();
@@ -662,6 +726,7 @@ std::vector<int> iteration_ends(const nrx_model_config &c) {
 
 struct FwdLayout {
   size_t meta, jobs, wprep, fields, dmrs, pairs, X, done, stamps, flags;   // the same for save and inference
+  size_t pstages = 0, pctl = 0;   // persistent forward (model flags bit 3, inference): stage table, control words
   size_t h8 = 0, a8 = 0, agg8 = 0, w8 = 0, wsc = 0, f8jobs = 0, amax = 0;   // FP8 models
   std::vector<size_t> h;      // h_0 .. h_C (inference: one buffer)
   std::vector<size_t> z, a;   // per block (inference: one a buffer, no z)
@@ -674,6 +739,9 @@ struct FwdLayout {
   size_t wpart = 0, cpart = 0, lpart = 0, rpart = 0;
   size_t total;
 };
+
+// stages of the persistent forward: StateInit, message-passing rounds, two convs per block, readout
+int persist_stages(const nrx_model *m) { return 2 + m->cfg.n_rounds + 2 * m->cfg.n_blocks; }
 
 constexpr int WGRAD_PARTS = 512;      // bound on row partitions of the weight-gradient kernel
 constexpr int BWD_GRID_MAX = 4096;    // bound on per-workgroup partial buffers
@@ -694,6 +762,12 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
   L.stamps = o; o = align256(o + (size_t)(P->n + 1) * 8);
   L.flags = o; o = align256(o + (size_t)P->n * 4);
   const int C = m->cfg.n_blocks, R = m->cfg.n_rounds;
+  if ((m->cfg.flags & 8) && !save) {
+    const int ns = persist_stages(m);
+    L.pstages = o; o = align256(o + sizeof(PersistStage) * ns);
+    // two control words (claim counter, abort), then one finished flag per (stage, tile)
+    L.pctl = o; o = align256(o + 4 * (64 + (size_t)ns * P->ptile_base.back()));
+  }
   if (m->fp8) {
     const size_t act8 = align256((size_t)P->rows * NRX_D);
     L.h8 = o; o += act8;
@@ -727,7 +801,9 @@ FwdLayout fwd_layout(const nrx_model *m, const Plan *P, bool save) {
     L.dmsg = o; o += act;
     L.dm1 = o; o += act;
     L.dr = o; o += act;
-    L.wpart = o; o = align256(o + (size_t)2 * num_cu() * 128 * 128 * 4);   // partitions x jobs <= 2 blocks per CU
+    // partitions x (taps x slices) 128x128 partial blocks: <= 2 per CU for the one-tap-per-workgroup kernel,
+    // <= 3 per CU for the three-tap kernel (one workgroup per CU)
+    L.wpart = o; o = align256(o + (size_t)3 * num_cu() * 128 * 128 * 4);
     L.cpart = o; o = align256(o + (size_t)(P->n + 1) * 14 * 768 * 4);   // per-slot partials + reduced table
     L.lpart = o; o = align256(o + (size_t)BWD_GRID_MAX * 256 * 4);
     // dW2 partials: one set per readout for ReadoutLLRs, two (column groups) for ReadoutChEst
@@ -770,6 +846,52 @@ nrx_status model_pinned(nrx_model *m) {
     return fail(NRX_ERR_HIP, "hipHostMalloc failed");
   memcpy(m->pinned_jobs, m->jobs.data(), sizeof(PrepJob) * m->jobs.size());
   return NRX_OK;
+}
+
+// Stage kinds of the persistent forward over the first c_run blocks, in the order forward_impl adds them.
+std::vector<int> persist_kinds(const nrx_model *m, int c_run) {
+  std::vector<int> k{PK_CONV_STORE};
+  for (int i = 0; i < c_run; ++i) {
+    if (m->blocks[i].mp_round >= 0) k.push_back(PK_MP);
+    k.push_back(PK_CONV_LN);
+    k.push_back(PK_CONV_RESID);
+  }
+  k.push_back(PK_READOUT);
+  return k;
+}
+
+// Persistent stage tables in pinned host memory, keyed by their contents: a table never changes once
+// made, so an asynchronous copy (or a graph replay) always reads what its call wrote.
+constexpr size_t PERSIST_TABLES_MAX = 32;
+constexpr int PERSIST_SPIN_LIMIT = 1 << 21;   // polls of one dependency flag (far above any legal wait)
+int g_persist_grid = -1;
+int persist_grid() {
+  if (g_persist_grid < 0) g_persist_grid = persist_max_grid();
+  return g_persist_grid;
+}
+std::shared_ptr<PinnedBuf> persist_table(nrx_model *m, const std::vector<PersistStage> &pst) {
+  const size_t bytes = sizeof(PersistStage) * pst.size();
+  std::string key((const char *)pst.data(), bytes);
+  std::lock_guard<std::mutex> lk(m->mu);
+  auto it = m->ptables.find(key);
+  if (it != m->ptables.end()) {
+    it->second.used = ++m->ptable_tick;
+    m->last_ptable = it->second.buf;
+    return it->second.buf;
+  }
+  if (m->ptables.size() >= PERSIST_TABLES_MAX) {
+    auto lru = m->ptables.begin();
+    for (auto e = m->ptables.begin(); e != m->ptables.end(); ++e)
+      if (e->second.used < lru->second.used) lru = e;
+    m->ptables.erase(lru);   // a graph that captured it keeps its own reference
+  }
+  auto b = std::make_shared<PinnedBuf>();
+  if (hipHostMalloc(&b->ptr, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+  b->bytes = bytes;
+  memcpy(b->ptr, pst.data(), bytes);
+  m->ptables[key] = nrx_model::PTable{b, ++m->ptable_tick};
+  m->last_ptable = b;
+  return b;
 }
 
 template <typename T>
@@ -815,14 +937,32 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   if (amax) HIPCHK(hipMemsetAsync(amax, 0, m->act_scale.size() * 4, st));
 
   const int grid_mlp = std::min<int>((int)std::max(P->mt.size(), P->rt.size()), num_cu() * 4);
+  // persistent forward (model flags bit 3): the layers below are collected as stages of one launch
+  // instead of being launched one by one (plain BF16 inference: one readout, no second readout)
+  const bool persist = std::is_same<T, bf16_t>::value && (m->cfg.flags & 8) && !save && !f8 && !amax &&
+                       llr_stride == 0 && !hest && L.pctl;
+  std::vector<PersistStage> pst;
+  auto add_stage = [&](int kind, const void *args) {
+    if constexpr (std::is_same<T, bf16_t>::value) {
+      PersistStage e{};
+      e.kind = kind;
+      if (kind <= PK_CONV_RESID) e.c = *(const ConvArgs<bf16_t> *)args;
+      else e.m = *(const MlpArgs<bf16_t> *)args;
+      pst.push_back(e);
+    }
+  };
   // launch one conv of layer class cls with its selected variant (E4M3 kernels when fp8op)
   auto conv = [&](ConvArgs<T> ca, int epi, int cls, bool fp8op) {
+    if (persist) {
+      add_stage(epi == EPI_STORE ? PK_CONV_STORE : (epi == EPI_LN_RELU ? PK_CONV_LN : PK_CONV_RESID), &ca);
+      return;
+    }
     int v = m->conv_variant[cls];
     if (fp8op) v = std::min(v, NRX_CONV8_VARIANTS - 1);
     else if (kConvVariants[v].pref == 2 && ((ca.c0 + ca.c1) / (64 / (int)sizeof(T))) % 2)
       v = 1;   // the LDS-operand kernels walk the input channels two chunks at a time
     const ConvVariant &cv = fp8op ? kConv8Variants[v] : kConvVariants[v];
-    const int ti = tile_size_index(cv.mb);
+    const int ti = variant_tiles(cv);
     ca.tiles = D.ct[ti];
     ca.n_tiles = (int)P->ct[ti].size();
     int grid = std::min<int>(ca.n_tiles, num_cu() * cv.occ);
@@ -886,6 +1026,12 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ra.slot_done = fin ? (unsigned int *)(ws + L.done) : nullptr;
       ra.stamps = fin ? (unsigned long long *)(ws + L.stamps) : nullptr;
       ra.slot_flags = slot_flags;
+      if (persist) {   // the persistent kernel counts finished readout tiles itself
+        ra.slot_done = nullptr;
+        ra.stamps = nullptr;
+        add_stage(PK_READOUT, &ra);
+        continue;
+      }
       ProfMark pm(m, NRX_K_READOUT, st);
       launch_readout<T>(ra, grid_mlp, st);
     }
@@ -929,8 +1075,12 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ma.geo = D.geo;
       ma.tiles = D.mt;
       ma.n_tiles = (int)P->mt.size();
-      ProfMark pm(m, NRX_K_MP, st);
-      launch_mp<T>(ma, grid_mlp, st);
+      if (persist) {
+        add_stage(PK_MP, &ma);
+      } else {
+        ProfMark pm(m, NRX_K_MP, st);
+        launch_mp<T>(ma, grid_mlp, st);
+      }
     }
     ConvArgs<T> ca = a;
     ca.src0 = h_in; ca.c0 = NRX_D;
@@ -975,6 +1125,37 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     }
   }
   readout(c_run, llr_stride > 0 ? n_run - 1 : 0, true);
+  if (persist) {
+    const std::vector<int> kinds = persist_kinds(m, c_run);
+    bool same = kinds.size() == pst.size();
+    for (size_t i = 0; same && i < pst.size(); ++i) same = kinds[i] == pst[i].kind;
+    if (!same) return fail(NRX_ERR_INVALID, "persistent stage list out of step with the layer sequence");
+    const int grid = persist_grid();
+    if (grid <= 0) return fail(NRX_ERR_UNSUPPORTED, "the persistent forward kernel does not fit on this device");
+    std::shared_ptr<PinnedBuf> tab = persist_table(m, pst);
+    if (!tab) return fail(NRX_ERR_HIP, "hipHostMalloc of the persistent stage table failed");
+    HIPCHK(hipMemcpyAsync(ws + L.pstages, tab->ptr, tab->bytes, hipMemcpyHostToDevice, st));
+    const int64_t n_tiles = P->ptile_base.back();
+    unsigned int *ctl = (unsigned int *)(ws + L.pctl);
+    launch_zero_words(ctl, 64 + (int64_t)pst.size() * n_tiles, st);
+    PersistArgs pa{};
+    pa.stages = (const PersistStage *)(ws + L.pstages);
+    pa.n_stages = (int)pst.size();
+    pa.n_groups = (int)P->pgroup.size() - 1;
+    pa.geo = D.geo;
+    pa.tile_base = D.ptile_base;
+    pa.item_base = D.pitem_base;
+    pa.item_tiles = PERSIST_ITEM_TILES;
+    pa.tile_rows = D.ptile_rows;
+    pa.group_slot = D.pgroup;
+    pa.ctl = ctl;
+    pa.done = ctl + 64;
+    pa.slot_done = (unsigned int *)(ws + L.done);
+    pa.stamps = (unsigned long long *)(ws + L.stamps);
+    pa.slot_flags = slot_flags;
+    pa.spin_limit = PERSIST_SPIN_LIMIT;
+    launch_persist(pa, grid, st);
+  }
   HIPCHK(hipGetLastError());
   return NRX_OK;
 }
@@ -1075,6 +1256,35 @@ extern "C" int32_t nrx_num_iterations(const nrx_model *m) {
   return m ? (int32_t)iteration_ends(m->cfg).size() : 0;
 }
 
+extern "C" int64_t nrx_persist_schedule(nrx_model *m, const nrx_slot_desc *slots, int32_t n, int32_t *stage,
+                                        int32_t *slot, int32_t *tile, int32_t *n_tiles, int64_t cap, int32_t *kinds,
+                                        int32_t kinds_cap) {
+  if (!m || !stage || !slot || !tile || !n_tiles || !kinds) return (fail(NRX_ERR_INVALID, "null argument"), -1);
+  if (!(m->cfg.flags & 8)) return (fail(NRX_ERR_INVALID, "the model has no persistent forward (flags bit 3)"), -1);
+  PlanRef PR;
+  if (get_plan(slots, n, m->cfg.n_ant, m->cfg.m_max, 0, &PR) != NRX_OK) return -1;
+  const Plan *P = PR.get();
+  const std::vector<int> ends = iteration_ends(m->cfg);
+  const int n_run = m->n_iter > 0 ? m->n_iter : (int)ends.size();
+  const std::vector<int> k = persist_kinds(m, ends[n_run - 1]);
+  const int ns = (int)k.size();
+  const int64_t items = (int64_t)ns * P->pitem_base.back();
+  if (cap < items || kinds_cap < ns) return (fail(NRX_ERR_SHAPE, "room for %lld items and %d stages needed",
+                                                   (long long)items, ns), -1);
+  for (int i = 0; i < ns; ++i) kinds[i] = k[i];
+  const int ng = (int)P->pgroup.size() - 1;
+  for (int64_t it = 0; it < items; ++it) {
+    const PersistIdx x = persist_decode((int)it, ns, ng, [&](int i) { return P->pitem_base[i]; },
+                                        [&](int i) { return P->pgroup[i]; });
+    const int cnt = P->ptile_base[x.slot + 1] - P->ptile_base[x.slot];
+    stage[it] = x.stage;
+    slot[it] = x.slot;
+    tile[it] = x.item * PERSIST_ITEM_TILES;
+    n_tiles[it] = std::min(PERSIST_ITEM_TILES, cnt - tile[it]);
+  }
+  return items;
+}
+
 namespace {
 template <typename F>
 nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F run, hipStream_t st) {
@@ -1093,6 +1303,11 @@ nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F
     // host-side allocations happen before the capture
     nrx_status ps = model_pinned(m);
     if (ps != NRX_OK) return ps;
+    if (m->cfg.flags & 8) {
+      // the persistent forward's stage table (pinned) is made by an eager pass on the caller's stream
+      ps = run(st);
+      if (ps != NRX_OK) return ps;
+    }
     {
       std::lock_guard<std::mutex> lk(g_plans.mu);
       if (!P->pinned) {
@@ -1103,6 +1318,10 @@ nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F
     }
     if (!m->graphs->cap) HIPCHK(hipStreamCreateWithFlags(&m->graphs->cap, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(m->mu);
+      m->last_ptable.reset();   // set by a persistent forward to the stage table the graph will copy
+    }
     HIPCHK(hipStreamBeginCapture(m->graphs->cap, hipStreamCaptureModeThreadLocal));
     nrx_status s = run(m->graphs->cap);
     hipError_t e = hipStreamEndCapture(m->graphs->cap, &graph);
@@ -1120,7 +1339,7 @@ nrx_status graph_forward(nrx_model *m, const PlanRef &PR, const GraphKey &key, F
       (void)hipGraphExecDestroy(lru->second.exec);
       m->graphs->execs.erase(lru);
     }
-    m->graphs->execs[key] = Graphs::Entry{exec, PR, ++m->graphs->tick};
+    m->graphs->execs[key] = Graphs::Entry{exec, PR, ++m->graphs->tick, m->last_ptable};
   }
   HIPCHK(hipGraphLaunch(exec, st));
   return NRX_OK;
@@ -1353,8 +1572,10 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     a.n_taps = conv ? 9 : 1;
     a.tap0 = conv ? 0 : 4;
     a.n_slices = (c0 + c1 + 127) / 128;
-    // one round of workgroups (2 per CU), all with the same number of rows
-    a.n_part = std::max(1, std::min(WGRAD_PARTS, (2 * num_cu()) / (a.n_taps * a.n_slices)));
+    // one round of workgroups (2 per CU; 1 for the 8-wave three-tap kernel), all with the same number of rows
+    const int jobs = wgrad_jobs_per_partition(a.n_taps, a.n_slices, std::is_same<T, bf16_t>::value);
+    const int per_cu = jobs == a.n_taps * a.n_slices ? 2 : 1;
+    a.n_part = std::max(1, std::min(WGRAD_PARTS, (per_cu * num_cu()) / jobs));
     a.partials = wpart;
     launch_wgrad<T>(a, st);
     launch_wgrad_reduce(wpart, a.n_part, a.n_taps, a.tap0, a.n_slices, cin_real, cin_total, conv ? 1 : 0, dst, dw,
@@ -1383,7 +1604,7 @@ nrx_status backward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const 
     int v = epi == EPI_LN_BWD ? 4 : m->conv_variant[cls];
     if (kConvVariants[v].pref == 2 && ((a.c0 + a.c1) / (64 / (int)sizeof(T))) % 2) v = 1;
     const ConvVariant &cv = kConvVariants[v];
-    const int ti = tile_size_index(cv.mb);
+    const int ti = variant_tiles(cv);
     a.tiles = D.ct[ti];
     a.n_tiles = (int)P->ct[ti].size();
     int grid = std::min<int>(a.n_tiles, std::min(num_cu() * cv.occ, BWD_GRID_MAX));

@@ -95,6 +95,7 @@ _SIGS = {
     "nrx_calibrate": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp]),
     "nrx_slot_flags": (_i32, [_vp, _DESC, _i32, _vp, _sz, _vp, _vp]),
     "nrx_fallback_lmmse": (_i32, [_DESC, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nrx_persist_schedule": (_i64, [_vp, _DESC, _i32, _vp, _vp, _vp, _vp, _i64, _vp, _i32]),
     "nrx_saved_token": (_i64, [_vp]),
     "nrx_check_token": (_i32, [_vp, _vp, _i64]),
     "nrx_last_error": (ctypes.c_char_p, []),
@@ -319,6 +320,20 @@ def nrx_fallback_lmmse(slots, m_max, y, flags, llr, ws, h=None, n0=None, stream=
     arr, n = _descs(slots)
     _check(_lib.nrx_fallback_lmmse(arr, n, m_max, _ptr(y), _ptr(h), _ptr(n0), _ptr(flags), _ptr(llr), _ptr(ws),
                                    ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def nrx_persist_schedule(model, slots, cap=1 << 22):
+    """Work order of the persistent forward: (stage, slot, first tile, tiles) arrays over the items, and the
+    stage kinds."""
+    arr, n = _descs(slots)
+    st, sl, ti, nt = (np.zeros(cap, dtype=np.int32) for _ in range(4))
+    kinds = np.zeros(64, dtype=np.int32)
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    k = int(_lib.nrx_persist_schedule(model, arr, n, c(st), c(sl), c(ti), c(nt), cap, c(kinds), 64))
+    if k < 0:
+        raise NrxError(NRX_ERR_INVALID, _lib.nrx_last_error().decode())
+    ns = int(st[:k].max()) + 1 if k else 0
+    return st[:k].copy(), sl[:k].copy(), ti[:k].copy(), nt[:k].copy(), kinds[:ns].copy()
 
 
 def nrx_saved_token(model):

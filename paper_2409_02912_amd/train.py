@@ -157,7 +157,24 @@ class Trainer:
             L.nrx_bce(self.descs, self.m_max, self.llr, self.bits, self.dllr, self.loss, self.nerr, self.bws)
             L.nrx_backward(self.model, self.params, self.descs, self.dllr, self.grad, self.ws)
         self.step += 1
-        L.nrx_adam(self.params, self.grad, self.m, self.v, self.step, lr=self.lr)
+        L.nrx_adam(self.params, self.grad, self.m, self.v, self.step, lr=self.lr_at(self.step))
+
+    def lr_at(self, step):
+        """Learning rate of an Adam step: self.lr, or with a schedule set by set_schedule a linear warm-up over
+        `warmup` steps from its start, then a cosine decay to lr_final at step `end`."""
+        sch = getattr(self, "schedule", None)
+        if not sch:
+            return self.lr
+        k = step - sch["start"]
+        if k < sch["warmup"]:
+            return self.lr * (k + 1) / sch["warmup"]
+        span = max(sch["end"] - sch["start"] - sch["warmup"], 1)
+        f = min(max((k - sch["warmup"]) / span, 0.0), 1.0)
+        return sch["lr_final"] + 0.5 * (self.lr - sch["lr_final"]) * (1.0 + math.cos(math.pi * f))
+
+    def set_schedule(self, start, end, warmup=0, lr_final=None):
+        self.schedule = {"start": int(start), "end": int(end), "warmup": int(warmup),
+                         "lr_final": self.lr if lr_final is None else float(lr_final)}
 
     def close(self):
         L.nrx_model_destroy(self.model)
@@ -276,6 +293,11 @@ def main():
     ap.add_argument("--init", default=None, help="start from these fp32 weights (.npy), e.g. to fine-tune")
     ap.add_argument("--data-batches", type=int, default=0, help="train on a finite set of this many batches")
     ap.add_argument("--eval-every", type=int, default=0, help="evaluate every this many steps (and at the start)")
+    ap.add_argument("--lr-final", type=float, default=None,
+                    help="cosine decay of the learning rate from --lr to this value at --steps")
+    ap.add_argument("--schedule-start", type=int, default=None,
+                    help="step at which the warm-up and decay begin (default: the step the run starts at)")
+    ap.add_argument("--warmup", type=int, default=0, help="linear learning-rate warm-up steps")
     ap.add_argument("--eval-workloads", default=None,
                     help="comma-separated workloads to evaluate on (default: the training workload)")
     args = ap.parse_args()
@@ -291,6 +313,9 @@ def main():
         tr.init_from(np.load(args.init, allow_pickle=False))
         print(json.dumps({"init": args.init}), flush=True)
     evals = (args.eval_workloads or args.workload).split(",")
+    if args.lr_final is not None or args.warmup:
+        s0 = tr.step if args.schedule_start is None else args.schedule_start
+        tr.set_schedule(s0, args.steps, args.warmup, args.lr_final)
 
     def eval_all():
         if args.gamma > 0:
@@ -318,7 +343,8 @@ def main():
             torch.cuda.synchronize()
             el = time.time() - t0
             rec = {"step": tr.step, "loss": tr.loss.item(), "losses": tr.losses.tolist(),
-                   "ber": tr.nerr.item() / tr.n_bits, "s_per_step": el / max(tr.step - start, 1)}
+                   "ber": tr.nerr.item() / tr.n_bits, "s_per_step": el / max(tr.step - start, 1),
+                   "lr": tr.lr_at(tr.step)}
             if tr.gamma > 0:
                 rec["mse"] = tr.mses.tolist()
             print(json.dumps(rec), flush=True)

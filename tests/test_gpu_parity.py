@@ -148,7 +148,7 @@ def test_nrx_forward_reduced_width_multi_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(11)))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(14)))
 
 
 def test_bce_and_adam_match_oracle():
@@ -900,7 +900,7 @@ FP8_TOL = 0.25        # norm-wise LLR error bound of the E4M3 block convs (deriv
 FP8_AGREE = 0.99      # hard-decision agreement where |LLR_oracle| > 2
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_nrx_forward_fp8(variant):
     """FP8 model: calibrated per-layer activation scales, E4M3 block convs, LLRs against the
     FP64 oracle (norm-wise error and hard decisions), for each FP8 conv tile shape."""
@@ -993,6 +993,35 @@ def test_full_size_sampled_parity():
             log(f"  prec {prec}: worst relative error {worst:.2e} over {len(expected)} sampled subcarriers")
         finally:
             L.nrx_model_destroy(model)
+    # FP8 at the same size: activation scales calibrated on another batch of the workload (the GPU
+    # simulator's batch 1, an input only), the FP8 bar of the small cases on the sampled subcarriers
+    model = L.nrx_model_create(net.B, net.d, net.C, net.R, m_max, L.NRX_FP8)
+    try:
+        cfg = L.sim_config(n_taps=w["n_taps"], tap_decay_ns=w["decay_ns"], doppler_max_hz=w["doppler"], rho=w["rho"],
+                           snr_db_lo=w["snr"][0], snr_db_hi=w["snr"][1])
+        y_cal = torch.empty_like(y)
+        sws = ws_tensor(L.slot_sim_workspace_bytes(cfg, descs))
+        L.slot_sim(cfg, 0, 1, descs, m_max, y_cal, sws)
+        del sws
+        llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+        L.nrx_calibrate(model, wd, descs, y_cal, llr, ws)
+        L.nrx_autotune(model, wd, descs, y, llr, ws)
+        llr.fill_(float("nan"))
+        L.nrx_forward(model, wd, descs, y, llr, ws)
+        torch.cuda.synchronize()
+        got = split_llr(llr.cpu().numpy(), shapes, m_max)
+        worst, agree_n, agree_d = 0.0, 0, 0
+        for (slot, s0), e in expected.items():
+            g = got[slot][:, :, s0, :]
+            worst = max(worst, rel_err(g, e))
+            big = np.abs(e) > 2.0
+            agree_n += int(np.sum((g[big] > 0) == (e[big] > 0)))
+            agree_d += int(np.sum(big))
+        log(f"  fp8: worst relative error {worst:.3e}, decision agreement {agree_n / max(agree_d, 1):.5f} over {agree_d}")
+        assert worst <= FP8_TOL and agree_n >= FP8_AGREE * agree_d
+    finally:
+        L.nrx_model_destroy(model)
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
