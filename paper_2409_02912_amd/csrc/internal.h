@@ -179,7 +179,7 @@ struct PersistArgs {
   int32_t spin_limit;           // polls of a dependency flag before the wait gives up
 };
 constexpr int PERSIST_TILE = 512;       // rows per persistent tile (before rounding down to whole REs)
-constexpr int PERSIST_ITEM_TILES = 4;   // tiles per work item
+constexpr int PERSIST_ITEM_TILES = 4;   // most tiles per work item (large batches)
 
 // Item it of the persistent order -> (stage, slot, item of the slot).  IB(i) reads item_base[i], GS(i)
 // group_slot[i]; the same code runs in the kernel (scalar loads) and on the host.

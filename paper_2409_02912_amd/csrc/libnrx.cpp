@@ -102,6 +102,7 @@ struct Plan {
   // per tile (whole REs, at most PERSIST_TILE); slot groups (first slot of each, n_groups + 1 entries) of at
   // least PERSIST_GROUP tiles
   std::vector<int32_t> ptile_base, pitem_base, ptile_rows, pgroup;
+  int pitem_tiles = 1;           // consecutive tiles per persistent work item
   int64_t rows = 0, max_rows = 0, max_re = 0, max_pairs = 0, max_ute = 0, max_bits = 0;
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
@@ -163,6 +164,8 @@ std::vector<int64_t> plan_key(const nrx_slot_desc *d, int n, int sim_taps) {
   }
   return k;
 }
+
+int num_cu();   // compute units of the current device (256 when it cannot be queried)
 
 // Validates the descriptors of a batch.  max_ant bounds n_ant, m_max the bits per symbol.
 nrx_status validate_slots(const nrx_slot_desc *d, int n, int max_ant, int m_max) {
@@ -264,18 +267,26 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->tap_off.push_back(tp);
   {
     int32_t tb = 0, ib = 0, in_group = 0;
-    P->pgroup.push_back(0);
+    std::vector<int32_t> cnt(n);
     for (int i = 0; i < n; ++i) {
       const int U = P->geo[i].U;
       const int tr = (PERSIST_TILE / U) * U;
       const int64_t rows_i = (int64_t)P->geo[i].S * 14 * U;
-      const int32_t cnt = (int32_t)((rows_i + tr - 1) / tr);
+      cnt[i] = (int32_t)((rows_i + tr - 1) / tr);
+      P->ptile_rows.push_back(tr);
+      tb += cnt[i];
+    }
+    // several tiles per item amortise an item's start (claim, waits, pipeline fill) in large batches; a
+    // small batch (one slot in the real-time regime) keeps one tile per item so that it fills the device
+    P->pitem_tiles = std::max(1, std::min(PERSIST_ITEM_TILES, tb / (4 * num_cu())));
+    tb = 0;
+    P->pgroup.push_back(0);
+    for (int i = 0; i < n; ++i) {
       P->ptile_base.push_back(tb);
       P->pitem_base.push_back(ib);
-      P->ptile_rows.push_back(tr);
-      tb += cnt;
-      ib += (cnt + PERSIST_ITEM_TILES - 1) / PERSIST_ITEM_TILES;
-      in_group += cnt;
+      tb += cnt[i];
+      ib += (cnt[i] + P->pitem_tiles - 1) / P->pitem_tiles;
+      in_group += cnt[i];
       if (in_group >= PERSIST_GROUP && i + 1 < n) { P->pgroup.push_back(i + 1); in_group = 0; }
     }
     P->ptile_base.push_back(tb);
@@ -1145,7 +1156,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     pa.geo = D.geo;
     pa.tile_base = D.ptile_base;
     pa.item_base = D.pitem_base;
-    pa.item_tiles = PERSIST_ITEM_TILES;
+    pa.item_tiles = P->pitem_tiles;
     pa.tile_rows = D.ptile_rows;
     pa.group_slot = D.pgroup;
     pa.ctl = ctl;
@@ -1279,8 +1290,8 @@ extern "C" int64_t nrx_persist_schedule(nrx_model *m, const nrx_slot_desc *slots
     const int cnt = P->ptile_base[x.slot + 1] - P->ptile_base[x.slot];
     stage[it] = x.stage;
     slot[it] = x.slot;
-    tile[it] = x.item * PERSIST_ITEM_TILES;
-    n_tiles[it] = std::min(PERSIST_ITEM_TILES, cnt - tile[it]);
+    tile[it] = x.item * P->pitem_tiles;
+    n_tiles[it] = std::min(P->pitem_tiles, cnt - tile[it]);
   }
   return items;
 }

@@ -36,6 +36,11 @@ WORKLOADS = {
     # the small training workload with two CGNN iterations (multi-loss and depth control)
     "t2": dict(n_slots=32, n_prb=8, n_ant=4, n_ue=2, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
                snr=(0.0, 15.0), d=128, n_blocks=4, n_rounds=2),
+    # the C5 network and channel on small slots (8 PRB, 32 per batch): many more optimiser steps per GPU
+    # second than the 106-PRB batches (the network does not depend on the PRB count), to separate what the
+    # architecture can reach from what the C5 budget reaches
+    "c5s": dict(n_slots=32, n_prb=8, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
+                snr=(-2.0, 20.0), d=128, n_blocks=6, n_rounds=2),
     # headline workload: 273 PRB, 4 UEs, 8 antennas, 16-QAM, batch 32
     "m": dict(n_slots=32, n_prb=273, n_ant=8, n_ue=4, m=4, n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0,
               snr=(10.0, 10.0), d=128, n_blocks=6, n_rounds=2),
