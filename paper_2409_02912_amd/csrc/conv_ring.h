@@ -19,7 +19,10 @@
 // count suffices.  A halo requested at a chunk's first group is covered by the wait at the chunk's
 // last group (NG - 1 > NBUF - 2 groups later).
 // SCHED: 0 scheduling barriers between pipeline steps, 1 none (compiler interleaves),
-// 2 scheduling barriers and raised wave priority around the MFMA steps
+// 2 scheduling barriers and raised wave priority around the MFMA steps, 3 scheduling barriers and a wave
+// priority that falls as the wave gets through the group (3 at its first steps .. 0 at its last): of the
+// two waves sharing a SIMD the one behind is issued first, so they reach the barrier together instead of
+// one of them finishing its group alone at a lower MFMA rate
 #pragma once
 #include "conv_common.h"
 
@@ -220,6 +223,13 @@ __device__ __forceinline__ void conv_ring_body(const ConvArgs<T> &a, const Src &
 #pragma unroll
       for (int i = 0; i < 8 * G; ++i) {
         const int nb = i & 7;
+        if constexpr (SCHED == 3) {
+          constexpr int Q = (8 * G + 3) / 4;   // steps per priority level
+          if (i == 0) __builtin_amdgcn_s_setprio(3);
+          else if (i == Q) __builtin_amdgcn_s_setprio(2);
+          else if (i == 2 * Q) __builtin_amdgcn_s_setprio(1);
+          else if (i == 3 * Q) __builtin_amdgcn_s_setprio(0);
+        }
         const v16 b2 = i + 2 < 8 * G ? load_bf(i + 2) : b1;
         if (nb == 4 && i / 8 + 1 < G) load_a(i / 8 + 1, afn);
 #pragma unroll
@@ -232,7 +242,7 @@ __device__ __forceinline__ void conv_ring_body(const ConvArgs<T> &a, const Src &
         b1 = b2;
         if constexpr (SCHED != 1) __builtin_amdgcn_sched_barrier(0);
       }
-      if constexpr (SCHED == 2) __builtin_amdgcn_s_setprio(0);
+      if constexpr (SCHED == 2 || SCHED == 3) __builtin_amdgcn_s_setprio(0);
       if (gsa <= NBUF - 2) __builtin_amdgcn_s_waitcnt(WAIT_BA);
       else __builtin_amdgcn_s_waitcnt(WAIT_B);
       dma_barrier();

@@ -45,9 +45,11 @@ struct ConvVariant {
   int aligned = 0;   // 1: tiles of CONV_ALIGNED_TILE rows starting on subcarrier boundaries
 };
 constexpr int CONV_ALIGNED_TILE = 504;   // whole subcarriers for U = 1..4 (14 U rows each)
-#define NRX_CONV_VARIANTS 14
+#define NRX_CONV_VARIANTS 15
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
-#define NRX_CONV8_VARIANTS 4
+constexpr int CONV_DEFAULT_VARIANT = 14;   // a new model's variant for every conv class
+#define NRX_CONV8_VARIANTS 5
+constexpr int CONV8_DEFAULT_VARIANT = 0;   // ... and for the E4M3 block convs of FP8 models
 extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64
 
 // FP8 convolution (EPI_LN_RELU or EPI_RESID) on E4M3 operands a.src8_*, a.w8, a.wscale.

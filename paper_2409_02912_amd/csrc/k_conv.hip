@@ -404,6 +404,7 @@ const ConvVariant kConvVariants[NRX_CONV_VARIANTS] = {
     {8, 1, 3},            // as 7, workgroups started at staggered times
     {8, 1, 3},            // as 10, workgroups started at staggered times
     {8, 1, 3, 1},         // as 7 on 504-row tiles of whole subcarriers, three 3-tap weight slots
+    {8, 1, 3},            // as 7, wave priority falling through each group (SIMD partners kept level)
 };
 
 template <typename T>
@@ -467,6 +468,7 @@ void launch_conv(const ConvArgs<T> &a, int epi, int variant, int grid, hipStream
   NRX_RING_CASE(11, 4, 8, 3, 1, 2, 0, 1, 0)
   NRX_RING_CASE(12, 4, 8, 3, 1, 2, 2, 1, 0)
   NRX_RING_CASE(13, 4, 8, 3, 1, 3, 0, 0, 1)
+  NRX_RING_CASE(14, 4, 8, 3, 1, 2, 3, 0, 0)
 #undef NRX_RING_CASE
 }
 

@@ -32,7 +32,9 @@ constexpr int BSLOT = 8 * 16 * BROWB;
 
 __device__ __forceinline__ int bswz(int row) { return row & 7; }
 
-template <int EPI, int MB, int NW, int STAG>
+// STAG: staggered start; PRIO: wave priority falling through each tap pair (3 at its first n-blocks .. 0 at its
+// last), so that the two waves sharing a SIMD stay level
+template <int EPI, int MB, int NW, int STAG, int PRIO = 0>
 __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t> a) {
   constexpr int TILE = 16 * MB * NW;
   constexpr int HMAX = halo_rows_max(TILE);
@@ -158,8 +160,9 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
         stage_b(0, (kb + 1) & 1);
         stage_a(geo_of(tn), 0, (ka + 1) & 1);
       }
-      const unsigned char *la = &lds_a[ka & 1][0];
-      const unsigned char *lbr = &lds_b[kb & 1][0];
+      // local-address-space pointers: the fragment loads then stay where the scheduling barriers put them
+      const lds_u8 *la = (const lds_u8 *)&lds_a[ka & 1][0];
+      const lds_u8 *lbr = (const lds_u8 *)&lds_b[kb & 1][0];
       // taps 2p and 2p+1 (tap 9 does not exist: its weights are zero, its rows the zero row)
       const int t1 = 2 * p, t2 = 2 * p + 1;
       const int dj1 = t1 % 3 - 1, dj2 = t2 % 3 - 1;
@@ -188,9 +191,19 @@ __global__ __launch_bounds__(64 * NW, 1) void conv3x3_fp8_kernel(ConvArgs<bf16_t
       i32x8_t b0 = load_bf(0), b1 = load_bf(1);
 #pragma unroll
       for (int nb = 0; nb < 8; ++nb) {
+        if constexpr (PRIO) {
+          if (nb == 0) __builtin_amdgcn_s_setprio(3);
+          else if (nb == 2) __builtin_amdgcn_s_setprio(2);
+          else if (nb == 4) __builtin_amdgcn_s_setprio(1);
+          else if (nb == 6) __builtin_amdgcn_s_setprio(0);
+        }
         const i32x8_t b2 = nb < 6 ? load_bf(nb + 2) : b1;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb][nb] = mfma_fp8(af[mb], b0, acc[mb][nb]);
+        // pins the step's MFMAs here: each accumulator is updated once per pair, so without this the
+        // compiler sinks every MFMA of the pair past its end-of-pair wait and barrier, after all its loads
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) asm volatile("" : "+v"(acc[mb][nb]));
         b0 = b1;
         b1 = b2;
         __builtin_amdgcn_sched_barrier(0);
@@ -260,21 +273,23 @@ const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS] = {
     {6, 1, 2},   // 384-row tiles of 4 waves (6 m-blocks each)
     {4, 1, 2},   // 256-row tiles of 4 waves (4 m-blocks each)
     {8, 2, 2},   // as 0, workgroups started at staggered times
+    {8, 2, 2},   // as 0, wave priority falling through each tap pair
 };
 
 void launch_conv8(const ConvArgs<bf16_t> &a, int epi, int variant, int grid, hipStream_t st) {
-#define NRX_FP8_CASE(V, M, NWV, STG)                                                                   \
+#define NRX_FP8_CASE(V, M, NWV, STG, PR)                                                               \
   if (variant == V) {                                                                                  \
     if (epi == EPI_LN_RELU)                                                                            \
-      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_LN_RELU, M, NWV, STG>), dim3(grid), dim3(64 * NWV), 0, st, a); \
+      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_LN_RELU, M, NWV, STG, PR>), dim3(grid), dim3(64 * NWV), 0, st, a); \
     else                                                                                               \
-      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_RESID, M, NWV, STG>), dim3(grid), dim3(64 * NWV), 0, st, a);   \
+      hipLaunchKernelGGL((conv3x3_fp8_kernel<EPI_RESID, M, NWV, STG, PR>), dim3(grid), dim3(64 * NWV), 0, st, a);   \
     return;                                                                                            \
   }
-  NRX_FP8_CASE(0, 4, 8, 0)
-  NRX_FP8_CASE(1, 6, 4, 0)
-  NRX_FP8_CASE(2, 4, 4, 0)
-  NRX_FP8_CASE(3, 4, 8, 1)
+  NRX_FP8_CASE(0, 4, 8, 0, 0)
+  NRX_FP8_CASE(1, 6, 4, 0, 0)
+  NRX_FP8_CASE(2, 4, 4, 0, 0)
+  NRX_FP8_CASE(3, 4, 8, 1, 0)
+  NRX_FP8_CASE(4, 4, 8, 0, 1)
 #undef NRX_FP8_CASE
 }
 

@@ -27,8 +27,9 @@
 
 namespace {
 
-// the conv shape of the persistent kernel: 512-row tiles of 8 waves, 3-tap weight slots, 2 slots
-constexpr int PK_MB = 4, PK_NW = 8, PK_G = 3, PK_NBUF = 2;
+// the conv shape of the persistent kernel: 512-row tiles of 8 waves, 3-tap weight slots, 2 slots, wave priority
+// falling through each group (the per-layer variants 7 and 14)
+constexpr int PK_MB = 4, PK_NW = 8, PK_G = 3, PK_NBUF = 2, PK_SCHED = 3;
 using PkRing = RingShape<PK_MB, PK_NW, PK_G, PK_NBUF>;
 static_assert(PkRing::TILE == PERSIST_TILE, "tile");
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
@@ -110,11 +111,11 @@ __global__ __launch_bounds__(64 * PK_NW, 1) void persist_kernel(PersistArgs p) {
       const ConvArgs<bf16_t> &c = *(const ConvArgs<bf16_t> *)&S->c;
       const RunTiles run{slot, ta, tb - ta, rows, slot_rows};
       if (kind == PK_CONV_STORE)
-        conv_ring_body<bf16_t, EPI_STORE, PK_MB, PK_NW, PK_G, PK_NBUF, 0>(c, run, lds, lnp);
+        conv_ring_body<bf16_t, EPI_STORE, PK_MB, PK_NW, PK_G, PK_NBUF, PK_SCHED>(c, run, lds, lnp);
       else if (kind == PK_CONV_LN)
-        conv_ring_body<bf16_t, EPI_LN_RELU, PK_MB, PK_NW, PK_G, PK_NBUF, 0>(c, run, lds, lnp);
+        conv_ring_body<bf16_t, EPI_LN_RELU, PK_MB, PK_NW, PK_G, PK_NBUF, PK_SCHED>(c, run, lds, lnp);
       else
-        conv_ring_body<bf16_t, EPI_RESID, PK_MB, PK_NW, PK_G, PK_NBUF, 0>(c, run, lds, lnp);
+        conv_ring_body<bf16_t, EPI_RESID, PK_MB, PK_NW, PK_G, PK_NBUF, PK_SCHED>(c, run, lds, lnp);
     } else {
       const MlpArgs<bf16_t> &m = *(const MlpArgs<bf16_t> *)&S->m;
       const int r0 = ta * rows, r1 = tb * rows < slot_rows ? tb * rows : slot_rows;

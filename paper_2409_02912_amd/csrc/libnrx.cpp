@@ -504,6 +504,10 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   m->cfg = c;
   m->tsize = c.precision == NRX_FP32 ? 4 : 2;   // FP8 models keep BF16 for everything but the block convs
   m->fp8 = c.precision == NRX_FP8;
+  // convolution variants until nrx_conv_variant / nrx_autotune choose others: the fastest at the headline
+  // batch (BF16 ring kernel with SIMD-levelled wave priority; the first E4M3 kernel for FP8 block convs)
+  for (int cls = NRX_K_CONV_IN; cls <= NRX_K_CONV_B; ++cls)
+    m->conv_variant[cls] = m->fp8 && cls != NRX_K_CONV_IN ? CONV8_DEFAULT_VARIANT : CONV_DEFAULT_VARIANT;
   const int d = c.d, B = c.n_ant;
   m->cx = std::max(32, 4 * B);
   std::vector<int> mpb;
@@ -1209,8 +1213,9 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
   };
   if ((m->cfg.flags & 1) && !m->profile) {
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
-    uint64_t vs = 0;
-    for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (4 * c);
+    uint64_t vs = 0;   // the classes' variants, 8 bits each
+    static_assert(NRX_K_NCLASS * 8 <= 64 && NRX_CONV_VARIANTS <= 256, "variant key");
+    for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (8 * c);
     s = graph_forward(m, PR,
                       GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride, hest,
                                h_stride},

@@ -161,11 +161,12 @@ class Trainer:
 
     def lr_at(self, step):
         """Learning rate of an Adam step: self.lr, or with a schedule set by set_schedule a linear warm-up over
-        `warmup` steps from its start, then a cosine decay to lr_final at step `end`."""
+        `warmup` steps from its start, then a cosine decay to lr_final at step `end` (steps before the start
+        take the schedule's first rate)."""
         sch = getattr(self, "schedule", None)
         if not sch:
             return self.lr
-        k = step - sch["start"]
+        k = max(step - sch["start"], 0)
         if k < sch["warmup"]:
             return self.lr * (k + 1) / sch["warmup"]
         span = max(sch["end"] - sch["start"] - sch["warmup"], 1)

@@ -148,7 +148,7 @@ def test_nrx_forward_reduced_width_multi_ue(prec, tol):
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_nrx_forward_ragged_multi_ue(prec, tol):
     shapes = [s for s in RAGGED if s["n_ant"] <= 8]
-    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(14)))
+    _nrx_case(shapes, cgnn.NetConfig(8, 128, 3, 2, 6), prec, 3, tol, 6, variants=tuple(range(15)))
 
 
 def test_bce_and_adam_match_oracle():
@@ -900,7 +900,7 @@ FP8_TOL = 0.25        # norm-wise LLR error bound of the E4M3 block convs (deriv
 FP8_AGREE = 0.99      # hard-decision agreement where |LLR_oracle| > 2
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_nrx_forward_fp8(variant):
     """FP8 model: calibrated per-layer activation scales, E4M3 block convs, LLRs against the
     FP64 oracle (norm-wise error and hard decisions), for each FP8 conv tile shape."""

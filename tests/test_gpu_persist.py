@@ -1,7 +1,7 @@
 """GPU parity of the persistent forward (model flags bit 3): one launch for every layer of every slot.
 
 It runs the same convolution, message-passing and readout bodies as the per-layer launches (ring conv
-shape of variant 7 everywhere), so its LLRs equal those of the per-layer pass bit for bit; both are also
+shape and schedule of variant 14 everywhere), so its LLRs equal those of the per-layer pass bit for bit; both are also
 checked against the oracle.  Uneven batches (PRBs, UEs, antennas, modulations), a full-band batch that
 spans several slot groups, and hipGraph replays."""
 import numpy as np
@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_2409_02912_amd.libnrx")
 
 SIMCFG = dict(n_taps=12, decay_ns=487.42, doppler=0.0, rho=0.0, snr=(0.0, 30.0))
-RING_VARIANT = 7   # the per-layer kernels with the persistent kernel's conv shape
+RING_VARIANT = 14   # the per-layer kernels with the persistent kernel's conv shape and schedule
 
 
 def dev(a):
