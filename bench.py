@@ -122,7 +122,7 @@ def ragged_batch(steps, no_autotune, tune_cache=None, persistent=False):
         if not no_autotune and not persistent:
             L.nrx_autotune(model, dw, descs, y, llr, ws, cache_path=tune_cache)
         variants = ({L.KERNEL_CLASSES[c]: L.nrx_conv_variant(model, c)[0] for c in L.CONV_CLASSES}
-                    if not persistent else "persistent kernel (ring conv shape of variant 7)")
+                    if not persistent else "persistent kernel (ring conv shape and schedule of variant 14)")
         flags = torch.full((len(shapes),), -1, dtype=torch.int32, device="cuda")
         lat = torch.zeros(len(shapes), dtype=torch.float32, device="cuda")
         for _ in range(2):
