@@ -388,6 +388,8 @@ def main():
                     help="let the autotuner choose the BF16 / FP8 conv variants too (default: the library's defaults)")
     ap.add_argument("--bf16-only", action="store_true", help="skip the FP32 pass and batch-1 runs (profiling)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 pass")
+    ap.add_argument("--no-fp8-policies", action="store_true",
+                    help="skip the FP8 passes with only conv_a or only conv_b in E4M3")
     ap.add_argument("--no-persistent", action="store_true", help="skip the persistent-launch BF16 pass")
     ap.add_argument("--variant-sweep", action="store_true", help="time every conv variant per layer class")
     ap.add_argument("--ragged-steps", type=int, default=5,
@@ -453,8 +455,12 @@ def main():
     passes = [(L.NRX_BF16, "bf16")]
     if not args.no_persistent:
         passes.append((L.NRX_BF16, "bf16_persistent"))
+    # FP8 passes: both block convs in E4M3 (the library default), then each alone (the other in BF16)
+    fp8_masks = {"fp8": 3, "fp8_conv_a": 1, "fp8_conv_b": 2}
     if not args.no_fp8:
         passes.append((L.NRX_FP8, "fp8"))
+        if not args.no_fp8_policies:
+            passes += [(L.NRX_FP8, "fp8_conv_a"), (L.NRX_FP8, "fp8_conv_b")]
     if not args.bf16_only:
         passes.append((L.NRX_FP32, "fp32"))
     for prec, name in passes:
@@ -462,9 +468,11 @@ def main():
         model = L.nrx_model_create(*net_args, prec, flags=1 | (8 if name == "bf16_persistent" else 0))
         ws = torch.empty(L.nrx_workspace_bytes(model, descs), dtype=torch.uint8, device="cuda")
         llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
-        if name == "fp8":
+        if name in fp8_masks:
             L.nrx_calibrate(model, dw, descs, y_cal, llr, ws)
-            results.setdefault("fp8_scales", L.nrx_act_scales(model).tolist())
+            L.nrx_fp8_layers(model, fp8_masks[name])
+            if name == "fp8":
+                results.setdefault("fp8_scales", L.nrx_act_scales(model).tolist())
         steps = args.fp32_steps if name == "fp32" else args.steps
         warm = 1 if name == "fp32" else args.warmup
         if args.variant_sweep:
@@ -519,7 +527,7 @@ def main():
         llrs[name] = llr
         flag_words[name] = torch.zeros(n_slots, dtype=torch.int32, device="cuda")
         L.nrx_slot_flags(model, descs, ws, flag_words[name])
-        if args.bf16_only:
+        if args.bf16_only or name in ("fp8_conv_a", "fp8_conv_b"):
             results[name]["batch1_ms"] = None
             L.nrx_model_destroy(model)
             continue
@@ -569,8 +577,9 @@ def main():
         b32 = ber["fp32"]
         tol = max(0.05 * b32, 3 * math.sqrt(max(b32 * (1 - b32), 1e-30) / n_bits))
         ber["matched"] = abs(ber["bf16"] - b32) <= tol
-        if "fp8" in ber:
-            ber["fp8_matched"] = abs(ber["fp8"] - b32) <= tol
+        for k8 in ("fp8", "fp8_conv_a", "fp8_conv_b"):
+            if k8 in ber:
+                ber[k8 + "_matched"] = abs(ber[k8] - b32) <= tol
         ber["tolerance"] = tol
         rel_llr = (torch.linalg.vector_norm(llrs["bf16"] - llrs["fp32"]) /
                    torch.linalg.vector_norm(llrs["fp32"])).item()
@@ -638,6 +647,19 @@ def main():
                                           "peak": 8000.0, "unit": "GB/s",
                                           "frac": rows * 768 / (cb8 * 1e-3) / 8e12,
                                           "mfma_frac": conv_flops / (cb8 * 1e-3) / PEAKS["fp8"]}}
+    pol = {k: {"fp8_layers": {1: "conv_a", 2: "conv_b", 3: "conv_a + conv_b"}[fp8_masks[k]],
+               "slots_per_s": n_slots / (results[k]["ms_per_step"] * 1e-3), "ms_per_step": results[k]["ms_per_step"],
+               "speedup_vs_bf16": ms / results[k]["ms_per_step"], "ber": ber.get(k),
+               "ber_matched": ber.get(k + "_matched")}
+           for k in fp8_masks if k in results}
+    if pol:
+        out["fp8_policies"] = pol
+        ok = [k for k in pol if pol[k]["ber_matched"]]
+        if "fp8" in out and ok:   # the fastest E4M3 policy whose BER matches the FP32 pass
+            best = max(ok, key=lambda k: pol[k]["slots_per_s"])
+            out["fp8"]["matched_ber_policy"] = {"fp8_layers": pol[best]["fp8_layers"],
+                                                "slots_per_s": pol[best]["slots_per_s"],
+                                                "speedup_vs_bf16": pol[best]["speedup_vs_bf16"]}
     if "bf16_persistent" in results:
         msp = results["bf16_persistent"]["ms_per_step"]
         out["bf16_persistent"] = {"slots_per_s": n_slots / (msp * 1e-3), "ms_per_step": msp,

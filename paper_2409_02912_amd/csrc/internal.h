@@ -49,6 +49,7 @@ constexpr int CONV_ALIGNED_TILE = 504;   // whole subcarriers for U = 1..4 (14 U
 extern const ConvVariant kConvVariants[NRX_CONV_VARIANTS];
 constexpr int CONV_DEFAULT_VARIANT = 14;   // a new model's variant for every conv class
 #define NRX_CONV8_VARIANTS 5
+constexpr int NRX_N_MODS = 4;   // modulations by bits per symbol: 2, 4, 6, 8 (index bits / 2 - 1)
 constexpr int CONV8_DEFAULT_VARIANT = 0;   // ... and for the E4M3 block convs of FP8 models
 extern const ConvVariant kConv8Variants[NRX_CONV8_VARIANTS];   // mb = tile rows / 64
 

@@ -103,12 +103,17 @@ struct Plan {
   // least PERSIST_GROUP tiles
   std::vector<int32_t> ptile_base, pitem_base, ptile_rows, pgroup;
   int pitem_tiles = 1;           // consecutive tiles per persistent work item
+  // batches that mix modulations: per modulation (index m / 2 - 1) the conv and readout tiles of the slots
+  // with a UE of that modulation, which the Var-IO StateInit and readout launches of that modulation walk
+  bool mod_lists = false;
+  std::vector<Tile> ctm[NRX_N_MODS][N_TILE_SIZES], rtm[NRX_N_MODS];
   int64_t rows = 0, max_rows = 0, max_re = 0, max_pairs = 0, max_ute = 0, max_bits = 0;
   int64_t dmrs_total = 0, pairs_total = 0, n_data_bits = 0;
   int max_ubl = 0;
   // device table blob
   size_t off_geo = 0, off_ct[N_TILE_SIZES] = {}, off_mt = 0, off_rt = 0, off_pair = 0, off_tap = 0;
   size_t off_ptb = 0, off_pib = 0, off_ptr = 0, off_pg = 0, meta_bytes = 0;
+  size_t off_ctm[NRX_N_MODS][N_TILE_SIZES] = {}, off_rtm[NRX_N_MODS] = {};
   std::vector<char> blob;        // host image of the device tables
   void *pinned = nullptr;        // pinned copy, allocated on first upload
   void *packed_geo = nullptr;    // lmmse_demap: pinned geometry copy with h offsets into its workspace
@@ -296,6 +301,24 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->rows = row;
   P->dmrs_total = dm;
   P->pairs_total = pr;
+  {
+    std::vector<int> slot_mods(n, 0);   // bit mi: the slot has a UE of modulation 2 (mi + 1)
+    int all = 0;
+    for (int i = 0; i < n; ++i) {
+      for (int u = 0; u < P->geo[i].U; ++u) slot_mods[i] |= 1 << (P->geo[i].m[u] / 2 - 1);
+      all |= slot_mods[i];
+    }
+    P->mod_lists = __builtin_popcount(all) > 1;
+    if (P->mod_lists)
+      for (int mi = 0; mi < NRX_N_MODS; ++mi) {
+        if (!(all >> mi & 1)) continue;
+        for (int k = 0; k < N_TILE_SIZES; ++k)
+          for (const Tile &t : P->ct[k])
+            if (slot_mods[t.slot] >> mi & 1) P->ctm[mi][k].push_back(t);
+        for (const Tile &t : P->rt)
+          if (slot_mods[t.slot] >> mi & 1) P->rtm[mi].push_back(t);
+      }
+  }
   size_t o = 0;
   P->off_geo = o; o = align256(o + sizeof(SlotGeo) * P->geo.size());
   for (int k = 0; k < N_TILE_SIZES; ++k) { P->off_ct[k] = o; o = align256(o + sizeof(Tile) * P->ct[k].size()); }
@@ -307,6 +330,10 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   P->off_pib = o; o = align256(o + sizeof(int32_t) * P->pitem_base.size());
   P->off_ptr = o; o = align256(o + sizeof(int32_t) * P->ptile_rows.size());
   P->off_pg = o; o = align256(o + sizeof(int32_t) * P->pgroup.size());
+  for (int mi = 0; mi < NRX_N_MODS; ++mi) {
+    for (int k = 0; k < N_TILE_SIZES; ++k) { P->off_ctm[mi][k] = o; o = align256(o + sizeof(Tile) * P->ctm[mi][k].size()); }
+    P->off_rtm[mi] = o; o = align256(o + sizeof(Tile) * P->rtm[mi].size());
+  }
   P->meta_bytes = o;
   P->blob.assign(o, 0);
   char *b = P->blob.data();
@@ -320,6 +347,11 @@ nrx_status get_plan(const nrx_slot_desc *d, int n, int max_ant, int m_max, int s
   memcpy(b + P->off_pib, P->pitem_base.data(), sizeof(int32_t) * P->pitem_base.size());
   memcpy(b + P->off_ptr, P->ptile_rows.data(), sizeof(int32_t) * P->ptile_rows.size());
   memcpy(b + P->off_pg, P->pgroup.data(), sizeof(int32_t) * P->pgroup.size());
+  for (int mi = 0; mi < NRX_N_MODS; ++mi) {
+    for (int k = 0; k < N_TILE_SIZES; ++k)
+      memcpy(b + P->off_ctm[mi][k], P->ctm[mi][k].data(), sizeof(Tile) * P->ctm[mi][k].size());
+    memcpy(b + P->off_rtm[mi], P->rtm[mi].data(), sizeof(Tile) * P->rtm[mi].size());
+  }
   *out = P;
   g_plans.plans[std::move(key)] = PlanCache::Entry{std::move(P), ++g_plans.tick};
   return NRX_OK;
@@ -342,6 +374,7 @@ nrx_status plan_upload(Plan *P, char *dst, hipStream_t st) {
 struct Dev {
   const SlotGeo *geo;
   const Tile *ct[N_TILE_SIZES], *mt, *rt;
+  const Tile *ctm[NRX_N_MODS][N_TILE_SIZES], *rtm[NRX_N_MODS];
   const int64_t *pair_off, *tap_off;
   const int32_t *ptile_base, *pitem_base, *ptile_rows, *pgroup;
 };
@@ -358,6 +391,10 @@ Dev dev_tables(const Plan *P, char *ws) {
   d.pitem_base = (const int32_t *)(ws + P->off_pib);
   d.ptile_rows = (const int32_t *)(ws + P->off_ptr);
   d.pgroup = (const int32_t *)(ws + P->off_pg);
+  for (int mi = 0; mi < NRX_N_MODS; ++mi) {
+    for (int k = 0; k < N_TILE_SIZES; ++k) d.ctm[mi][k] = (const Tile *)(ws + P->off_ctm[mi][k]);
+    d.rtm[mi] = (const Tile *)(ws + P->off_rtm[mi]);
+  }
   return d;
 }
 
@@ -431,6 +468,7 @@ struct nrx_model {
   //   [2C + r]: aggregated messages of round r
   bool fp8 = false;
   bool calibrating = false;             // forward records max |activation| instead of using FP8
+  int fp8_layers = 3;                   // FP8 models: bit 0 conv_a / conv_a_mp in E4M3, bit 1 conv_b
   bool calibrated = false;
   std::vector<float> act_scale;
   uint64_t scale_epoch = 0;
@@ -935,6 +973,9 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
   }
   // FP8 models: E4M3 block-conv operands (or, while calibrating, BF16 convs that record max |activation|)
   const bool f8 = m->fp8 && !m->calibrating && !save;
+  // which block convs run in E4M3 (the others in BF16); an E4M3 conv reads E4M3 copies of its inputs, so
+  // their producers write those copies (and BF16 where a BF16 conv reads them)
+  const bool f8a = f8 && (m->fp8_layers & 1), f8b = f8 && (m->fp8_layers & 2);
   uint8_t *h8 = m->fp8 ? (uint8_t *)(ws + L.h8) : nullptr;
   uint8_t *a8 = m->fp8 ? (uint8_t *)(ws + L.a8) : nullptr;
   uint8_t *agg8 = m->fp8 ? (uint8_t *)(ws + L.agg8) : nullptr;
@@ -974,12 +1015,17 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     }
     int v = m->conv_variant[cls];
     if (fp8op) v = std::min(v, NRX_CONV8_VARIANTS - 1);
+    else if (m->fp8 && cls != NRX_K_CONV_IN) v = CONV_DEFAULT_VARIANT;   // a block conv kept in BF16
     else if (kConvVariants[v].pref == 2 && ((ca.c0 + ca.c1) / (64 / (int)sizeof(T))) % 2)
       v = 1;   // the LDS-operand kernels walk the input channels two chunks at a time
     const ConvVariant &cv = fp8op ? kConv8Variants[v] : kConvVariants[v];
     const int ti = variant_tiles(cv);
     ca.tiles = D.ct[ti];
     ca.n_tiles = (int)P->ct[ti].size();
+    if (ca.only_m && P->mod_lists) {   // Var-IO StateInit: only the slots with a UE of this modulation
+      ca.tiles = D.ctm[ca.only_m / 2 - 1][ti];
+      ca.n_tiles = (int)P->ctm[ca.only_m / 2 - 1][ti].size();
+    }
     int grid = std::min<int>(ca.n_tiles, num_cu() * cv.occ);
     grid = (grid + 7) / 8 * 8;    // the kernel's XCD-aware order needs a multiple of 8
     ProfMark pm(m, cls, st);
@@ -1006,7 +1052,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     a0.bias = vec(ci.c.b, ci.c.bpad);
     a0.pe = fields + ci.c.field;
     a0.only_m = ci.m;
-    if (f8) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
+    if (f8a) { a0.out8 = h8; a0.out8_inv = inv_scale(0); }
     if (amax) a0.amax = amax + 0;
     conv(a0, EPI_STORE, NRX_K_CONV_IN, false);
   }
@@ -1038,6 +1084,10 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ra.n_tiles = (int)P->rt.size();
       // the pass completes at the last launch of the last readout
       const bool fin = last && i + 1 == ros_run.size();
+      if (R.m && P->mod_lists && !fin && !persist) {   // Var-IO: only the slots with a UE of this modulation
+        ra.tiles = D.rtm[R.m / 2 - 1];
+        ra.n_tiles = (int)P->rtm[R.m / 2 - 1].size();
+      }
       ra.slot_done = fin ? (unsigned int *)(ws + L.done) : nullptr;
       ra.stamps = fin ? (unsigned long long *)(ws + L.stamps) : nullptr;
       ra.slot_flags = slot_flags;
@@ -1052,6 +1102,8 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     }
     if (hest) {   // ReadoutChEst on the same state (double readout)
       MlpArgs<T> ca = ra;
+      ca.tiles = D.rt;
+      ca.n_tiles = (int)P->rt.size();
       ca.w1 = wprep + m->ro_ch.p1;
       ca.b1 = vec(m->ro_ch.b1, m->ro_ch.b1pad);
       ca.b2 = w + m->ro_ch.b2;
@@ -1084,7 +1136,7 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
       ma.b1 = vec(m->mp[r].b1, m->mp[r].b1pad);
       ma.b2 = vec(m->mp[r].b2, m->mp[r].b2pad);
       ma.out = agg;
-      if (f8) { ma.out = nullptr; ma.out8 = agg8; ma.out8_inv = inv_scale(2 * C + r); }
+      if (f8a) { ma.out = nullptr; ma.out8 = agg8; ma.out8_inv = inv_scale(2 * C + r); }
       if (amax) ma.amax = amax + 2 * C + r;
       ma.save_m1 = save ? buf(L.m1[r]) : nullptr;
       ma.geo = D.geo;
@@ -1108,17 +1160,19 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     ca.out = abuf;
     ca.save_z = save ? buf(L.z[i]) : nullptr;
     ca.save_stats = save ? (float *)(ws + L.stats[i]) : nullptr;
-    if (f8) {
+    if (f8a) {
       ca.src8_0 = h8;
       ca.src8_1 = agg ? agg8 : nullptr;
       ca.w8 = (const uint8_t *)(ws + L.w8) + B.a.w8;
       ca.wscale = (const float *)(ws + L.wsc) + B.a.ws8;
+    }
+    if (f8b) {   // conv_b reads the E4M3 copy of a only
       ca.out = nullptr;
       ca.out8 = a8;
       ca.out8_inv = inv_scale(C + i);
     }
     if (amax) ca.amax = amax + C + i;
-    conv(ca, save ? EPI_LN_RELU_SAVE : EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, f8);
+    conv(ca, save ? EPI_LN_RELU_SAVE : EPI_LN_RELU, agg ? NRX_K_CONV_A_MP : NRX_K_CONV_A, f8a);
     ConvArgs<T> cb = a;
     cb.src0 = abuf; cb.c0 = NRX_D; cb.src1 = nullptr; cb.c1 = 0;
     cb.w = wprep + B.b.prep;
@@ -1126,14 +1180,14 @@ nrx_status forward_impl(nrx_model *m, const Plan *P, const FwdLayout &L, const f
     cb.pe = nullptr;
     cb.resid = h_in;
     cb.out = h_out;
-    if (f8) {
+    if (f8b) {
       cb.src8_0 = a8;
       cb.w8 = (const uint8_t *)(ws + L.w8) + B.b.w8;
       cb.wscale = (const float *)(ws + L.wsc) + B.b.ws8;
-      if (i + 1 < C) { cb.out8 = h8; cb.out8_inv = inv_scale(i + 1); }
     }
+    if (f8a && i + 1 < C) { cb.out8 = h8; cb.out8_inv = inv_scale(i + 1); }
     if (amax && i + 1 < C) cb.amax = amax + i + 1;
-    conv(cb, EPI_RESID, NRX_K_CONV_B, f8);
+    conv(cb, EPI_RESID, NRX_K_CONV_B, f8b);
     if (llr_stride > 0 && i + 1 < c_run) {
       for (int k = 0; k < n_run - 1; ++k)
         if (ends[k] == i + 1) readout(i + 1, k, false);
@@ -1214,8 +1268,9 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
   if ((m->cfg.flags & 1) && !m->profile) {
     // replay the whole launch sequence from a graph captured once per (batch, buffers)
     uint64_t vs = 0;   // the classes' variants, 8 bits each
-    static_assert(NRX_K_NCLASS * 8 <= 64 && NRX_CONV_VARIANTS <= 256, "variant key");
+    static_assert(NRX_K_NCLASS * 8 <= 56 && NRX_CONV_VARIANTS <= 256, "variant key");
     for (int c = 0; c < NRX_K_NCLASS; ++c) vs |= (uint64_t)m->conv_variant[c] << (8 * c);
+    vs |= (uint64_t)m->fp8_layers << 56;
     s = graph_forward(m, PR,
                       GraphKey{P, w, y, h_ls, llr, ws, save_acts != 0, vs, m->scale_epoch, iters, llr_stride, hest,
                                h_stride},
@@ -1443,6 +1498,15 @@ int n_conv_variants(const nrx_model *m, int cls) {
   return m->fp8 && cls != NRX_K_CONV_IN ? NRX_CONV8_VARIANTS : NRX_CONV_VARIANTS;
 }
 }  // namespace
+
+extern "C" nrx_status nrx_fp8_layers(nrx_model *m, int32_t mask, int32_t *current) {
+  if (!m) return fail(NRX_ERR_INVALID, "null model");
+  if (!m->fp8) return fail(NRX_ERR_INVALID, "not an FP8 model");
+  if (mask > 3) return fail(NRX_ERR_INVALID, "fp8 layer mask %d (bits 0, 1)", mask);
+  if (mask >= 0) m->fp8_layers = mask;
+  if (current) *current = m->fp8_layers;
+  return NRX_OK;
+}
 
 extern "C" nrx_status nrx_conv_variant(nrx_model *m, int32_t cls, int32_t variant, int32_t *current,
                                        int32_t *n_variants) {

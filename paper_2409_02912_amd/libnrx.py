@@ -89,6 +89,7 @@ _SIGS = {
     "nrx_profile_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "nrx_autotune": (_i32, [_vp, _vp, _DESC, _i32, _vp, _vp, _vp, _sz, ctypes.c_char_p, _vp]),
     "nrx_conv_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "nrx_fp8_layers": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
     "nrx_slot_latency": (_i32, [_vp, _DESC, _i32, _vp, _vp, _vp]),
     "nrx_act_scale_count": (_i32, [_vp]),
     "nrx_act_scales": (_i32, [_vp, _vp, _vp, _i32]),
@@ -387,6 +388,13 @@ def nrx_autotune(model, w, slots, y, llr, ws, cache_path=None, stream=None):
     arr, n = _descs(slots)
     _check(_lib.nrx_autotune(model, _ptr(w), arr, n, _ptr(y), _ptr(llr), _ptr(ws), ws.numel() * ws.element_size(),
                              cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def nrx_fp8_layers(model, mask=-1):
+    """FP8 model: block convs in E4M3 (bit 0 conv_a, bit 1 conv_b); sets mask when >= 0, returns the current one."""
+    cur = _i32()
+    _check(_lib.nrx_fp8_layers(model, mask, ctypes.byref(cur)))
+    return cur.value
 
 
 def nrx_conv_variant(model, cls, variant=-1):

@@ -290,3 +290,19 @@ def test_noalloc_lmmse_host_checks():
     with pytest.raises(L.NrxError) as e:
         L.lmmse_demap_noalloc(one, 4, None, t, stream=st)
     assert e.value.status == L.NRX_ERR_INVALID
+
+
+def test_fp8_layer_mask_host_checks():
+    m8 = L.nrx_model_create(8, 128, 2, 1, 4, L.NRX_FP8)
+    m16 = L.nrx_model_create(8, 128, 2, 1, 4, L.NRX_BF16)
+    try:
+        assert L.nrx_fp8_layers(m8) == 3                  # both block convs in E4M3 by default
+        assert L.nrx_fp8_layers(m8, 1) == 1 and L.nrx_fp8_layers(m8) == 1
+        assert L.nrx_fp8_layers(m8, 0) == 0
+        with pytest.raises(L.NrxError):
+            L.nrx_fp8_layers(m8, 4)
+        with pytest.raises(L.NrxError):
+            L.nrx_fp8_layers(m16, 1)                      # not an FP8 model
+    finally:
+        L.nrx_model_destroy(m8)
+        L.nrx_model_destroy(m16)

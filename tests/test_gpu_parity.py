@@ -314,35 +314,47 @@ def test_nrx_backward_fp32_matches_oracle(variant):
 
 VARIO_SHAPES = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[4, 2], slot_number=1),
                 dict(n_prb=3, n_ant=4, n_ue=3, bits=[6, 4, 2], slot_number=2)]
+# slots of one modulation each beside a mixed one: each modulation's StateInit and readout launches walk only
+# the tiles of the slots with a UE of that modulation
+VARIO_SLOT_SHAPES = [dict(n_prb=4, n_ant=4, n_ue=2, bits=[2, 2], slot_number=3),
+                     dict(n_prb=3, n_ant=4, n_ue=3, bits=[4, 4, 4], slot_number=4),
+                     dict(n_prb=5, n_ant=4, n_ue=1, bits=[8], slot_number=5),
+                     dict(n_prb=2, n_ant=4, n_ue=2, bits=[6, 2], slot_number=6)]
 
 
+@pytest.mark.parametrize("shapes", ["mixed", "per_slot"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
-def test_nrx_forward_var_io_matches_oracle(prec, tol):
+def test_nrx_forward_var_io_matches_oracle(prec, tol, shapes):
     """Var-IO (Sec. III, Fig. 2): one StateInit and one ReadoutLLRs per modulation (2, 4, 6, 8 bits), each UE's
-    state initialised and read out by its own; the batch mixes QPSK, 16-QAM and 64-QAM UEs, the 256-QAM layers are
-    unused."""
+    state initialised and read out by its own.  "mixed": every slot mixes QPSK, 16-QAM and 64-QAM UEs, the 256-QAM
+    layers are unused; "per_slot": most slots use one modulation, so each modulation's launches cover a subset of
+    the slots (also with the pass replayed as a hipGraph)."""
+    shp = VARIO_SHAPES if shapes == "mixed" else VARIO_SLOT_SHAPES
     net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
-    log(f"Var-IO forward: prec={prec}")
-    ref_slots = oracle_batch(VARIO_SHAPES, sim_cfg_oracle(SIMCFG), 61, 0, 8)
+    log(f"Var-IO forward: prec={prec}, {shapes} modulations")
+    ref_slots = oracle_batch(shp, sim_cfg_oracle(SIMCFG), 61, 0, 8)
     w = synth.he_weights(cgnn.layout(net), 61, perturb=True)
-    model = L.nrx_model_create(net.B, net.d, net.C, net.R, 8, prec, flags=4)
-    try:
-        assert [(n, tuple(s)) for n, _, s in L.weight_layout(model)] == [(n, tuple(s)) for n, s in cgnn.layout(net)]
-        exp = oracle_nrx(w, net, ref_slots)
-        descs, sz = L.make_slots(VARIO_SHAPES, 8)
-        y = _upload_batch(VARIO_SHAPES, ref_slots)
-        llr = torch.full((sz["llr"],), float("nan"), dtype=torch.float32, device="cuda")
-        ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
-        L.nrx_forward(model, dev(w), descs, y, llr, ws)
-        torch.cuda.synchronize()
-        got = llr.cpu().numpy().astype(np.float64)
-        assert np.all(np.isfinite(got)), "LLR entries left unwritten"
-        e = rel_err(np.concatenate([x.reshape(-1) for x in split_llr(got, VARIO_SHAPES, 8)]),
-                    np.concatenate([x.reshape(-1) for x in exp]))
-        log(f"  LLR relative error {e:.2e}")
-        assert e <= tol
-    finally:
-        L.nrx_model_destroy(model)
+    exp = oracle_nrx(w, net, ref_slots)
+    descs, sz = L.make_slots(shp, 8)
+    y = _upload_batch(shp, ref_slots)
+    for flags in ((4,) if shapes == "mixed" else (4, 4 | 1)):
+        model = L.nrx_model_create(net.B, net.d, net.C, net.R, 8, prec, flags=flags)
+        try:
+            assert [(n, tuple(s)) for n, _, s in L.weight_layout(model)] == [(n, tuple(s)) for n, s in cgnn.layout(net)]
+            llr = torch.full((sz["llr"],), float("nan"), dtype=torch.float32, device="cuda")
+            ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+            for rep in range(2 if flags & 1 else 1):
+                llr.fill_(float("nan"))
+                L.nrx_forward(model, dev(w), descs, y, llr, ws)
+                torch.cuda.synchronize()
+                got = llr.cpu().numpy().astype(np.float64)
+                assert np.all(np.isfinite(got)), "LLR entries left unwritten"
+                e = rel_err(np.concatenate([x.reshape(-1) for x in split_llr(got, shp, 8)]),
+                            np.concatenate([x.reshape(-1) for x in exp]))
+                log(f"  flags {flags} pass {rep}: LLR relative error {e:.2e}")
+                assert e <= tol
+        finally:
+            L.nrx_model_destroy(model)
 
 
 def test_nrx_backward_var_io_fp32_matches_oracle():
@@ -765,6 +777,21 @@ def test_trained_nrx_beats_lmmse():
     assert b1 < b2 - 5 * sd
 
 
+def test_trained_c5_network_against_lmmse():
+    """The committed C5 network (6 blocks, 2 message-passing rounds, 4 UEs x 8 antennas, Sec. II-B training) against
+    LS + LMMSE with genie N0 at 10 dB on held-out C5 slots.  It does not beat the classical receiver yet (its BER
+    is about 1.17 times LS + LMMSE after 400k training steps, still falling with training): the bar holds it to
+    within 25 % of it, so that a regression of the weights or of the forward pass shows."""
+    import os
+    from paper_2409_02912_amd.train import evaluate
+    w = np.load(os.path.join(os.path.dirname(L.LIB_PATH), "weights", "nrx_c5.npy"), allow_pickle=False)
+    log("trained C5 NRX vs LS+LMMSE: 10 dB, held-out seed")
+    r = evaluate(w, synth.WORKLOADS["c5"], seed=99, batches=2, snr_db=10.0)
+    b1, b2, n = r["ber_nrx"], r["ber_lmmse"], r["n_bits"]
+    log(f"  BER nrx {b1:.4f}  lmmse {b2:.4f}  ratio {b1 / b2:.3f}  bits {n}")
+    assert b1 < 1.25 * b2
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
 def test_graph_replay_matches_eager(prec, tol):
     """Model flag bit 0: the forward pass captured once and replayed on new inputs in the same
@@ -925,21 +952,29 @@ def test_nrx_forward_fp8(variant):
         assert scales.size == 2 * net.C + net.R and np.all(scales > 0)
         for c in (L.NRX_K_CONV_A, L.NRX_K_CONV_A_MP, L.NRX_K_CONV_B):
             L.nrx_conv_variant(model, c, variant)
-        llr.zero_()
-        L.nrx_forward(model, wd, descs, y, llr, ws)
-        torch.cuda.synchronize()
-        got = split_llr(llr.cpu().numpy(), shapes, m_max)
-        worst, agree_n, agree_d = 0.0, 0, 0
-        for i in range(len(shapes)):
-            for u in range(shapes[i]["n_ue"]):
-                worst = max(worst, rel_err(got[i][u], exp[i][u]))
-                big = np.abs(exp[i][u]) > 2.0
-                agree_n += int(np.sum((got[i][u][big] > 0) == (exp[i][u][big] > 0)))
-                agree_d += int(np.sum(big))
-        log(f"fp8 variant {variant}: worst relative error {worst:.3e}, decision agreement "
-            f"{agree_n / max(agree_d, 1):.5f} over {agree_d}")
-        assert worst <= FP8_TOL
-        assert agree_n >= FP8_AGREE * agree_d
+        # E4M3 for both block convs, then (variant 0) for only one of them, the other in BF16
+        errs = {}
+        for mask in ((3, 1, 2) if variant == 0 else (3,)):
+            L.nrx_fp8_layers(model, mask)
+            llr.zero_()
+            L.nrx_forward(model, wd, descs, y, llr, ws)
+            torch.cuda.synchronize()
+            got = split_llr(llr.cpu().numpy(), shapes, m_max)
+            worst, agree_n, agree_d = 0.0, 0, 0
+            for i in range(len(shapes)):
+                for u in range(shapes[i]["n_ue"]):
+                    worst = max(worst, rel_err(got[i][u], exp[i][u]))
+                    big = np.abs(exp[i][u]) > 2.0
+                    agree_n += int(np.sum((got[i][u][big] > 0) == (exp[i][u][big] > 0)))
+                    agree_d += int(np.sum(big))
+            log(f"fp8 variant {variant}, E4M3 layers {mask}: worst relative error {worst:.3e}, decision agreement "
+                f"{agree_n / max(agree_d, 1):.5f} over {agree_d}")
+            assert worst <= FP8_TOL
+            assert agree_n >= FP8_AGREE * agree_d
+            errs[mask] = worst
+        if len(errs) == 3:
+            # half the quantised convolutions: a smaller error than with both, for at least one of the halves
+            assert min(errs[1], errs[2]) < errs[3]
     finally:
         L.nrx_model_destroy(model)
 
