@@ -152,6 +152,81 @@ __global__ void features_kernel(const SlotGeo *geo, const float2 *y, const float
   }
 }
 
+// The input features of a block of consecutive rows of one slot in two phases.  Phase 1: one thread per
+// (row, antenna) interpolates the LS estimate and reads the received sample, consecutive lanes taking
+// consecutive antennas, so that the loads of a row's pairs and samples are contiguous; the values go to
+// LDS (and the estimate to h_out).  Phase 2: one thread per (row, 8 channels) assembles its channels from
+// LDS and writes them as one 16- or 32-byte vector, a wave a contiguous block of X.
+constexpr int FEAT_MAX_B = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void features_lds_kernel(const SlotGeo *geo, const float2 *y, const float2 *pairs,
+                                                           const int64_t *pair_off, int model_B, int cx, T *X,
+                                                           float2 *h_out, const unsigned int *slot_mask,
+                                                           unsigned int *slot_flags) {
+  __shared__ float2 ys[256 / 4][FEAT_MAX_B], hs[256 / 4][FEAT_MAX_B];
+  const int slot = blockIdx.y;
+  if (slot_mask && !slot_mask[slot]) return;
+  const SlotGeo g = geo[slot];
+  const int S = g.S, U = g.U, B = g.B;
+  const int ngrp = cx / 8, rpb = 256 / ngrp;   // rows per block
+  const int rows = S * 14 * U;
+  const int r0 = blockIdx.x * rpb;
+  if (r0 >= rows) return;
+  const int np = S / 4;
+  const float2 *P = pairs + pair_off[slot];
+  bool bad = false;
+  for (int it = threadIdx.x; it < rpb * B; it += 256) {
+    const int rl = it / B, b = it - rl * B, r = r0 + rl;
+    if (r >= rows) break;   // it grows with rl
+    const int s = r / (14 * U);
+    const int rem = r - s * 14 * U;
+    const int t = rem / U, u = rem - t * U;
+    const int delta = u >> 1;
+    const int p0 = 1 + delta, plast = 4 * (np - 1) + 1 + delta;
+    int n0;
+    float w;
+    if (s <= p0) { n0 = 0; w = 0.f; }
+    else if (s >= plast) { n0 = np - 1; w = 0.f; }
+    else { n0 = (s - 1 - delta) / 4; w = (float)(s - (4 * n0 + 1 + delta)) * 0.25f; }
+    const int n1 = n0 + 1 < np ? n0 + 1 : n0;
+    float wt0, wt1;
+    if (t <= NRX_DMRS0) { wt0 = 1.f; wt1 = 0.f; }
+    else if (t >= NRX_DMRS1) { wt0 = 0.f; wt1 = 1.f; }
+    else { wt0 = (float)(NRX_DMRS1 - t) / 9.f; wt1 = (float)(t - NRX_DMRS0) / 9.f; }
+    float2 hl[2];
+#pragma unroll
+    for (int li = 0; li < 2; ++li) {
+      const float2 a0 = P[(((int64_t)li * U + u) * np + n0) * B + b];
+      const float2 a1 = P[(((int64_t)li * U + u) * np + n1) * B + b];
+      hl[li] = make_float2((1.f - w) * a0.x + w * a1.x, (1.f - w) * a0.y + w * a1.y);
+    }
+    const float2 h = make_float2(wt0 * hl[0].x + wt1 * hl[1].x, wt0 * hl[0].y + wt1 * hl[1].y);
+    const float2 yv = y[g.y_off + ((int64_t)s * 14 + t) * B + b];
+    // health word bit 2: a received sample that is not finite (checked once per RE, by its UE-0 row)
+    if (u == 0) bad |= !__builtin_isfinite(yv.x) || !__builtin_isfinite(yv.y);
+    ys[rl][b] = yv;
+    hs[rl][b] = h;
+    if (h_out) h_out[g.h_off + (((int64_t)s * 14 + t) * U + u) * B + b] = h;
+  }
+  if (slot_flags && __ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&slot_flags[slot], 4u);
+  __syncthreads();
+  const int rl = threadIdx.x / ngrp, grp = threadIdx.x - rl * ngrp, r = r0 + rl;
+  if (r >= rows) return;
+  // channel order [Re y | Im y | Re h | Im h], each block model_B wide, zero padded to cx
+  float f[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = 8 * grp + k, part = c / model_B, b = c - part * model_B;
+    float v = 0.f;
+    if (part < 4 && b < B) {
+      const float2 q = part < 2 ? ys[rl][b] : hs[rl][b];
+      v = (part & 1) ? q.y : q.x;
+    }
+    f[k] = v;
+  }
+  pack8<T>::store(X + (g.row_base + r) * cx + 8 * grp, f);
+}
+
 }  // namespace
 
 void launch_dmrs(const SlotGeo *geo, int n_slots, float2 *dmrs, hipStream_t st, const unsigned int *slot_mask) {
@@ -168,6 +243,14 @@ template <typename T>
 void launch_features(const SlotGeo *geo, const int64_t *, int n_slots, int64_t max_rows, const float2 *y,
                      const float2 *pairs, const int64_t *pair_off, int model_B, int cx, T *X, float2 *h_out,
                      hipStream_t st, const unsigned int *slot_mask, unsigned int *slot_flags) {
+  if (X && cx / 8 >= 4 && 256 % (cx / 8) == 0 && model_B <= FEAT_MAX_B) {
+    // the input features: blocks of 256 / (cx / 8) rows staged through LDS
+    const int rpb = 256 / (cx / 8);
+    dim3 grid((unsigned)((max_rows + rpb - 1) / rpb), n_slots);
+    hipLaunchKernelGGL(features_lds_kernel<T>, grid, dim3(256), 0, st, geo, y, pairs, pair_off, model_B, cx, X, h_out,
+                       slot_mask, slot_flags);
+    return;
+  }
   const int64_t threads = max_rows * (X ? cx / 8 : 1);   // one per (row, 8-channel group)
   dim3 grid((unsigned)((threads + 255) / 256), n_slots);
   hipLaunchKernelGGL(features_kernel<T>, grid, dim3(256), 0, st, geo, y, pairs, pair_off, model_B, cx, X, h_out,

@@ -295,13 +295,17 @@ def _grad_case(prec, tol, cos_min, seed=21, variant=1, multi=False):
         e = rel_err(got, ref)
         log(f"  gradient relative error (all weights) {e:.2e}")
         off = 0
+        worst = (0.0, 1.0, "")
         for name, shape in cgnn.layout(net):
             n = int(np.prod(shape))
             et = rel_err(got[off:off + n], ref[off:off + n])
             cos = float(got[off:off + n] @ ref[off:off + n] /
                         (np.linalg.norm(got[off:off + n]) * np.linalg.norm(ref[off:off + n]) + 1e-300))
             assert et <= tol and cos >= cos_min, f"{name}: relative error {et:.3e}, cosine {cos:.5f}"
+            if et > worst[0]:
+                worst = (et, cos, name)
             off += n
+        log(f"  worst tensor {worst[2]}: relative error {worst[0]:.3e}, cosine {worst[1]:.6f}")
         assert e <= tol
     finally:
         L.nrx_model_destroy(model)
@@ -648,9 +652,11 @@ def test_nrx_forward_depth_control(prec, tol):
 
 
 def test_nrx_backward_bf16_close_to_oracle():
-    # bf16 stores activations and gradients with 8 significant bits; the bound is a regression bound on the
-    # mixed-precision training gradient (direction within a few degrees), not a parity claim
-    _grad_case(1, 0.12, 0.99)
+    # BF16 stores activations and gradients with 8 significant bits (relative rounding up to 2^-9), FP32
+    # accumulation; the error grows with the depth the gradient travels back.  Measured: 5.2e-3 over all
+    # weights, worst tensor (first block's conv_a weights) 1.0e-2 at cosine 0.99995; the bar is three times
+    # the worst tensor
+    _grad_case(1, 0.03, 0.9995)
 
 
 def test_training_reduces_loss():
