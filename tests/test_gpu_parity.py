@@ -786,8 +786,8 @@ def test_trained_nrx_beats_lmmse():
 def test_trained_c5_network_against_lmmse():
     """The committed C5 network (6 blocks, 2 message-passing rounds, 4 UEs x 8 antennas, Sec. II-B training) against
     LS + LMMSE with genie N0 at 10 dB on held-out C5 slots.  It does not beat the classical receiver yet (its BER
-    is about 1.17 times LS + LMMSE after 400k training steps, still falling with training): the bar holds it to
-    within 25 % of it, so that a regression of the weights or of the forward pass shows."""
+    is 1.11 times LS + LMMSE on these slots after 700k training steps, still falling with training): the bar
+    holds it within 20 % of it, so that a regression of the weights or of the forward pass shows."""
     import os
     from paper_2409_02912_amd.train import evaluate
     w = np.load(os.path.join(os.path.dirname(L.LIB_PATH), "weights", "nrx_c5.npy"), allow_pickle=False)
@@ -795,7 +795,7 @@ def test_trained_c5_network_against_lmmse():
     r = evaluate(w, synth.WORKLOADS["c5"], seed=99, batches=2, snr_db=10.0)
     b1, b2, n = r["ber_nrx"], r["ber_lmmse"], r["n_bits"]
     log(f"  BER nrx {b1:.4f}  lmmse {b2:.4f}  ratio {b1 / b2:.3f}  bits {n}")
-    assert b1 < 1.25 * b2
+    assert b1 < 1.2 * b2
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 2e-2)])
