@@ -37,8 +37,10 @@ struct WgStage<bf16_t> {
   uint32_t x[4][4], d[4][4];
 };
 
+// (the FP32 form's staged rows, twice the BF16 bytes, take most of a CU's LDS: one workgroup per CU, so
+// it asks for one wave per SIMD; the BF16 form for two)
 template <typename T>
-__global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 2 ? 2 : 1) void wgrad_kernel(WgradArgs<T> a) {
   __shared__ __align__(16) T xt[2][128 * TP];
   __shared__ __align__(16) T dt[2][128 * TP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
