@@ -231,7 +231,8 @@ def evaluate(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=Non
 def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, batch=None, n_prb=None, var_io=False):
     """Held-out channel-estimation MSE (mean |ĥ - h|^2 over the batch's complex entries) of the ReadoutChEst output
     after the last CGNN iteration, next to that of the LS estimate with linear interpolation the network starts from
-    (Sec. II-A), on fresh slots at one SNR."""
+    (Sec. II-A), on fresh slots at one SNR; and the BER of LMMSE equalisation + max-log demapping (genie N0) given
+    either estimate, i.e. what the refined estimate is worth to a classical receiver."""
     import torch
     dev = "cuda"
     m_max = w["m"]
@@ -254,9 +255,16 @@ def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, bat
         sws = torch.empty(L.slot_sim_workspace_bytes(sim, descs), dtype=torch.uint8, device=dev)
         mws = torch.empty(L.nrx_mse_workspace_bytes(descs), dtype=torch.uint8, device=dev)
         loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        bits = torch.empty(sz["bits"], dtype=torch.uint8, device=dev)
+        n0 = torch.empty(len(shapes), dtype=torch.float32, device=dev)
+        llm = torch.empty(sz["llr"], dtype=torch.float32, device=dev)
+        lws = torch.empty(L.lmmse_workspace_bytes(descs), dtype=torch.uint8, device=dev)
+        bws = torch.empty(L.nrx_bce_workspace_bytes(descs, m_max), dtype=torch.uint8, device=dev)
+        nerr = torch.zeros(1, dtype=torch.int64, device=dev)
         m_nrx = m_ls = 0.0
+        e_ls = e_ref = n_bits = 0
         for b in range(batches):
-            L.slot_sim(sim, seed, b, descs, m_max, y, sws, h_true=h_true)
+            L.slot_sim(sim, seed, b, descs, m_max, y, sws, h_true=h_true, bits=bits, n0=n0)
             L.nrx_forward_chest(model, params, descs, y, llr, hest, ws, h_ls=h_ls)
             L.nrx_mse(descs, hest, h_true, 1.0, None, loss, mws)
             torch.cuda.synchronize()
@@ -264,7 +272,17 @@ def evaluate_chest(w_params, w, seed, batches, snr_db, precision=L.NRX_BF16, bat
             L.nrx_mse(descs, h_ls, h_true, 1.0, None, loss, mws)
             torch.cuda.synchronize()
             m_ls += loss.item()
-        return {"mse_nrx": m_nrx / batches, "mse_ls": m_ls / batches}
+            for h, acc in ((h_ls, "ls"), (hest, "ref")):
+                L.lmmse_demap(descs, m_max, y, llm, lws, h=h, n0=n0)
+                L.nrx_bce(descs, m_max, llm, bits, None, loss, nerr, bws)
+                torch.cuda.synchronize()
+                if acc == "ls":
+                    e_ls += nerr.item()
+                else:
+                    e_ref += nerr.item()
+            n_bits += sum(12 * 12 * s["n_prb"] * sum(s["bits"]) for s in shapes)
+        return {"mse_nrx": m_nrx / batches, "mse_ls": m_ls / batches,
+                "ber_lmmse_ls": e_ls / n_bits, "ber_lmmse_refined": e_ref / n_bits}
     finally:
         L.nrx_model_destroy(model)
 

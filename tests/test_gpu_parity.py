@@ -705,7 +705,9 @@ def test_multi_loss_training_gives_usable_shallow_readout():
 def test_double_readout_training_refines_channel_estimate():
     """Double-readout training (Sec. II-A, II-B): with the gamma-scaled MSE against the true channel, ReadoutChEst
     learns a channel estimate more accurate than the LS estimate with interpolation the network starts from
-    (held-out MSE at 10 dB after 2500 steps from scratch, gamma = 1: measured 0.024 against 0.035)."""
+    (held-out MSE at 10 dB after 2500 steps from scratch, gamma = 1: measured 0.024 against 0.035).  The refined
+    estimate is also worth bits to a classical receiver: LMMSE equalisation + max-log demapping given ReadoutChEst's
+    estimate makes fewer errors than given the LS estimate (same slots, genie N0)."""
     from paper_2409_02912_amd.train import Trainer, evaluate_chest
     w = synth.WORKLOADS["t"]
     log("training: workload t, double readout (gamma 1), 2500 steps")
@@ -718,7 +720,9 @@ def test_double_readout_training_refines_channel_estimate():
     finally:
         tr.close()
     log(f"  held-out channel MSE: ReadoutChEst {r['mse_nrx']:.4f}, LS {r['mse_ls']:.4f}")
+    log(f"  LMMSE BER given ReadoutChEst {r['ber_lmmse_refined']:.4f}, given LS {r['ber_lmmse_ls']:.4f}")
     assert r["mse_nrx"] < 0.85 * r["mse_ls"]
+    assert r["ber_lmmse_refined"] < r["ber_lmmse_ls"]
 
 
 @pytest.mark.parametrize("var_io", [False, True])
