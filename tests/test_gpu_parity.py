@@ -707,7 +707,8 @@ def test_double_readout_training_refines_channel_estimate():
     learns a channel estimate more accurate than the LS estimate with interpolation the network starts from
     (held-out MSE at 10 dB after 2500 steps from scratch, gamma = 1: measured 0.024 against 0.035).  The refined
     estimate is also worth bits to a classical receiver: LMMSE equalisation + max-log demapping given ReadoutChEst's
-    estimate makes fewer errors than given the LS estimate (same slots, genie N0)."""
+    estimate makes fewer errors than given the LS estimate (same slots, genie N0; measured BER 0.033 against
+    0.041)."""
     from paper_2409_02912_amd.train import Trainer, evaluate_chest
     w = synth.WORKLOADS["t"]
     log("training: workload t, double readout (gamma 1), 2500 steps")
@@ -790,7 +791,7 @@ def test_trained_nrx_beats_lmmse():
 def test_trained_c5_network_against_lmmse():
     """The committed C5 network (6 blocks, 2 message-passing rounds, 4 UEs x 8 antennas, Sec. II-B training) against
     LS + LMMSE with genie N0 at 10 dB on held-out C5 slots.  It does not beat the classical receiver yet (its BER
-    is 1.11 times LS + LMMSE on these slots after 700k training steps, still falling with training): the bar
+    is 1.09 times LS + LMMSE on these slots after 825k training steps, still falling with training): the bar
     holds it within 20 % of it, so that a regression of the weights or of the forward pass shows."""
     import os
     from paper_2409_02912_amd.train import evaluate
