@@ -531,7 +531,6 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
     return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
   if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
-  if ((c.flags & 4) && c.precision == NRX_FP8) return fail(NRX_ERR_UNSUPPORTED, "Var-IO needs FP32 or BF16");
   if ((c.flags & 8) && (c.precision != NRX_BF16 || (c.flags & 4)))
     return fail(NRX_ERR_UNSUPPORTED, "the persistent forward (flags bit 3) runs BF16 models with shared input and output layers");
   if (c.flags & ~15) return fail(NRX_ERR_INVALID, "unknown model flags 0x%x", c.flags);

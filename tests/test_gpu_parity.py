@@ -990,6 +990,48 @@ def test_nrx_forward_fp8(variant):
         L.nrx_model_destroy(model)
 
 
+def test_nrx_forward_fp8_var_io():
+    """FP8 Var-IO model (Sec. III, Fig. 2, with the E4M3 block convs): each modulation's StateInit (BF16) writes
+    the E4M3 copy of its own UEs' rows only, the block convs read that copy, each modulation's readout reads its
+    UEs; slots of one modulation beside mixed ones, eager and replayed as a hipGraph.  LLRs against the FP64
+    oracle to the FP8 bars."""
+    shp = VARIO_SLOT_SHAPES
+    net = cgnn.NetConfig(4, 128, 3, 1, 8, var_io=True)
+    ref_slots = oracle_batch(shp, sim_cfg_oracle(SIMCFG), 62, 0, 8)
+    w = synth.he_weights(cgnn.layout(net), 62, perturb=True)
+    exp = oracle_nrx(w, net, ref_slots)
+    descs, sz = L.make_slots(shp, 8)
+    y = _upload_batch(shp, ref_slots)
+    wd = dev(w)
+    for flags in (4, 4 | 1):
+        log(f"FP8 Var-IO forward: flags {flags}")
+        model = L.nrx_model_create(net.B, net.d, net.C, net.R, 8, L.NRX_FP8, flags=flags)
+        try:
+            llr = torch.zeros(sz["llr"], dtype=torch.float32, device="cuda")
+            ws = ws_tensor(L.nrx_workspace_bytes(model, descs))
+            L.nrx_calibrate(model, wd, descs, y, llr, ws)
+            for rep in range(2 if flags & 1 else 1):
+                llr.fill_(float("nan"))
+                L.nrx_forward(model, wd, descs, y, llr, ws)
+                torch.cuda.synchronize()
+                got = llr.cpu().numpy().astype(np.float64)
+                assert np.all(np.isfinite(got)), "LLR entries left unwritten"
+                got = split_llr(got, shp, 8)
+                worst, agree_n, agree_d = 0.0, 0, 0
+                for i in range(len(shp)):
+                    for u in range(shp[i]["n_ue"]):
+                        worst = max(worst, rel_err(got[i][u], exp[i][u]))
+                        big = np.abs(exp[i][u]) > 2.0
+                        agree_n += int(np.sum((got[i][u][big] > 0) == (exp[i][u][big] > 0)))
+                        agree_d += int(np.sum(big))
+                log(f"  pass {rep}: worst relative error {worst:.3e}, decision agreement "
+                    f"{agree_n / max(agree_d, 1):.5f} over {agree_d}")
+                assert worst <= FP8_TOL
+                assert agree_n >= FP8_AGREE * agree_d
+        finally:
+            L.nrx_model_destroy(model)
+
+
 def test_full_size_sampled_parity():
     """The benchmark workload at full size and in the benchmark's launch configuration (32 slots x
     273 PRB x 14 symbols, 4 UEs, 8 antennas, 16-QAM; d = 128, 6 blocks, 2 rounds; autotuned conv
