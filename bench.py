@@ -655,11 +655,11 @@ def main():
     if pol:
         out["fp8_policies"] = pol
         ok = [k for k in pol if pol[k]["ber_matched"]]
-        if "fp8" in out and ok:   # the fastest E4M3 policy whose BER matches the FP32 pass
-            best = max(ok, key=lambda k: pol[k]["slots_per_s"])
-            out["fp8"]["matched_ber_policy"] = {"fp8_layers": pol[best]["fp8_layers"],
-                                                "slots_per_s": pol[best]["slots_per_s"],
-                                                "speedup_vs_bf16": pol[best]["speedup_vs_bf16"]}
+        if "fp8" in out:   # the fastest E4M3 policy whose BER matches the FP32 pass (null: none does)
+            best = max(ok, key=lambda k: pol[k]["slots_per_s"]) if ok else None
+            out["fp8"]["matched_ber_policy"] = None if best is None else {
+                "fp8_layers": pol[best]["fp8_layers"], "slots_per_s": pol[best]["slots_per_s"],
+                "speedup_vs_bf16": pol[best]["speedup_vs_bf16"]}
     if "bf16_persistent" in results:
         msp = results["bf16_persistent"]["ms_per_step"]
         out["bf16_persistent"] = {"slots_per_s": n_slots / (msp * 1e-3), "ms_per_step": msp,
