@@ -403,7 +403,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the NRX batch is data-parallel over slots with no exchange, "
-              "and multi-GPU runs are not part of this build.", file=sys.stderr)
+              "and the benchmark has no multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -8,7 +8,7 @@ counter words, two 32-bit key words, ten rounds; each round multiplies words 0
 and 2 by fixed odd constants, mixes the high halves with words 1/3 and the key,
 and the key is bumped by the Weyl constants between rounds.  The paper itself
 draws its random quantities (payload bits, channels, noise, SNR; training
-section and Eq. (1)) without naming a generator; this one is the build's choice,
+section and Eq. (1)) without naming a generator; this one is the project's choice,
 implemented independently on the GPU side.
 """
 import numpy as np

@@ -529,7 +529,7 @@ extern "C" nrx_status nrx_model_create(const nrx_model_config *cfg, nrx_model **
   if (c.n_rounds < 0 || c.n_rounds > c.n_blocks) return fail(NRX_ERR_SHAPE, "n_rounds %d outside 0..n_blocks", c.n_rounds);
   if (c.m_max != 2 && c.m_max != 4 && c.m_max != 6 && c.m_max != 8) return fail(NRX_ERR_SHAPE, "m_max %d", c.m_max);
   if (c.precision != NRX_FP32 && c.precision != NRX_BF16 && c.precision != NRX_FP8)
-    return fail(NRX_ERR_UNSUPPORTED, "precision %d not available in this build", c.precision);
+    return fail(NRX_ERR_UNSUPPORTED, "precision %d not available", c.precision);
   if (c.precision == NRX_FP8 && c.d != NRX_D) return fail(NRX_ERR_UNSUPPORTED, "FP8 models need d = 128");
   if ((c.flags & 8) && (c.precision != NRX_BF16 || (c.flags & 4)))
     return fail(NRX_ERR_UNSUPPORTED, "the persistent forward (flags bit 3) runs BF16 models with shared input and output layers");
@@ -1253,7 +1253,7 @@ nrx_status forward_entry(nrx_model *m, const float *w, const nrx_slot_desc *slot
   Plan *P = PR.get();
   if (s != NRX_OK) return s;
   if (m->fp8 && save_acts) return fail(NRX_ERR_UNSUPPORTED, "FP8 models are inference-only (train in BF16)");
-  if (m->cfg.d != NRX_D && save_acts) return fail(NRX_ERR_UNSUPPORTED, "training needs d = 128 in this build");
+  if (m->cfg.d != NRX_D && save_acts) return fail(NRX_ERR_UNSUPPORTED, "training needs d = 128");
   const FwdLayout L = fwd_layout(m, P, save_acts != 0);
   if (ws_bytes < L.total) return fail(NRX_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, L.total);
   const int iters = m->n_iter > 0 ? m->n_iter : (int)iteration_ends(m->cfg).size();

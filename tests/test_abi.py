@@ -198,7 +198,7 @@ def test_fp8_model_host_checks():
 
 
 def test_dmrs_symbol_mask_only_type_a_with_one_additional_position():
-    # the descriptor names the DMRS symbols; this build implements symbols 2 and 11 (Sec. III-B) and
+    # the descriptor names the DMRS symbols; the library implements symbols 2 and 11 (Sec. III-B) and
     # rejects any other pattern explicitly rather than silently using 2 and 11
     model = L.nrx_model_create(4, 128, 2, 0, 2)
     try:
