@@ -401,3 +401,78 @@ def test_var_io():
     fd = (f({k: W[k] + eps * v[k] for k in W}) - f({k: W[k] - eps * v[k] for k in W})) / (2 * eps)
     an = sum(np.sum(G[k] * v[k]) for k in W)
     assert abs(fd - an) <= 1e-6 * abs(fd)
+
+
+def test_conv_backward_is_the_adjoint():
+    """The 3x3 conv is bilinear in (x, w): for any output cotangent g, <conv(x, w), g> = <x, dx> = <w, dw>, and
+    db sums g over the grid.  Exact identities (fp64 rounding only); a transposed kernel, a flipped tap or a
+    shifted window in the backward breaks them."""
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((6, 5, 2, 3))          # [S, T, U, C]: the UE axis rides along like the conv's
+    w = rng.standard_normal((3, 3, 3, 4))
+    g = rng.standard_normal((6, 5, 2, 4))
+    y = cgnn.conv3x3(x, w, np.zeros(4))
+    dx, dw, db = cgnn.conv3x3_backward(x, w, g)
+    ref = float(np.sum(y * g))
+    assert abs(float(np.sum(x * dx)) - ref) < 1e-10 * abs(ref) + 1e-10
+    assert abs(float(np.sum(w * dw)) - ref) < 1e-10 * abs(ref) + 1e-10
+    assert np.allclose(db, g.reshape(-1, 4).sum(axis=0), rtol=0, atol=1e-12)
+    # per-element: dx[s, t] collects w[i, j] applied to g[s - i + 1, t - j + 1] (direct sum)
+    S, T = 6, 5
+    want = np.zeros_like(x)
+    for s in range(S):
+        for t in range(T):
+            for i in range(3):
+                for j in range(3):
+                    so, to = s - i + 1, t - j + 1
+                    if 0 <= so < S and 0 <= to < T:
+                        want[s, t] += g[so, to] @ w[i, j].T
+    assert np.allclose(dx, want, rtol=0, atol=1e-12)
+
+
+def test_layer_norm_backward_against_central_differences():
+    """LayerNorm backward: central differences of <LN(z), r> in z, gamma and beta, and the exact properties of
+    the input gradient: zero mean over the normalised axis, and (gamma = 1) a component along the normalised
+    input of rstd <r, zhat> (1 - mean zhat^2), which the epsilon inside the square root leaves nonzero."""
+    rng = np.random.default_rng(12)
+    z = rng.standard_normal((3, 8)) * 2.0 + 0.5
+    gam = 1.0 + 0.3 * rng.standard_normal(8)
+    bet = 0.2 * rng.standard_normal(8)
+    r = rng.standard_normal((3, 8))
+    f = lambda zz, gg, bb: float(np.sum(cgnn.layer_norm(zz, gg, bb)[0] * r))
+    _, cache = cgnn.layer_norm(z, gam, bet)
+    dz, dg, db = cgnn.layer_norm_backward(r, gam, cache)
+    eps = 1e-6
+    for arr, grad, name in ((z, dz, "z"), (gam, dg, "gamma"), (bet, db, "beta")):
+        fd = np.zeros_like(arr)
+        for idx in np.ndindex(arr.shape):
+            p, m = arr.copy(), arr.copy()
+            p[idx] += eps
+            m[idx] -= eps
+            args = {"z": (z, gam, bet), "gamma": (z, gam, bet), "beta": (z, gam, bet)}[name]
+            ap = [p if a is arr else a for a in args]
+            am = [m if a is arr else a for a in args]
+            fd[idx] = (f(*ap) - f(*am)) / (2 * eps)
+        assert np.allclose(grad, fd, rtol=1e-6, atol=1e-8), name
+    assert np.allclose(dz.sum(axis=-1), 0.0, atol=1e-12)
+    _, c1 = cgnn.layer_norm(z, np.ones(8), np.zeros(8))
+    dz1, _, _ = cgnn.layer_norm_backward(r, np.ones(8), c1)
+    zh, rs = c1
+    want = rs[:, 0] * np.sum(r * zh, axis=-1) * (1.0 - np.mean(zh ** 2, axis=-1))
+    assert np.allclose(np.sum(dz1 * zh, axis=-1), want, rtol=1e-9, atol=1e-14)
+    assert np.all(np.abs(want) < 1e-4)   # orthogonal up to the epsilon term
+
+
+def test_softplus_and_sigmoid():
+    """softplus(x) - softplus(-x) = x, softplus(0) = ln 2, sigmoid(x) + sigmoid(-x) = 1, sigmoid is the
+    derivative of softplus, and both stay finite far out (the BCE of a confident LLR)."""
+    x = np.linspace(-30.0, 30.0, 601)
+    assert np.allclose(cgnn.softplus(x) - cgnn.softplus(-x), x, rtol=0, atol=1e-12)
+    assert cgnn.softplus(np.array(0.0)) == pytest.approx(np.log(2.0), abs=1e-15)
+    assert np.allclose(cgnn.sigmoid(x) + cgnn.sigmoid(-x), 1.0, rtol=0, atol=1e-15)
+    h = 1e-5
+    assert np.allclose((cgnn.softplus(x + h) - cgnn.softplus(x - h)) / (2 * h), cgnn.sigmoid(x), rtol=0, atol=1e-9)
+    big = np.array([-1000.0, 1000.0])
+    assert np.array_equal(cgnn.softplus(big), np.array([0.0, 1000.0]))
+    assert np.array_equal(cgnn.sigmoid(big), np.array([0.0, 1.0]))
+    assert cgnn.relu(np.array(-2.0)) == 0.0 and cgnn.relu(np.array(3.0)) == 3.0

@@ -82,6 +82,31 @@ def test_lmmse_noiseless_recovers_symbols():
     assert np.allclose(z[:, dsym], x[:, dsym], atol=1e-10)
 
 
+def test_lmmse_demap_layout_and_noiseless_decisions():
+    """LMMSE + max-log demapping into the LLR layout [u][t][s][j], given the channel: on a noiseless slot with
+    the true channel and a tiny N0, every data-RE LLR decides its transmitted bit (l > 0 decides 1), DMRS
+    symbols and the outputs j >= m_u are zero, for UEs of different modulations."""
+    rng = np.random.default_rng(21)
+    desc = slot_sim.SlotDesc(2, 4, 3, [2, 6, 8])
+    H = rng.standard_normal((desc.n_sc, 14, 3, 4)) + 1j * rng.standard_normal((desc.n_sc, 14, 3, 4))
+    y, _, bits = _grid_from_h(H, desc)
+    llr = receiver.lmmse_demap(y, H, 1e-9, desc, 8)
+    S = desc.n_sc
+    assert llr.shape == (3, 14, S, 8)
+    dsym = nr.data_symbols()
+    for t in range(14):
+        if t not in dsym:
+            assert np.all(llr[:, t] == 0.0)
+    for u, m in enumerate(desc.bits_per_sym):
+        assert np.all(llr[u, :, :, m:] == 0.0)
+        for t in dsym:
+            for s_ in range(S):
+                got = (llr[u, t, s_, :m] > 0).astype(np.uint8)
+                assert np.array_equal(got, bits[u, nr.data_re_index(s_, t, S), :m])
+        # reliable decisions: every data LLR far from zero at this N0
+        assert np.min(np.abs(llr[u][np.ix_(dsym, range(S), range(m))])) > 1e3
+
+
 def test_lmmse_single_user_is_mrc():
     rng = np.random.default_rng(3)
     h = rng.standard_normal((50, 1, 4)) + 1j * rng.standard_normal((50, 1, 4))
